@@ -1,0 +1,209 @@
+"""Benchmark: weighted-sum-rendering forward + backward on one MI355X.
+
+One step = one pass of the whole path over one synthetic frame: projection
+(+ SH colour/opacity + depth weights), binning, raster forward, raster
+backward and projection backward, for 1,000,000 Gaussians (32-blob mixture,
+SH degree 3 with view-dependent opacity, linear-correction weights) seen by
+one 1920x1080 camera.  Inputs are resident in HBM before timing starts.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--tile 16]
+                    [--storage f32|f16|bf16] [--no-cpu-baseline]
+
+Prints one JSON line.  Per-kernel durations come from HIP events recorded on
+the stream the kernels run on.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd frames/s and Gaussian-pixel evals/s at 1M splats 1080p; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# algorithmic FP32 work per in-support (pixel, Gaussian) pair
+FWD_FLOPS_PER_PAIR = 20
+BWD_FLOPS_PER_PAIR = 48
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--config", default="headline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=24, help="image rows the CPU baseline renders")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(n: int, pixels: int, storage: str, nv: int = 1) -> dict:
+    """HBM bytes the method must move per step (SH degree 3 RGBA, LC weights).
+    Attributes: means 3, log-scales 3, quaternion 4, SH 16x4 values + v_i."""
+    vals = 3 + 3 + 4 + 64
+    attr = n * (vals * (4 if storage == "f32" else 2) + 4)
+    grads = n * (vals + 1) * 4
+    return {
+        "project": attr + n * nv * 56,                       # attributes in, 2D record + rect out
+        "raster_fwd": pixels * 16,                           # colour + denominator out
+        "raster_bwd": pixels * 28,                           # dL/dC, C, D in
+        "project_bwd": attr + n * nv * 36 + grads,           # attributes + 2D grads in, grads out
+        "step": 2 * attr + grads + pixels * 44,
+    }
+
+
+def cpu_baseline(scene, cams, settings, rows: int) -> dict:
+    """The FP64 reference checker as it stands, on a bounded sample: `rows`
+    image rows in 6 evenly spaced strips, forward + backward, extrapolated to
+    a full frame by the pixel ratio."""
+    import oracle
+    cam = cams[0]
+    H, W = int(cam["height"]), int(cam["width"])
+    nstrips = 6
+    h = max(1, rows // nstrips)
+    ys = np.linspace(0, H - h, nstrips).astype(int)
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    for y in ys:
+        crop = (0, int(y), W, int(y) + h)
+        oracle.render(scene, cam, settings, crop=crop)
+        oracle.render_bwd(scene, cam, settings, rng.standard_normal((h, W, 3)), crop=crop)
+    dt = time.perf_counter() - t0
+    frac = nstrips * h / H
+    return {"value": frac / dt, "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 C checker (strict all-pairs mode), forward+backward on {nstrips} full-width strips of "
+                      f"{h} rows ({nstrips * h} of {H} rows) of the same frame, {dt:.1f} s; frames/s = "
+                      f"sampled fraction / time"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the weighted-sum path here is a single-GPU build "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import wsr_synth as ws
+    from paper_2410_18931_amd import WSRContext, _lib, globals_tensor, scene_to_device
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    scene, cams, st = ws.make_scene(args.config)
+    st = st.copy(tile=args.tile)
+    n = scene["means"].shape[1]
+    dev = scene_to_device(scene, storage=args.storage)
+    g = globals_tensor(st)
+    ctx = WSRContext(n, cams, st)
+    P = ctx.total_pixels
+    rgb = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+    den = torch.empty((P,), dtype=torch.float32, device="cuda")
+    dL = torch.randn((P, 3), generator=torch.Generator(device="cuda").manual_seed(0), device="cuda")
+    grads = ctx.alloc_grads(dev)
+    sc = ctx.scene_struct(dev)
+    gs = _lib.WsrGrads(*(grads[k].data_ptr() for k in ("means", "log_scales", "quats", "sh", "opacity_logit",
+                                                       "lc_v", "globals")))
+    lib = ctx.lib
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+    ptr = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+    wsp = ptr(ctx.ws)
+
+    # size the id list once (untimed), and count the in-support pairs
+    ctx.project(dev, g)
+    ctx.bin(grow=True)
+    _, _, cnt = ctx.render_fwd(g, count=True)
+    pairs = int(cnt.sum().item())
+    binned = ctx.last_pairs
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        _lib.check("wsr_project", lib.wsr_project(C.byref(sc), ctx.cams_c, ctx.nv, C.byref(ctx.params), ptr(g),
+                                                  wsp, ctx.ws_bytes, None, sp))
+        if ev:
+            ev[1].record(stream)
+        _lib.check("wsr_bin", lib.wsr_bin(ctx.cams_c, ctx.nv, C.byref(ctx.params), n, wsp, ctx.ws_bytes,
+                                          ptr(ctx.ids), ctx.capacity, sp))
+        if ev:
+            ev[2].record(stream)
+        _lib.check("wsr_render_fwd", lib.wsr_render_fwd(ctx.cams_c, ctx.nv, C.byref(ctx.params), n, ptr(g), wsp,
+                                                        ctx.ws_bytes, ptr(ctx.ids), ctx.capacity, ptr(rgb),
+                                                        ptr(den), None, sp))
+        if ev:
+            ev[3].record(stream)
+        _lib.check("wsr_raster_bwd", lib.wsr_raster_bwd(ctx.cams_c, ctx.nv, C.byref(ctx.params), n, ptr(g), wsp,
+                                                        ctx.ws_bytes, ptr(ctx.ids), ctx.capacity, ptr(dL),
+                                                        ptr(rgb), ptr(den), sp))
+        if ev:
+            ev[4].record(stream)
+        _lib.check("wsr_project_bwd", lib.wsr_project_bwd(C.byref(sc), ctx.cams_c, ctx.nv, C.byref(ctx.params),
+                                                          ptr(g), wsp, ctx.ws_bytes, C.byref(gs), None, sp))
+        if ev:
+            ev[5].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.check()
+    print(f"# warmup done: {n} Gaussians, {P} px, {binned} binned pairs, {pairs} in-support pairs", file=sys.stderr,
+          flush=True)
+
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check()  # the id list did not overflow during timing
+
+    names = ["project", "bin", "raster_fwd", "raster_bwd", "project_bwd"]
+    stage_ms = {nm: float(np.mean([ev[j].elapsed_time(ev[j + 1]) for ev in events])) for j, nm in enumerate(names)}
+    ms = (t1 - t0) * 1e3 / args.steps
+    fps = 1e3 / ms
+    ab = algorithmic_bytes(n, P, args.storage)
+    dominant = max(("raster_fwd", "raster_bwd"), key=lambda s: stage_ms[s])
+    flops = pairs * (FWD_FLOPS_PER_PAIR if dominant == "raster_fwd" else BWD_FLOPS_PER_PAIR)
+    achieved = flops / (stage_ms[dominant] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(fps, 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.storage == "f32" else f"{args.storage}-storage/f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {n:,} Gaussians (32-blob mixture, SH degree 3 RGBA with "
+                               f"view-dependent opacity, LC weights), one {cams[0]['width']}x{cams[0]['height']} "
+                               f"view, tile {args.tile}, {args.storage} attribute storage",
+                   "gaussians": n, "width": cams[0]["width"], "height": cams[0]["height"], "tile": args.tile,
+                   "storage": args.storage},
+        "gaussian_pixel_evals_per_s": pairs / (ms * 1e-3),
+        "in_support_pairs": pairs, "binned_tile_pairs": binned,
+        "hbm_frac_step": ab["step"] / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "roofline": {"kernel": f"{dominant} (raster_{'fwd' if dominant == 'raster_fwd' else 'bwd'}_kernel)",
+                     "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "flops_per_pair": FWD_FLOPS_PER_PAIR if dominant == "raster_fwd" else BWD_FLOPS_PER_PAIR,
+                     "launch_ms": round(stage_ms[dominant], 4)},
+        "stage_hbm_gbs": {k: round(ab[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in names},
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(scene, cams, st, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

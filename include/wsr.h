@@ -1,0 +1,197 @@
+/*
+ * wsr.h — C-ABI of the sort-free Weighted Sum Rendering (WSR) rasterizer for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library renders 3D Gaussian scenes with the weighted sum of Sec. 4.2,
+ * Eq. 7 of "Sort-free Gaussian Splatting via Weighted Sum Rendering":
+ *
+ *     C = (c_B w_B + sum_i c_i a_i) / (w_B + sum_i a_i),
+ *     a_i = u_i w(d_i) exp(-q_i / 2)   for q_i <= tau, else 0,
+ *
+ * where q_i is the Mahalanobis form of pixel centre and projected Gaussian
+ * (Sec. 3, Eqs. 3 and 5), c_i the SH colour (Eq. 4), u_i the maximum opacity
+ * (sigmoid of a logit, Sec. 3; or the unclamped SH opacity of Sec. 4.3,
+ * Eq. 11) and w the depth weight (Eqs. 8-10: DIR, EXP, LC).  No depth sort
+ * happens anywhere: per-tile lists carry Gaussian ids only (Sec. 4.1).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named *_dev, and every scene/gradient/image/workspace pointer,
+ *    are DEVICE pointers owned by the caller.  Camera and parameter structs
+ *    are HOST memory, read during the call only.
+ *  - All work is enqueued on `stream` (a hipStream_t passed as void*; NULL
+ *    means the default stream) and is asynchronous; no entry point
+ *    allocates or frees device memory.  Only wsr_pair_count and wsr_check
+ *    synchronise the stream.
+ *  - Inputs are never modified.  Outputs are fully overwritten.
+ *  - Host-detectable errors (null pointers, SH degree > 3, unsupported tile,
+ *    workspace too small, more than WSR_MAX_VIEWS views) return an error
+ *    status before anything is enqueued.  A per-tile list overflow is
+ *    detected on the device: wsr_bin then records a flag in the workspace
+ *    (read by wsr_check) and every later stage reads only in-bounds entries,
+ *    so the images are incomplete but memory stays safe.
+ *  - NaN / Inf inputs are not checked; they propagate.
+ *  - Calls on one workspace must not overlap; different workspaces are
+ *    independent.
+ *
+ * Multi-view images are concatenated: view v's image starts at pixel
+ * sum_{v'<v} width_v' * height_v'; colours are [H][W][3] float32 and the
+ * denominator [H][W] float32 per view.
+ */
+#ifndef WSR_H_
+#define WSR_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WSR_ABI_VERSION 1
+#define WSR_MAX_VIEWS 256
+
+typedef enum {
+    WSR_OK = 0,
+    WSR_ERR_INVALID = 1,     /* bad argument; nothing enqueued */
+    WSR_ERR_WORKSPACE = 2,   /* workspace smaller than wsr_workspace_bytes */
+    WSR_ERR_CAPACITY = 3,    /* per-tile list overflow (device flag) */
+    WSR_ERR_HIP = 4          /* a HIP runtime call failed */
+} wsr_status;
+
+/* Depth weight w(d) of Sec. 4.2: Eq. 8 (DIR, w = 1), Eq. 9 (EXP,
+ * w = exp(-sigma d^beta)), Eq. 10 (LC, w = max(0, 1 - d/sigma) v_i). */
+typedef enum { WSR_WEIGHT_DIR = 0, WSR_WEIGHT_EXP = 1, WSR_WEIGHT_LC = 2 } wsr_weight_kind;
+
+/* Maximum opacity: sigmoid(logit) in [0, 1] (Sec. 3), or the view-dependent
+ * SH opacity u = SH_alpha(dir) + opacity_offset, unclamped (Sec. 4.3, Eq. 11). */
+typedef enum { WSR_OPACITY_LOGIT = 0, WSR_OPACITY_SH = 1 } wsr_opacity_mode;
+
+/* Storage type of means, log_scales, quats and sh.  Arithmetic is FP32 or
+ * wider whatever the storage. */
+typedef enum { WSR_STORE_F32 = 0, WSR_STORE_F16 = 1, WSR_STORE_BF16 = 2 } wsr_storage;
+
+/* The scene model of Sec. 3 in planar structure-of-arrays layout.
+ * K = (sh_degree + 1)^2.  Element type of the four `void` arrays is given
+ * by `storage`; opacity_logit and lc_v are float32. */
+typedef struct {
+    int64_t n;                 /* number of Gaussians, >= 0 */
+    int32_t sh_degree;         /* 0..3 */
+    int32_t storage;           /* wsr_storage */
+    int32_t opacity_mode;      /* wsr_opacity_mode */
+    int32_t reserved_;
+    const void* means;         /* [3][n]  centre p */
+    const void* log_scales;    /* [3][n]  s = exp(log_scales) */
+    const void* quats;         /* [4][n]  (w, x, y, z); normalised on load */
+    const void* sh;            /* [K][n][4] RGBA per coefficient; A = opacity SH */
+    const float* opacity_logit;/* [n]  used iff opacity_mode == LOGIT */
+    const float* lc_v;         /* [n]  used iff weight kind == LC */
+} wsr_scene;
+
+/* Pinhole camera: world -> camera [R | T] row-major (+z forward, +y down),
+ * focal lengths and principal point in pixels.  Pixel (px, py) is sampled at
+ * (px + 0.5, py + 0.5). */
+typedef struct {
+    float viewmat[12];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} wsr_camera;
+
+/* Renderer settings.  tau is the support cutoff on q (a pair contributes iff
+ * q <= tau); dilation is added to the diagonal of Sigma2D (px^2); near culls
+ * Gaussians with camera-space z <= near; tile is 8, 16 or 32. */
+typedef struct {
+    int32_t weight_kind;       /* wsr_weight_kind */
+    int32_t tile;              /* 8 | 16 | 32 */
+    float tau;                 /* 9 = 3-sigma ellipse */
+    float dilation;            /* 0.3 */
+    float near_z;              /* 0.2 */
+    float opacity_offset;      /* 0.5; SH opacity mode only */
+} wsr_params;
+
+/* Learnable global parameters, a DEVICE array of 6 floats:
+ * [0] sigma, [1] beta (EXP only), [2] w_B, [3..5] c_B (RGB). */
+#define WSR_GLOBALS 6
+
+/* Gradient outputs (DEVICE, float32, same planar layouts as wsr_scene). */
+typedef struct {
+    float* means;              /* [3][n] */
+    float* log_scales;         /* [3][n] */
+    float* quats;              /* [4][n] */
+    float* sh;                 /* [K][n][4]; A column zero in LOGIT mode */
+    float* opacity_logit;      /* [n]; may be NULL in SH mode */
+    float* lc_v;               /* [n]; may be NULL unless LC */
+    float* globals;            /* [6], see WSR_GLOBALS */
+} wsr_grads;
+
+int32_t wsr_abi_version(void);
+const char* wsr_status_string(int32_t status);
+
+/* Bytes of the workspace needed for n Gaussians over the given views and
+ * tile size (does not include the per-tile id list, see wsr_bin).
+ * Returns -1 on invalid arguments. */
+int64_t wsr_workspace_bytes(int64_t n, const wsr_camera* cams, int32_t n_views, int32_t tile);
+
+/* Steps a1-a5 for every (view, Gaussian) pair (Sec. 3 Eqs. 3-5; Eq. 4;
+ * Eqs. 8-11): view transform and near-plane cull, EWA projection with
+ * dilation, conic, SH colour, opacity, depth weight, and the tile
+ * rectangle of each splat's support ellipse.  Writes the workspace.
+ * out_proj (nullable, DEVICE [n_views][n][16] float32) receives, per pair:
+ * visible, mu_x, mu_y, conic A, B, C, r, g, b, u, w, depth, and four zeros. */
+int32_t wsr_project(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views,
+                    const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
+                    float* out_proj, void* stream);
+
+/* Step a6 (Sec. 4.1): build per-tile lists of Gaussian ids for every view,
+ * with no depth key (Eq. 7 is a commutative sum, so order is irrelevant).
+ * ids is a DEVICE uint32 array of `capacity` entries.  If the number of
+ * (tile, Gaussian) pairs exceeds capacity the overflow flag is set. */
+int32_t wsr_bin(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
+                void* ws, int64_t ws_bytes, uint32_t* ids, int64_t capacity, void* stream);
+
+/* Step a7 (Eq. 7): per-pixel FP32 sums and normalisation with the weighted
+ * background.  out_rgb: concatenated [H][W][3]; out_den: concatenated
+ * [H][W] (w_B + sum a_i); out_count (nullable, int32 [H][W]): the number of
+ * in-support pairs per pixel. */
+int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
+                       const float* globals, const void* ws, int64_t ws_bytes, const uint32_t* ids,
+                       int64_t capacity, float* out_rgb, float* out_den, int32_t* out_count,
+                       void* stream);
+
+/* Steps a8-a9: gradient of a loss L given dL/dC (concatenated [H][W][3]),
+ * the forward's colour and denominator.  Recomputes every pair's amplitude
+ * (nothing per pair is stored by the forward) and writes every field of
+ * grads (they are overwritten, not accumulated).  out_grad2d (nullable,
+ * DEVICE [n_views][n][9]) receives the per-(view, Gaussian) gradient with
+ * respect to (mu_x, mu_y, A, B, C, r, g, b, a) where (A, B, C) is the conic
+ * (q = A dx^2 + 2B dx dy + C dy^2) and a = u w the amplitude. */
+int32_t wsr_render_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views,
+                       const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
+                       const uint32_t* ids, int64_t capacity, const float* dL_drgb, const float* rgb,
+                       const float* den, const wsr_grads* grads, float* out_grad2d, void* stream);
+
+/* The two halves of wsr_render_bwd, for callers that schedule or time them
+ * separately; wsr_render_bwd is exactly wsr_raster_bwd then wsr_project_bwd.
+ * wsr_raster_bwd (step a8, Eq. 7 differentiated) leaves the per-(view,
+ * Gaussian) 2D gradients and per-tile background partial sums in the
+ * workspace; wsr_project_bwd (step a9) chains them to the scene parameters
+ * (Eqs. 3-11 differentiated) and writes `grads`. */
+int32_t wsr_raster_bwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
+                       const float* globals, void* ws, int64_t ws_bytes, const uint32_t* ids,
+                       int64_t capacity, const float* dL_drgb, const float* rgb, const float* den,
+                       void* stream);
+int32_t wsr_project_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views,
+                        const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
+                        const wsr_grads* grads, float* out_grad2d, void* stream);
+
+/* Synchronises `stream` and returns, in *out_total, the number of
+ * (tile, Gaussian) pairs the last wsr_bin on this workspace produced (the
+ * size the id list needs). */
+int32_t wsr_pair_count(const void* ws, int64_t ws_bytes, int64_t* out_total, void* stream);
+
+/* Synchronises `stream`; returns WSR_ERR_CAPACITY if the last wsr_bin on
+ * this workspace overflowed its id list, else WSR_OK. */
+int32_t wsr_check(const void* ws, int64_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WSR_H_ */

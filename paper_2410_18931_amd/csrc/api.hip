@@ -1,0 +1,228 @@
+// C-ABI entry points of the WSR library (declared in include/wsr.h): argument
+// checks, workspace layout, and the launch sequence of each step.
+#include <cmath>
+#include <cstring>
+
+#include "wsr_internal.h"
+
+namespace wsr {
+
+int64_t project_bwd_blocks(int64_t n);
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+bool valid_tile(int32_t t) { return t == 8 || t == 16 || t == 32; }
+
+int32_t to_status(hipError_t e) { return e == hipSuccess ? WSR_OK : WSR_ERR_HIP; }
+
+}  // namespace
+
+bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, Layout* L, DevCamera* dc) {
+  if (n < 0 || n > 0xffffffffLL || !cams || nv < 1 || nv > WSR_MAX_VIEWS || !valid_tile(tile)) return false;
+  *L = Layout();
+  L->n = n;
+  L->nv = nv;
+  L->tile = tile;
+  L->nblk = static_cast<int32_t>(n > 0 ? (n + kBinChunk - 1) / kBinChunk : 1);
+  int64_t tiles = 0, pixels = 0, hist = 0;
+  for (int v = 0; v < nv; ++v) {
+    const wsr_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > 32767 || c.height > 32767) return false;
+    if (!(c.fx > 0.f) || !(c.fy > 0.f)) return false;
+    const int tx = (c.width + tile - 1) / tile, ty = (c.height + tile - 1) / tile;
+    if (tx > L->max_tiles_x) L->max_tiles_x = tx;
+    if (ty > L->max_tiles_y) L->max_tiles_y = ty;
+    if (dc) {
+      DevCamera& d = dc[v];
+      std::memset(&d, 0, sizeof(d));
+      for (int k = 0; k < 3; ++k) {
+        for (int j = 0; j < 3; ++j) d.R[3 * k + j] = c.viewmat[4 * k + j];
+        d.T[k] = c.viewmat[4 * k + 3];
+      }
+      d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+      d.width = c.width; d.height = c.height;
+      d.tiles_x = tx; d.tiles_y = ty;
+      d.tile_base = static_cast<int32_t>(tiles);
+      d.pix_base = pixels;
+      d.hist_base = hist;
+    }
+    tiles += static_cast<int64_t>(tx) * ty;
+    pixels += static_cast<int64_t>(c.width) * c.height;
+    hist += static_cast<int64_t>(tx) * ty * L->nblk;
+  }
+  if (tiles > 0x7fffffffLL) return false;
+  L->total_tiles = tiles;
+  L->total_pixels = pixels;
+  L->hist_len = hist;
+  L->scan_parts = (hist + 1 + kScanItems - 1) / kScanItems;
+  L->gpart_blocks = project_bwd_blocks(n);
+  const int64_t slots = n * nv;
+  size_t off = 0;
+  L->off_cams = off;     off = align256(off + sizeof(DevCamera) * WSR_MAX_VIEWS);
+  L->off_flags = off;    off = align256(off + sizeof(DevFlags));
+  L->off_rec = off;      off = align256(off + sizeof(SplatRec) * slots);
+  L->off_rect = off;     off = align256(off + sizeof(uint2) * slots);
+  L->off_hist = off;     off = align256(off + sizeof(uint32_t) * (hist + 1));
+  L->off_scan = off;     off = align256(off + sizeof(uint32_t) * L->scan_parts);
+  L->off_grad2d = off;   off = align256(off + sizeof(float) * 9 * slots);
+  L->off_tilepart = off; off = align256(off + sizeof(float) * 4 * tiles);
+  L->off_gpart = off;    off = align256(off + sizeof(double) * 2 * L->gpart_blocks);
+  L->bytes = off;
+  return true;
+}
+
+}  // namespace wsr
+
+using namespace wsr;
+
+namespace {
+
+bool scene_ok(const wsr_scene* s, int32_t weight_kind) {
+  if (!s || s->n < 0 || s->sh_degree < 0 || s->sh_degree > 3) return false;
+  if (s->storage < WSR_STORE_F32 || s->storage > WSR_STORE_BF16) return false;
+  if (s->opacity_mode != WSR_OPACITY_LOGIT && s->opacity_mode != WSR_OPACITY_SH) return false;
+  if (s->n == 0) return true;
+  if (!s->means || !s->log_scales || !s->quats || !s->sh) return false;
+  if (s->opacity_mode == WSR_OPACITY_LOGIT && !s->opacity_logit) return false;
+  if (weight_kind == WSR_WEIGHT_LC && !s->lc_v) return false;
+  return true;
+}
+
+bool params_ok(const wsr_params* p) {
+  return p && p->weight_kind >= WSR_WEIGHT_DIR && p->weight_kind <= WSR_WEIGHT_LC &&
+         (p->tile == 8 || p->tile == 16 || p->tile == 32) && std::isfinite(p->tau) && p->tau >= 0.f &&
+         std::isfinite(p->dilation) && std::isfinite(p->near_z);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t wsr_abi_version(void) { return WSR_ABI_VERSION; }
+
+const char* wsr_status_string(int32_t status) {
+  switch (status) {
+    case WSR_OK: return "ok";
+    case WSR_ERR_INVALID: return "invalid argument";
+    case WSR_ERR_WORKSPACE: return "workspace too small";
+    case WSR_ERR_CAPACITY: return "per-tile id list overflow";
+    case WSR_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int64_t wsr_workspace_bytes(int64_t n, const wsr_camera* cams, int32_t n_views, int32_t tile) {
+  Layout L;
+  if (!make_layout(n, cams, n_views, tile, &L, nullptr)) return -1;
+  return static_cast<int64_t>(L.bytes);
+}
+
+int32_t wsr_project(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views, const wsr_params* params,
+                    const float* globals, void* ws, int64_t ws_bytes, float* out_proj, void* stream) {
+  if (!params_ok(params) || !scene_ok(scene, params->weight_kind) || !globals || !ws) return WSR_ERR_INVALID;
+  Layout L;
+  DevCamera dc[WSR_MAX_VIEWS];
+  if (!make_layout(scene->n, cams, n_views, params->tile, &L, dc)) return WSR_ERR_INVALID;
+  if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_upload_cameras(dc, n_views, ws, L, st);
+  if (e == hipSuccess) e = launch_project(scene, params, globals, L, ws, out_proj, st);
+  return to_status(e);
+}
+
+int32_t wsr_bin(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n, void* ws,
+                int64_t ws_bytes, uint32_t* ids, int64_t capacity, void* stream) {
+  if (!params_ok(params) || !ws || capacity < 0 || (capacity > 0 && !ids)) return WSR_ERR_INVALID;
+  Layout L;
+  if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
+  if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
+  return to_status(launch_bin(L, ws, ids, capacity, static_cast<hipStream_t>(stream)));
+}
+
+int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
+                       const float* globals, const void* ws, int64_t ws_bytes, const uint32_t* ids,
+                       int64_t capacity, float* out_rgb, float* out_den, int32_t* out_count, void* stream) {
+  if (!params_ok(params) || !globals || !ws || !out_rgb || !out_den || capacity < 0 || (capacity > 0 && !ids))
+    return WSR_ERR_INVALID;
+  Layout L;
+  if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
+  if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
+  return to_status(launch_raster_fwd(L, ws, ids, capacity, params, globals, out_rgb, out_den, out_count,
+                                     static_cast<hipStream_t>(stream)));
+}
+
+int32_t wsr_raster_bwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
+                       const float* globals, void* ws, int64_t ws_bytes, const uint32_t* ids, int64_t capacity,
+                       const float* dL_drgb, const float* rgb, const float* den, void* stream) {
+  if (!params_ok(params) || !globals || !ws || !dL_drgb || !rgb || !den || capacity < 0 || (capacity > 0 && !ids))
+    return WSR_ERR_INVALID;
+  Layout L;
+  if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
+  if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_fill_zero(at<float>(ws, L.off_grad2d), sizeof(float) * 9 * L.n * L.nv, st);
+  if (e == hipSuccess) e = launch_raster_bwd(L, ws, ids, capacity, params, globals, dL_drgb, rgb, den, st);
+  return to_status(e);
+}
+
+int32_t wsr_project_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views, const wsr_params* params,
+                        const float* globals, void* ws, int64_t ws_bytes, const wsr_grads* grads, float* out_grad2d,
+                        void* stream) {
+  if (!params_ok(params) || !scene_ok(scene, params->weight_kind) || !globals || !ws || !grads || !grads->globals)
+    return WSR_ERR_INVALID;
+  if (scene->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->sh)) return WSR_ERR_INVALID;
+  Layout L;
+  if (!make_layout(scene->n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
+  if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
+  return to_status(launch_project_bwd(scene, params, globals, L, ws, grads, out_grad2d, static_cast<hipStream_t>(stream)));
+}
+
+int32_t wsr_render_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views, const wsr_params* params,
+                       const float* globals, void* ws, int64_t ws_bytes, const uint32_t* ids, int64_t capacity,
+                       const float* dL_drgb, const float* rgb, const float* den, const wsr_grads* grads,
+                       float* out_grad2d, void* stream) {
+  if (!params_ok(params) || !scene_ok(scene, params->weight_kind) || !grads || !grads->globals)
+    return WSR_ERR_INVALID;
+  if (scene->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->sh)) return WSR_ERR_INVALID;
+  const int32_t s = wsr_raster_bwd(cams, n_views, params, scene->n, globals, ws, ws_bytes, ids, capacity, dL_drgb,
+                                   rgb, den, stream);
+  if (s != WSR_OK) return s;
+  return wsr_project_bwd(scene, cams, n_views, params, globals, ws, ws_bytes, grads, out_grad2d, stream);
+}
+
+int32_t wsr_pair_count(const void* ws, int64_t ws_bytes, int64_t* out_total, void* stream) {
+  if (!ws || !out_total || ws_bytes < static_cast<int64_t>(sizeof(DevCamera) * WSR_MAX_VIEWS + sizeof(DevFlags)))
+    return WSR_ERR_INVALID;
+  Layout L;  // flags sit at a fixed offset after the camera table
+  wsr_camera probe = {};
+  probe.width = probe.height = 1;
+  probe.fx = probe.fy = 1.f;
+  make_layout(0, &probe, 1, 16, &L, nullptr);
+  DevFlags f;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&f, at<DevFlags>(ws, L.off_flags), sizeof(f), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return WSR_ERR_HIP;
+  *out_total = static_cast<int64_t>(f.total_pairs);
+  return WSR_OK;
+}
+
+int32_t wsr_check(const void* ws, int64_t ws_bytes, void* stream) {
+  if (!ws || ws_bytes < static_cast<int64_t>(sizeof(DevCamera) * WSR_MAX_VIEWS + sizeof(DevFlags)))
+    return WSR_ERR_INVALID;
+  Layout L;
+  wsr_camera probe = {};
+  probe.width = probe.height = 1;
+  probe.fx = probe.fy = 1.f;
+  make_layout(0, &probe, 1, 16, &L, nullptr);
+  DevFlags f;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&f, at<DevFlags>(ws, L.off_flags), sizeof(f), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return WSR_ERR_HIP;
+  return f.overflow ? WSR_ERR_CAPACITY : WSR_OK;
+}
+
+}  // extern "C"

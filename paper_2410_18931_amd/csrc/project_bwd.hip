@@ -1,0 +1,371 @@
+// Step a9 of the WSR path: chain the per-(view, Gaussian) 2D gradients
+// (dL/d mu, conic, colour, amplitude) back to the scene parameters of Sec. 3
+// (centre, log-scale, quaternion, SH), the opacity (logit, or the SH opacity
+// of Sec. 4.3, Eq. 11), the depth-weight parameters (Eqs. 9, 10) and the
+// background weight and colour of Eq. 7.
+//
+// One thread per Gaussian, looping over the views, so no atomics are needed
+// and every gradient is written once with coalesced planar stores.  The
+// gradient of Sigma3D is summed over views first and chained to (q, s) once.
+// The global parameters are reduced in double precision from per-block
+// partials (deterministic, no float atomics).
+#include "geom.h"
+#include "sh_basis.h"
+#include "wsr_internal.h"
+
+namespace wsr {
+namespace {
+
+constexpr int kBwdBlock = 128;
+
+struct BwdArgs {
+  const void* means;
+  const void* log_scales;
+  const void* quats;
+  const void* sh;
+  const float* logit;
+  const float* lc_v;
+  const float* globals;
+  const DevCamera* cams;
+  const float* grad2d;
+  wsr_grads g;
+  double* gpart;      // [blocks][2] = sigma, beta
+  int64_t n;
+  int32_t nv;
+  int32_t opa_mode;
+  int32_t weight_kind;
+  float near_z, dilation, opacity_offset;
+};
+
+template <int S, int DEG>
+__global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ double s_red[kBwdBlock / kWave][2];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBwdBlock + threadIdx.x;
+  const int64_t n = a.n;
+  double gsig = 0.0, gbeta = 0.0;
+  if (i < n) {
+    const double p0 = load_attr<S>(a.means, i);
+    const double p1 = load_attr<S>(a.means, n + i);
+    const double p2 = load_attr<S>(a.means, 2 * n + i);
+    const float rq[4] = {load_attr<S>(a.quats, i), load_attr<S>(a.quats, n + i),
+                         load_attr<S>(a.quats, 2 * n + i), load_attr<S>(a.quats, 3 * n + i)};
+    QuatScale qs;
+    const Sigma3 S3 = make_sigma3(rq[0], rq[1], rq[2], rq[3], load_attr<S>(a.log_scales, i),
+                                  load_attr<S>(a.log_scales, n + i), load_attr<S>(a.log_scales, 2 * n + i), &qs);
+    float4 coef[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) coef[k] = load_attr4<S>(a.sh, k * n + i);
+    const float logit = a.opa_mode == WSR_OPACITY_LOGIT ? a.logit[i] : 0.f;
+    const float lcv = a.weight_kind == WSR_WEIGHT_LC ? a.lc_v[i] : 0.f;
+    const double sigma = a.globals[0], beta = a.globals[1];
+
+    double dp[3] = {0.0, 0.0, 0.0};
+    double dS[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // symmetric dL/dSigma3D (xx, xy, xz, yy, yz, zz)
+    float4 dsh[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) dsh[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float dlogit = 0.f, dv = 0.f;
+
+    for (int v = 0; v < a.nv; ++v) {
+      const float* g2 = a.grad2d + (static_cast<int64_t>(v) * n + i) * 9;
+      float gv[9];
+      bool nz = false;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        gv[j] = g2[j];
+        nz |= gv[j] != 0.f;
+      }
+      if (!nz) continue;
+      const DevCamera& cam = a.cams[v];
+      ViewGeom g;
+      if (!view_geom(cam, p0, p1, p2, S3, qs.ok, a.near_z, a.dilation, &g)) continue;
+      double dt[3] = {0.0, 0.0, 0.0};
+
+      // --- colour, opacity and weight (a4, a5) ---
+      double dir[3], len;
+      view_dir(g, cam, p0, p1, p2, dir, &len);
+      const float fx3 = static_cast<float>(dir[0]), fy3 = static_cast<float>(dir[1]), fz3 = static_cast<float>(dir[2]);
+      float Y[K];
+      sh_eval<DEG>(fx3, fy3, fz3, Y);
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        acc.x = fmaf(coef[k].x, Y[k], acc.x);
+        acc.y = fmaf(coef[k].y, Y[k], acc.y);
+        acc.z = fmaf(coef[k].z, Y[k], acc.z);
+        acc.w = fmaf(coef[k].w, Y[k], acc.w);
+      }
+      const float u = a.opa_mode == WSR_OPACITY_SH ? acc.w + a.opacity_offset : 1.f / (1.f + expf(-logit));
+      const double d = g.tz;
+      double w = 1.0, dw_dd = 0.0;
+      if (a.weight_kind == WSR_WEIGHT_EXP) {
+        const double db = pow(d, beta);
+        w = exp(-sigma * db);
+        dw_dd = -sigma * beta * db / d * w;
+      } else if (a.weight_kind == WSR_WEIGHT_LC) {
+        const double lin = 1.0 - d / sigma;
+        w = lin > 0.0 ? lin * lcv : 0.0;
+        dw_dd = lin > 0.0 ? -lcv / sigma : 0.0;
+      }
+      const double gamp = gv[8];
+      const double du = gamp * w, dw = gamp * u;
+      if (a.weight_kind == WSR_WEIGHT_EXP) {
+        const double db = pow(d, beta);
+        gsig += dw * (-db * w);
+        gbeta += dw * (-sigma * db * log(d) * w);
+      } else if (a.weight_kind == WSR_WEIGHT_LC) {
+        const double lin = 1.0 - d / sigma;
+        if (lin > 0.0) {
+          dv += static_cast<float>(dw * lin);
+          gsig += dw * lcv * d / (sigma * sigma);
+        }
+      }
+      dt[2] += dw * dw_dd;
+      // gradient at the raw (pre-activation) SH sums, RGBA
+      float4 graw;
+      graw.x = acc.x + 0.5f > 0.f ? gv[5] : 0.f;
+      graw.y = acc.y + 0.5f > 0.f ? gv[6] : 0.f;
+      graw.z = acc.z + 0.5f > 0.f ? gv[7] : 0.f;
+      graw.w = 0.f;
+      if (a.opa_mode == WSR_OPACITY_SH) graw.w = static_cast<float>(du);
+      else dlogit += static_cast<float>(du) * u * (1.f - u);
+      float3 gY[K];
+      sh_eval_grad<DEG>(fx3, fy3, fz3, gY);
+      float3 ddir = make_float3(0.f, 0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        dsh[k].x = fmaf(graw.x, Y[k], dsh[k].x);
+        dsh[k].y = fmaf(graw.y, Y[k], dsh[k].y);
+        dsh[k].z = fmaf(graw.z, Y[k], dsh[k].z);
+        dsh[k].w = fmaf(graw.w, Y[k], dsh[k].w);
+        const float c = coef[k].x * graw.x + coef[k].y * graw.y + coef[k].z * graw.z + coef[k].w * graw.w;
+        ddir.x = fmaf(c, gY[k].x, ddir.x);
+        ddir.y = fmaf(c, gY[k].y, ddir.y);
+        ddir.z = fmaf(c, gY[k].z, ddir.z);
+      }
+      {
+        const double dd3[3] = {ddir.x, ddir.y, ddir.z};
+        const double radial = dd3[0] * dir[0] + dd3[1] * dir[1] + dd3[2] * dir[2];
+        for (int c = 0; c < 3; ++c) dp[c] += (dd3[c] - radial * dir[c]) / len;
+      }
+
+      // --- projected centre ---
+      const double gmx = gv[0], gmy = gv[1];
+      const double fx = cam.fx, fy = cam.fy, iz = g.izt;
+      dt[0] += gmx * fx * iz;
+      dt[1] += gmy * fy * iz;
+      dt[2] -= (gmx * fx * g.tx + gmy * fy * g.ty) * iz * iz;
+
+      // --- conic -> Sigma2D: dL/dSigma = -Q G Q with G the symmetric
+      // gradient of the conic matrix Q = [[A, B], [B, C]] ---
+      const double gA = gv[2], gBh = 0.5 * gv[3], gC = gv[4];
+      const double P00 = gA * g.A + gBh * g.B, P01 = gA * g.B + gBh * g.C;
+      const double P10 = gBh * g.A + gC * g.B, P11 = gBh * g.B + gC * g.C;
+      const double GS00 = -(g.A * P00 + g.B * P10);
+      const double GS11 = -(g.B * P01 + g.C * P11);
+      const double GS01 = -0.5 * ((g.A * P01 + g.B * P11) + (g.B * P00 + g.C * P10));
+
+      // --- Sigma2D = Tm S Tm^T + dilation, Tm rows a, b ---
+      double Sa[3], Sb[3];
+      sym_mul(S3, g.a, Sa);
+      sym_mul(S3, g.b, Sb);
+      // dL/dS += Tm^T G Tm
+      const double* A3 = g.a;
+      const double* B3 = g.b;
+      dS[0] += GS00 * A3[0] * A3[0] + 2.0 * GS01 * A3[0] * B3[0] + GS11 * B3[0] * B3[0];
+      dS[1] += GS00 * A3[0] * A3[1] + GS01 * (A3[0] * B3[1] + B3[0] * A3[1]) + GS11 * B3[0] * B3[1];
+      dS[2] += GS00 * A3[0] * A3[2] + GS01 * (A3[0] * B3[2] + B3[0] * A3[2]) + GS11 * B3[0] * B3[2];
+      dS[3] += GS00 * A3[1] * A3[1] + 2.0 * GS01 * A3[1] * B3[1] + GS11 * B3[1] * B3[1];
+      dS[4] += GS00 * A3[1] * A3[2] + GS01 * (A3[1] * B3[2] + B3[1] * A3[2]) + GS11 * B3[1] * B3[2];
+      dS[5] += GS00 * A3[2] * A3[2] + 2.0 * GS01 * A3[2] * B3[2] + GS11 * B3[2] * B3[2];
+      // dL/dTm = 2 G Tm S
+      double ga[3], gb[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        ga[j] = 2.0 * (GS00 * Sa[j] + GS01 * Sb[j]);
+        gb[j] = 2.0 * (GS01 * Sa[j] + GS11 * Sb[j]);
+      }
+      // a_j = fx/tz (W0j - rx W2j), b_j = fy/tz (W1j - ry W2j), rx = tx/tz unless clamped
+      const double* W = g.W;
+      const double ex = g.unclamped_x ? 1.0 : 0.0, ey = g.unclamped_y ? 1.0 : 0.0;
+      const double kx = fx * iz * iz, ky = fy * iz * iz;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        dt[2] -= ga[j] * kx * (W[j] - (1.0 + ex) * g.rx * W[6 + j]);
+        dt[2] -= gb[j] * ky * (W[3 + j] - (1.0 + ey) * g.ry * W[6 + j]);
+        dt[0] -= ex * ga[j] * kx * W[6 + j];
+        dt[1] -= ey * gb[j] * ky * W[6 + j];
+      }
+      // t = W p + T
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dp[c] += W[c] * dt[0] + W[3 + c] * dt[1] + W[6 + c] * dt[2];
+    }
+
+    // --- Sigma3D = M M^T, M = R diag(s): dL/dM = 2 G M ---
+    const double* R = qs.R;
+    const double s[3] = {qs.s0, qs.s1, qs.s2};
+    const double G[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+    double gR[9], gs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double gM = 2.0 * (G[3 * r] * R[j] * s[j] + G[3 * r + 1] * R[3 + j] * s[j] + G[3 * r + 2] * R[6 + j] * s[j]);
+        gR[3 * r + j] = gM * s[j];
+        gs[j] += gM * R[3 * r + j];
+      }
+    // R = (w^2 - |v|^2) I + 2 v v^T + 2 w [v]x for the unit quaternion (w, v)
+    const double w = qs.w, x = qs.x, y = qs.y, z = qs.z;
+    const double tr = gR[0] + gR[4] + gR[8];
+    const double kxs = gR[7] - gR[5], kys = gR[2] - gR[6], kzs = gR[3] - gR[1];
+    double gq[4];
+    gq[0] = 2.0 * w * tr + 2.0 * (x * kxs + y * kys + z * kzs);
+    const double vv[3] = {x, y, z};
+    const double ks[3] = {kxs, kys, kzs};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double Gv = gR[3 * c] * x + gR[3 * c + 1] * y + gR[3 * c + 2] * z;   // (G v)_c
+      const double GTv = gR[c] * x + gR[3 + c] * y + gR[6 + c] * z;              // (G^T v)_c
+      gq[1 + c] = -2.0 * vv[c] * tr + 2.0 * (Gv + GTv) + 2.0 * w * ks[c];
+    }
+    // through q / |q|
+    const double qn = sqrt(static_cast<double>(rq[0]) * rq[0] + static_cast<double>(rq[1]) * rq[1] +
+                           static_cast<double>(rq[2]) * rq[2] + static_cast<double>(rq[3]) * rq[3]);
+    const double qh[4] = {w, x, y, z};
+    const double proj = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
+
+    const bool ok = qs.ok;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.g.means[c * n + i] = static_cast<float>(dp[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.g.log_scales[c * n + i] = ok ? static_cast<float>(gs[c] * s[c]) : 0.f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a.g.quats[c * n + i] = ok ? static_cast<float>((gq[c] - qh[c] * proj) / qn) : 0.f;
+    float4* gsh = reinterpret_cast<float4*>(a.g.sh);
+#pragma unroll
+    for (int k = 0; k < K; ++k) gsh[k * n + i] = dsh[k];
+    if (a.g.opacity_logit) a.g.opacity_logit[i] = dlogit;
+    if (a.g.lc_v) a.g.lc_v[i] = dv;
+  }
+  // block partials of dL/dsigma, dL/dbeta
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    gsig += __shfl_xor(gsig, d, kWave);
+    gbeta += __shfl_xor(gbeta, d, kWave);
+  }
+  if (lane == 0) {
+    s_red[wv][0] = gsig;
+    s_red[wv][1] = gbeta;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBwdBlock / kWave; ++k) t += s_red[k][threadIdx.x];
+    a.gpart[static_cast<int64_t>(blockIdx.x) * 2 + threadIdx.x] = t;
+  }
+}
+
+// Final reduction of the global parameters: dL/dsigma, dL/dbeta from the
+// per-block partials, dL/dw_B and dL/dc_B from the per-tile partials.
+__global__ __launch_bounds__(256) void reduce_globals(const double* gpart, int64_t nblocks,
+                                                      const float* tilepart, int64_t ntiles, float* out) {
+  __shared__ double sh[256][6];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nblocks; b += 256) {
+    acc[0] += gpart[2 * b];
+    acc[1] += gpart[2 * b + 1];
+  }
+  for (int64_t t = threadIdx.x; t < ntiles; t += 256) {
+    acc[3] += tilepart[4 * t];
+    acc[4] += tilepart[4 * t + 1];
+    acc[5] += tilepart[4 * t + 2];
+    acc[2] += tilepart[4 * t + 3];
+  }
+  for (int k = 0; k < 6; ++k) sh[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int step = 128; step >= 1; step >>= 1) {
+    if (threadIdx.x < step)
+      for (int k = 0; k < 6; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + step][k];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) out[threadIdx.x] = static_cast<float>(sh[0][threadIdx.x]);
+}
+
+__global__ void fill_zero_kernel(uint32_t* p, int64_t words) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += stride) p[k] = 0u;
+}
+
+template <int S>
+hipError_t bwd_s(const BwdArgs& a, int deg, unsigned blocks, hipStream_t st) {
+  switch (deg) {
+    case 0: project_bwd_kernel<S, 0><<<blocks, kBwdBlock, 0, st>>>(a); break;
+    case 1: project_bwd_kernel<S, 1><<<blocks, kBwdBlock, 0, st>>>(a); break;
+    case 2: project_bwd_kernel<S, 2><<<blocks, kBwdBlock, 0, st>>>(a); break;
+    default: project_bwd_kernel<S, 3><<<blocks, kBwdBlock, 0, st>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t project_bwd_blocks(int64_t n) { return n > 0 ? (n + kBwdBlock - 1) / kBwdBlock : 1; }
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+  const int64_t words = static_cast<int64_t>(bytes / 4);
+  if (words == 0) return hipSuccess;
+  int64_t blocks = (words + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  fill_zero_kernel<<<static_cast<unsigned>(blocks), 256, 0, st>>>(static_cast<uint32_t*>(p), words);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const float* globals,
+                              const Layout& L, void* ws, const wsr_grads* g, float* out_grad2d,
+                              hipStream_t st) {
+  double* gpart = at<double>(ws, L.off_gpart);
+  const unsigned blocks = static_cast<unsigned>(project_bwd_blocks(L.n));
+  hipError_t e = hipSuccess;
+  if (L.n > 0) {
+    BwdArgs a;
+    a.means = sc->means;
+    a.log_scales = sc->log_scales;
+    a.quats = sc->quats;
+    a.sh = sc->sh;
+    a.logit = sc->opacity_logit;
+    a.lc_v = sc->lc_v;
+    a.globals = globals;
+    a.cams = at<DevCamera>(ws, L.off_cams);
+    a.grad2d = at<float>(ws, L.off_grad2d);
+    a.g = *g;
+    a.gpart = gpart;
+    a.n = L.n;
+    a.nv = L.nv;
+    a.opa_mode = sc->opacity_mode;
+    a.weight_kind = P->weight_kind;
+    a.near_z = P->near_z;
+    a.dilation = P->dilation;
+    a.opacity_offset = P->opacity_offset;
+    switch (sc->storage) {
+      case WSR_STORE_F16: e = bwd_s<WSR_STORE_F16>(a, sc->sh_degree, blocks, st); break;
+      case WSR_STORE_BF16: e = bwd_s<WSR_STORE_BF16>(a, sc->sh_degree, blocks, st); break;
+      default: e = bwd_s<WSR_STORE_F32>(a, sc->sh_degree, blocks, st); break;
+    }
+  } else {
+    e = launch_fill_zero(gpart, 2 * sizeof(double), st);
+  }
+  if (e != hipSuccess) return e;
+  if (out_grad2d && L.n > 0) {
+    e = hipMemcpyAsync(out_grad2d, at<float>(ws, L.off_grad2d), sizeof(float) * 9 * L.n * L.nv,
+                       hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  reduce_globals<<<1, 256, 0, st>>>(gpart, static_cast<int64_t>(blocks), at<float>(ws, L.off_tilepart),
+                                    L.total_tiles, g->globals);
+  return hipGetLastError();
+}
+
+}  // namespace wsr

@@ -1,0 +1,402 @@
+// Steps a7 and a8 of the WSR path: the per-pixel weighted sums of Sec. 4.2,
+// Eq. 7, and their gradient.
+//
+//   forward:  N = c_B w_B + sum_i c_i a_i,  D = w_B + sum_i a_i,  C = N / D
+//             a_i = amp_i exp(-q_i / 2) for q_i <= tau   (amp_i = u_i w(d_i))
+//   backward: per pixel gbar = dL/dC / D and s = gbar . C; per pair
+//             dL/da = gbar . c_i - s, then the chain to (mu, conic, c, amp).
+//
+// One workgroup per (view, tile).  Each wave owns a square block of the tile
+// (8x8 pixels for tiles 8 and 16, 16x16 for tile 32).  Per batch the group
+// stages splat records into LDS; each wave then keeps only the splats whose
+// support box meets its own block (wave ballot + compaction into an LDS
+// list), and every lane evaluates its pixel(s) against that list with FP32
+// register accumulation.  The sums are commutative, so the list order does
+// not matter, and no per-pair data is stored between forward and backward:
+// the backward recomputes every pair.
+#include "wsr_internal.h"
+
+namespace wsr {
+namespace {
+
+template <int T>
+struct TileGeom {
+  static constexpr int kThreads = T == 8 ? 64 : 256;
+  static constexpr int kWaves = kThreads / kWave;
+  static constexpr int kSub = T == 32 ? 16 : 8;        // wave block edge
+  static constexpr int kPpl = (kSub / 8) * (kSub / 8); // pixels per lane
+  static constexpr int kBatch = kThreads;              // records per LDS batch
+};
+
+// The support predicate and the Gaussian falloff.  Forward and backward call
+// exactly this code, so they take the same support decision for every pair,
+// whatever the tile size.
+__device__ __forceinline__ float pair_q(const SplatRec& r, float pcx, float pcy, float* dx_o, float* dy_o) {
+  const float dx = (pcx - r.r1.y) - r.r0.x;   // first difference is exact
+  const float dy = (pcy - r.r1.z) - r.r0.y;
+  const float t = fmaf(r.r0.z, dx, r.r0.w * dy);
+  *dx_o = dx;
+  *dy_o = dy;
+  return fmaf(t, dx, (r.r1.x * dy) * dy);
+}
+
+__device__ __forceinline__ float falloff(float q) { return __expf(-0.5f * q); }
+
+__device__ __forceinline__ float2 rec_extent(const SplatRec& r) {
+  const uint32_t e = __float_as_uint(r.r2.w);
+  const _Float16 ex = __builtin_bit_cast(_Float16, static_cast<uint16_t>(e & 0xffffu));
+  const _Float16 ey = __builtin_bit_cast(_Float16, static_cast<uint16_t>(e >> 16));
+  return make_float2(static_cast<float>(ex), static_cast<float>(ey));
+}
+
+// Does the splat's support box reach the wave block whose first pixel centre
+// is (bx, by) and whose last is (bx + sub - 1, by + sub - 1)?
+__device__ __forceinline__ bool box_hits(const SplatRec& r, float bx, float by, float sub1) {
+  const float2 e = rec_extent(r);
+  const float mx = r.r1.y + r.r0.x, my = r.r1.z + r.r0.y;
+  const float sx = 1e-3f * fabsf(mx) + 1e-2f, sy = 1e-3f * fabsf(my) + 1e-2f;  // rounding slack
+  return (mx + e.x + sx >= bx) && (mx - e.x - sx <= bx + sub1) &&
+         (my + e.y + sy >= by) && (my - e.y - sy <= by + sub1);
+}
+
+struct RasterArgs {
+  const DevCamera* cams;
+  const SplatRec* rec;
+  const uint32_t* hist;
+  const uint32_t* ids;
+  int64_t n;
+  int64_t capacity;
+  int32_t nv;
+  int32_t nblk;
+  float tau;
+  const float* globals;
+  // forward outputs
+  float* out_rgb;
+  float* out_den;
+  int32_t* out_count;
+  // backward inputs / outputs
+  const float* dL_drgb;
+  const float* rgb;
+  const float* den;
+  float* grad2d;
+  float* tilepart;
+};
+
+__device__ __forceinline__ int find_view(const DevCamera* cams, int nv, int tile) {
+  int v = 0;
+  while (v + 1 < nv && cams[v + 1].tile_base <= tile) ++v;
+  return v;
+}
+
+// Common tile set-up: view, tile coordinates, this lane's pixels, and the
+// [start, end) range of the tile's id list.
+template <int T>
+struct TileCtx {
+  int v, tx, ty;
+  int64_t n;
+  uint32_t start, end;
+  int wave, lane;
+  int bx0, by0;                   // first pixel of this wave's block
+  int px[TileGeom<T>::kPpl], py[TileGeom<T>::kPpl];
+};
+
+template <int T>
+__device__ __forceinline__ void tile_setup(const RasterArgs& a, TileCtx<T>& c, const DevCamera*& cam) {
+  using G = TileGeom<T>;
+  const int tile = blockIdx.x;
+  c.v = find_view(a.cams, a.nv, tile);
+  cam = &a.cams[c.v];
+  const int local = tile - cam->tile_base;
+  c.tx = local % cam->tiles_x;
+  c.ty = local / cam->tiles_x;
+  c.n = a.n;
+  const int64_t hb = cam->hist_base + static_cast<int64_t>(local) * a.nblk;
+  const uint64_t cap = static_cast<uint64_t>(a.capacity);
+  uint64_t s = a.hist[hb], e = a.hist[hb + a.nblk];
+  s = s < cap ? s : cap;
+  e = e < cap ? e : cap;
+  c.start = static_cast<uint32_t>(s);
+  c.end = static_cast<uint32_t>(e > s ? e : s);
+  c.wave = threadIdx.x / kWave;
+  c.lane = threadIdx.x % kWave;
+  c.bx0 = c.tx * T + (G::kWaves == 4 ? (c.wave & 1) * G::kSub : 0);
+  c.by0 = c.ty * T + (G::kWaves == 4 ? (c.wave >> 1) * G::kSub : 0);
+  const int lx = c.lane & 7, ly = c.lane >> 3;
+#pragma unroll
+  for (int k = 0; k < G::kPpl; ++k) {
+    c.px[k] = c.bx0 + lx + 8 * (k & 1);
+    c.py[k] = c.by0 + ly + 8 * (k >> 1);
+  }
+}
+
+// Stage one batch of records into LDS and build this wave's culled list.
+// Returns the list length.
+template <int T>
+__device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
+                                              SplatRec* s_rec, uint32_t* s_id, uint16_t* s_list) {
+  using G = TileGeom<T>;
+  __syncthreads();  // previous batch fully consumed
+  const uint32_t j = b + threadIdx.x;
+  if (j < c.end) {
+    const uint32_t id = a.ids[j];
+    s_id[threadIdx.x] = id;
+    s_rec[threadIdx.x] = a.rec[static_cast<int64_t>(c.v) * c.n + id];
+  }
+  __syncthreads();
+  const int cnt = static_cast<int>(min(static_cast<uint32_t>(G::kBatch), c.end - b));
+  uint16_t* list = s_list + c.wave * G::kBatch;
+  int m = 0;
+  const float bx = c.bx0 + 0.5f, by = c.by0 + 0.5f;
+  for (int k0 = 0; k0 < cnt; k0 += kWave) {
+    const int k = k0 + c.lane;
+    const bool hit = k < cnt && box_hits(s_rec[k], bx, by, static_cast<float>(G::kSub - 1));
+    const uint64_t mask = __ballot(hit);
+    if (hit) {
+      const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
+      list[pos] = static_cast<uint16_t>(k);
+    }
+    m += __popcll(mask);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return m;
+}
+
+template <int T, bool COUNT>
+__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
+  using G = TileGeom<T>;
+  __shared__ SplatRec s_rec[G::kBatch];
+  __shared__ uint32_t s_id[G::kBatch];
+  __shared__ uint16_t s_list[G::kWaves * G::kBatch];
+  TileCtx<T> c;
+  const DevCamera* cam;
+  tile_setup<T>(a, c, cam);
+
+  float nr[G::kPpl], ng[G::kPpl], nb[G::kPpl], dd[G::kPpl];
+  int cntp[G::kPpl];
+  float pcx[G::kPpl], pcy[G::kPpl];
+#pragma unroll
+  for (int k = 0; k < G::kPpl; ++k) {
+    nr[k] = ng[k] = nb[k] = dd[k] = 0.f;
+    cntp[k] = 0;
+    pcx[k] = static_cast<float>(c.px[k]) + 0.5f;
+    pcy[k] = static_cast<float>(c.py[k]) + 0.5f;
+  }
+  const float tau = a.tau;
+  for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
+    const int m = stage_and_cull<T>(a, c, b, s_rec, s_id, s_list);
+    const uint16_t* list = s_list + c.wave * G::kBatch;
+    for (int i = 0; i < m; ++i) {
+      const SplatRec r = s_rec[list[i]];
+#pragma unroll
+      for (int k = 0; k < G::kPpl; ++k) {
+        float dx, dy;
+        const float q = pair_q(r, pcx[k], pcy[k], &dx, &dy);
+        if (q <= tau) {
+          const float al = r.r1.w * falloff(q);
+          nr[k] = fmaf(al, r.r2.x, nr[k]);
+          ng[k] = fmaf(al, r.r2.y, ng[k]);
+          nb[k] = fmaf(al, r.r2.z, nb[k]);
+          dd[k] += al;
+          if (COUNT) ++cntp[k];
+        }
+      }
+    }
+  }
+  const float wbg = a.globals[2];
+  const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
+#pragma unroll
+  for (int k = 0; k < G::kPpl; ++k) {
+    if (c.px[k] >= cam->width || c.py[k] >= cam->height) continue;
+    const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py[k]) * cam->width + c.px[k];
+    const float D = wbg + dd[k];
+    const float Nr = fmaf(bgr, wbg, nr[k]), Ng = fmaf(bgg, wbg, ng[k]), Nb = fmaf(bgb, wbg, nb[k]);
+    float Cr = bgr, Cg = bgg, Cb = bgb;
+    if (D != 0.f) {
+      Cr = Nr / D;
+      Cg = Ng / D;
+      Cb = Nb / D;
+    }
+    a.out_rgb[3 * pix] = Cr;
+    a.out_rgb[3 * pix + 1] = Cg;
+    a.out_rgb[3 * pix + 2] = Cb;
+    a.out_den[pix] = D;
+    if (COUNT) a.out_count[pix] = cntp[k];
+  }
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
+}
+
+template <int T>
+__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(RasterArgs a) {
+  using G = TileGeom<T>;
+  __shared__ SplatRec s_rec[G::kBatch];
+  __shared__ uint32_t s_id[G::kBatch];
+  __shared__ uint16_t s_list[G::kWaves * G::kBatch];
+  __shared__ float s_bg[G::kWaves][4];
+  TileCtx<T> c;
+  const DevCamera* cam;
+  tile_setup<T>(a, c, cam);
+
+  const float wbg = a.globals[2];
+  const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
+  float gr[G::kPpl], gg[G::kPpl], gb[G::kPpl], sf[G::kPpl];
+  float pcx[G::kPpl], pcy[G::kPpl];
+  float bacc[4] = {0.f, 0.f, 0.f, 0.f};  // dL/dc_B (rgb), dL/dw_B
+#pragma unroll
+  for (int k = 0; k < G::kPpl; ++k) {
+    gr[k] = gg[k] = gb[k] = sf[k] = 0.f;
+    pcx[k] = static_cast<float>(c.px[k]) + 0.5f;
+    pcy[k] = static_cast<float>(c.py[k]) + 0.5f;
+    if (c.px[k] >= cam->width || c.py[k] >= cam->height) continue;
+    const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py[k]) * cam->width + c.px[k];
+    const float D = a.den[pix];
+    const float g0 = a.dL_drgb[3 * pix], g1 = a.dL_drgb[3 * pix + 1], g2 = a.dL_drgb[3 * pix + 2];
+    if (D != 0.f) {
+      const float iD = 1.f / D;
+      gr[k] = g0 * iD;
+      gg[k] = g1 * iD;
+      gb[k] = g2 * iD;
+      sf[k] = gr[k] * a.rgb[3 * pix] + gg[k] * a.rgb[3 * pix + 1] + gb[k] * a.rgb[3 * pix + 2];
+      bacc[0] += wbg * gr[k];
+      bacc[1] += wbg * gg[k];
+      bacc[2] += wbg * gb[k];
+      bacc[3] += gr[k] * bgr + gg[k] * bgg + gb[k] * bgb - sf[k];
+    } else {
+      // C is the background colour where the denominator vanishes
+      bacc[0] += g0;
+      bacc[1] += g1;
+      bacc[2] += g2;
+    }
+  }
+  const float tau = a.tau;
+  for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
+    const int m = stage_and_cull<T>(a, c, b, s_rec, s_id, s_list);
+    const uint16_t* list = s_list + c.wave * G::kBatch;
+    for (int i = 0; i < m; ++i) {
+      const int k_rec = list[i];
+      const SplatRec r = s_rec[k_rec];
+      float g9[9];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) g9[j] = 0.f;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < G::kPpl; ++k) {
+        float dx, dy;
+        const float q = pair_q(r, pcx[k], pcy[k], &dx, &dy);
+        if (q <= tau) {
+          any = true;
+          const float Gq = falloff(q);
+          const float al = r.r1.w * Gq;
+          const float dLda = gr[k] * r.r2.x + gg[k] * r.r2.y + gb[k] * r.r2.z - sf[k];
+          const float dq = -0.5f * al * dLda;
+          // q = A dx^2 + B2 dx dy + C dy^2 with dx = px - mu_x
+          g9[0] -= dq * fmaf(2.f * r.r0.z, dx, r.r0.w * dy);
+          g9[1] -= dq * fmaf(2.f * r.r1.x, dy, r.r0.w * dx);
+          g9[2] = fmaf(dq, dx * dx, g9[2]);
+          g9[3] = fmaf(dq, 2.f * dx * dy, g9[3]);
+          g9[4] = fmaf(dq, dy * dy, g9[4]);
+          g9[5] = fmaf(al, gr[k], g9[5]);
+          g9[6] = fmaf(al, gg[k], g9[6]);
+          g9[7] = fmaf(al, gb[k], g9[7]);
+          g9[8] = fmaf(dLda, Gq, g9[8]);
+        }
+      }
+      if (__ballot(any) == 0ull) continue;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) g9[j] = wave_sum(g9[j]);
+      if (c.lane == 0) {
+        float* dst = a.grad2d + (static_cast<int64_t>(c.v) * c.n + s_id[k_rec]) * 9;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) unsafeAtomicAdd(dst + j, g9[j]);
+      }
+    }
+  }
+  // per-tile background partial sums
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float s = wave_sum(bacc[j]);
+    if (c.lane == 0) s_bg[c.wave][j] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    float s = 0.f;
+#pragma unroll
+    for (int w = 0; w < G::kWaves; ++w) s += s_bg[w][threadIdx.x];
+    a.tilepart[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = s;
+  }
+}
+
+RasterArgs make_args(const Layout& L, const void* ws, const uint32_t* ids, int64_t capacity,
+                     const wsr_params* P, const float* globals) {
+  RasterArgs a = {};
+  a.cams = at<DevCamera>(ws, L.off_cams);
+  a.rec = at<SplatRec>(ws, L.off_rec);
+  a.hist = at<uint32_t>(ws, L.off_hist);
+  a.ids = ids;
+  a.n = L.n;
+  a.capacity = capacity;
+  a.nv = L.nv;
+  a.nblk = L.nblk;
+  a.tau = P->tau;
+  a.globals = globals;
+  return a;
+}
+
+template <int T>
+hipError_t fwd_t(const RasterArgs& a, int64_t tiles, bool count, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(tiles));
+  if (count)
+    raster_fwd_kernel<T, true><<<grid, TileGeom<T>::kThreads, 0, st>>>(a);
+  else
+    raster_fwd_kernel<T, false><<<grid, TileGeom<T>::kThreads, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int T>
+hipError_t bwd_t(const RasterArgs& a, int64_t tiles, hipStream_t st) {
+  raster_bwd_kernel<T><<<dim3(static_cast<unsigned>(tiles)), TileGeom<T>::kThreads, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_raster_fwd(const Layout& L, const void* ws, const uint32_t* ids, int64_t capacity,
+                             const wsr_params* P, const float* globals, float* out_rgb,
+                             float* out_den, int32_t* out_count, hipStream_t st) {
+  if (L.total_tiles == 0) return hipSuccess;
+  RasterArgs a = make_args(L, ws, ids, capacity, P, globals);
+  a.out_rgb = out_rgb;
+  a.out_den = out_den;
+  a.out_count = out_count;
+  const bool cnt = out_count != nullptr;
+  switch (L.tile) {
+    case 8: return fwd_t<8>(a, L.total_tiles, cnt, st);
+    case 32: return fwd_t<32>(a, L.total_tiles, cnt, st);
+    default: return fwd_t<16>(a, L.total_tiles, cnt, st);
+  }
+}
+
+hipError_t launch_raster_bwd(const Layout& L, void* ws, const uint32_t* ids, int64_t capacity,
+                             const wsr_params* P, const float* globals, const float* dL_drgb,
+                             const float* rgb, const float* den, hipStream_t st) {
+  if (L.total_tiles == 0) return hipSuccess;
+  RasterArgs a = make_args(L, ws, ids, capacity, P, globals);
+  a.dL_drgb = dL_drgb;
+  a.rgb = rgb;
+  a.den = den;
+  a.grad2d = at<float>(ws, L.off_grad2d);
+  a.tilepart = at<float>(ws, L.off_tilepart);
+  switch (L.tile) {
+    case 8: return bwd_t<8>(a, L.total_tiles, st);
+    case 32: return bwd_t<32>(a, L.total_tiles, st);
+    default: return bwd_t<16>(a, L.total_tiles, st);
+  }
+}
+
+}  // namespace wsr

@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP sources of the WSR library.
+// Everything here is gfx950-only (wave64, 160 KB LDS per CU).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wsr.h"
+
+namespace wsr {
+
+constexpr int kWave = 64;
+constexpr int kBinChunk = 8192;       // Gaussians per binning block
+constexpr int kTileChunk = 14336;     // tiles per binning LDS histogram (56 KB + static < 64 KB)
+constexpr int kScanItems = 4096;      // elements per scan block (256 threads x 16)
+constexpr int kRasterBatch = 256;     // splats staged in LDS per batch
+constexpr int kProjBlock = 256;
+
+// Camera as the kernels see it, with the per-view offsets into the
+// concatenated tile, pixel and histogram spaces.
+struct DevCamera {
+  float R[9];
+  float T[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_base;   // first global tile index of this view
+  int32_t pad0;
+  int64_t pix_base;    // first pixel of this view in the concatenated images
+  int64_t hist_base;   // first entry of this view in the (tile, block) count matrix
+};
+
+// Splat record written by the projection (48 bytes, three float4):
+//   r0 = (mx, my, A, B2)    centre relative to the integer origin (ox, oy), conic A, 2B
+//   r1 = (C, ox, oy, amp)   conic C, integer origin as exact floats, amplitude u*w
+//   r2 = (r, g, b, ext)     colour; ext packs the support half-extents (2 x fp16)
+struct __align__(16) SplatRec {
+  float4 r0, r1, r2;
+};
+
+// Device-side status words (in the workspace).
+struct DevFlags {
+  uint32_t overflow;        // id-list capacity exceeded
+  uint32_t wrapped;         // 32-bit pair count wrapped
+  uint64_t total_pairs;     // pairs produced by the last binning
+};
+
+struct Layout {
+  int64_t n = 0;
+  int32_t nv = 0;
+  int32_t tile = 16;
+  int32_t nblk = 1;          // binning blocks per view = ceil(n / kBinChunk)
+  int32_t max_tiles_x = 1;
+  int32_t max_tiles_y = 1;
+  int64_t total_tiles = 0;
+  int64_t total_pixels = 0;
+  int64_t hist_len = 0;      // entries of the count matrix (without the trailing total)
+  int64_t scan_parts = 0;
+  size_t off_cams = 0, off_flags = 0, off_rec = 0, off_rect = 0, off_hist = 0, off_scan = 0,
+         off_grad2d = 0, off_tilepart = 0, off_gpart = 0;
+  int64_t gpart_blocks = 0;
+  size_t bytes = 0;
+};
+
+// Fill `L` (and the device cameras `dc`, host array of nv entries) from the
+// arguments; returns false on invalid input.
+bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, Layout* L,
+                 DevCamera* dc);
+
+template <typename T>
+__host__ __device__ inline T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+template <typename T>
+__host__ __device__ inline const T* at(const void* base, size_t off) {
+  return reinterpret_cast<const T*>(static_cast<const char*>(base) + off);
+}
+
+// Storage loads: fp32, fp16 or bf16 element -> float.
+template <int S>
+__device__ inline float load_attr(const void* p, int64_t idx);
+template <>
+__device__ inline float load_attr<WSR_STORE_F32>(const void* p, int64_t idx) {
+  return static_cast<const float*>(p)[idx];
+}
+template <>
+__device__ inline float load_attr<WSR_STORE_F16>(const void* p, int64_t idx) {
+  return static_cast<float>(static_cast<const _Float16*>(p)[idx]);
+}
+template <>
+__device__ inline float load_attr<WSR_STORE_BF16>(const void* p, int64_t idx) {
+  const uint32_t b = static_cast<uint32_t>(static_cast<const uint16_t*>(p)[idx]) << 16;
+  return __uint_as_float(b);
+}
+
+// Four consecutive storage elements (one SH coefficient, RGBA) -> float4.
+template <int S>
+__device__ inline float4 load_attr4(const void* p, int64_t idx4);
+template <>
+__device__ inline float4 load_attr4<WSR_STORE_F32>(const void* p, int64_t idx4) {
+  return static_cast<const float4*>(p)[idx4];
+}
+template <>
+__device__ inline float4 load_attr4<WSR_STORE_F16>(const void* p, int64_t idx4) {
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  const h4 v = static_cast<const h4*>(p)[idx4];
+  return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+}
+template <>
+__device__ inline float4 load_attr4<WSR_STORE_BF16>(const void* p, int64_t idx4) {
+  const uint2 v = static_cast<const uint2*>(p)[idx4];
+  return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+                     __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+}
+
+// Launchers (host side), one per source file.
+hipError_t launch_project(const wsr_scene* sc, const wsr_params* P, const float* globals,
+                          const Layout& L, void* ws, float* out_proj, hipStream_t st);
+hipError_t launch_upload_cameras(const DevCamera* dc, int32_t nv, void* ws, const Layout& L,
+                                 hipStream_t st);
+hipError_t launch_bin(const Layout& L, void* ws, uint32_t* ids, int64_t capacity, hipStream_t st);
+hipError_t launch_raster_fwd(const Layout& L, const void* ws, const uint32_t* ids, int64_t capacity,
+                             const wsr_params* P, const float* globals, float* out_rgb,
+                             float* out_den, int32_t* out_count, hipStream_t st);
+hipError_t launch_raster_bwd(const Layout& L, void* ws, const uint32_t* ids, int64_t capacity,
+                             const wsr_params* P, const float* globals, const float* dL_drgb,
+                             const float* rgb, const float* den, hipStream_t st);
+hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const float* globals,
+                              const Layout& L, void* ws, const wsr_grads* g, float* out_grad2d,
+                              hipStream_t st);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace wsr

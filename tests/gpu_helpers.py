@@ -1,0 +1,88 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C-ABI
+binding and compare with the FP64 checker."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+import wsr_synth as ws
+from paper_2410_18931_amd import WSRContext, globals_tensor, scene_to_device
+
+IMG_TOL = 1e-4      # max-abs on [0, 1] colours
+GRAD_TOL = 1e-3     # per tensor: max |g_gpu - g_ref| <= GRAD_TOL * max |g_ref|
+AMB_ETA = 1e-4      # pairs with |q - tau| <= AMB_ETA * tau may flip in float32
+ILL_DEN = 1e-3      # |den| below this: ill-conditioned pixel, counted not gated
+
+
+def log(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_forward(scene, cams, settings, storage="f32", count=False, capacity=None):
+    ctx = WSRContext(scene["means"].shape[1], cams, settings, capacity=capacity)
+    dev = scene_to_device(scene, storage=storage)
+    g = globals_tensor(settings)
+    out = ctx.forward(dev, g, count=count)
+    torch.cuda.synchronize()
+    ctx.check()
+    return ctx, dev, g, out
+
+
+def to_views(ctx, t):
+    return [v.detach().cpu().numpy() for v in ctx.views(t)]
+
+
+def compare_image(C_gpu, ref, tol=IMG_TOL, label=""):
+    """Max-abs comparison that accounts for pairs whose support decision is
+    within rounding of the cutoff (the reference reports, per pixel, the sum
+    over such pairs of |a| * max|rgb - C|): those pixels may differ by up to
+    2 * that sum / |den| more.  Returns a dict of statistics."""
+    C_ref, den = ref["C"], ref["den"]
+    err = np.abs(C_gpu.astype(np.float64) - C_ref).max(axis=-1)
+    ill = np.abs(den) < ILL_DEN
+    amb = ref["amb_c"] > 0
+    bound = tol + 2.0 * ref["amb_c"] / np.maximum(np.abs(den), ILL_DEN)
+    clean = ~amb & ~ill
+    st = {
+        "max_err_clean": float(err[clean].max()) if clean.any() else 0.0,
+        "max_err_all": float(err[~ill].max()) if (~ill).any() else 0.0,
+        "ambiguous_px": int(amb.sum()), "ill_px": int(ill.sum()), "px": int(err.size),
+        "over_bound": int((err[~ill] > bound[~ill]).sum()),
+    }
+    log(f"[image {label}] {st}")
+    assert st["max_err_clean"] <= tol, st
+    assert st["over_bound"] == 0, st
+    assert st["ill_px"] <= max(2, 0.001 * err.size), st
+    assert st["ambiguous_px"] <= max(20, 0.01 * err.size), st
+    return st
+
+
+def compare_grads(g_gpu: dict, g_ref: dict, keys, tol=GRAD_TOL, label=""):
+    for k in keys:
+        a = np.asarray(g_gpu[k], dtype=np.float64)
+        b = np.asarray(g_ref[k], dtype=np.float64)
+        assert a.shape == b.shape, (k, a.shape, b.shape)
+        scale = np.abs(b).max()
+        err = np.abs(a - b).max()
+        log(f"[grad {label}] {k}: max|ref|={scale:.4g} max|err|={err:.4g} rel={err / max(scale, 1e-30):.3g}")
+        if scale == 0.0:
+            assert err <= 1e-6, (k, err)
+        else:
+            assert err <= tol * scale, (k, err, scale)
+
+
+def grads_to_numpy(g: dict) -> dict:
+    return {k: v.detach().cpu().numpy() for k, v in g.items()}
+
+
+def densest_crop(count_img: np.ndarray, size=64) -> tuple:
+    """(x0, y0, x1, y1) of the size x size window with the most pairs."""
+    H, W = count_img.shape
+    c = np.cumsum(np.cumsum(np.pad(count_img.astype(np.int64), ((1, 0), (1, 0))), 0), 1)
+    s = c[size:, size:] - c[:-size, size:] - c[size:, :-size] + c[:-size, :-size]
+    y, x = np.unravel_index(np.argmax(s), s.shape)
+    return int(x), int(y), int(x) + size, int(y) + size

@@ -1,0 +1,313 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 checker on
+the same seeded inputs.  Images within 1e-4 max-abs (plus the documented
+allowance for pairs within float rounding of the support cutoff), gradients
+within 1e-3 of each tensor's max-abs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import wsr_synth as ws
+from paper_2410_18931_amd import WSRContext, globals_tensor, render, scene_to_device
+from tests.gpu_helpers import (AMB_ETA, compare_grads, compare_image, densest_crop, gpu_forward,
+                               grads_to_numpy, log, to_views)
+from tests.oracle_helpers import empty_like
+
+pytestmark = pytest.mark.gpu
+
+SCENE_KEYS = ("means", "log_scales", "quats", "sh", "opacity_logit", "lc_v")
+
+
+def _grad_keys(settings, K):
+    keys = ["means", "log_scales", "quats", "sh"]
+    if settings.opacity_mode == "logit":
+        keys.append("opacity_logit")
+    if settings.weight_kind == "lc":
+        keys.append("lc_v")
+    return keys
+
+
+def _oracle_globals(settings, gref):
+    out = gref.copy()
+    if settings.weight_kind == "dir":
+        out[0] = 0.0
+    if settings.weight_kind != "exp":
+        out[1] = 0.0
+    return out
+
+
+def _check_globals(g_gpu, g_ref, label):
+    a, b = np.asarray(g_gpu, np.float64), np.asarray(g_ref, np.float64)
+    log(f"[globals {label}] gpu={a} ref={b}")
+    np.testing.assert_allclose(a, b, rtol=1e-3, atol=1e-3 * max(1.0, np.abs(b).max()))
+
+
+# ---------------------------------------------------------------- c1 (small)
+
+@pytest.fixture(scope="module")
+def c1():
+    return ws.make_scene("c1")
+
+
+def test_c1_projection_stage(c1):
+    sc, cams, st = c1
+    log("case: c1 projection stage")
+    ctx = WSRContext(sc["means"].shape[1], cams, st)
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    proj = torch.zeros((1, ctx.n, 16), dtype=torch.float32, device="cuda")
+    ctx.project(dev, g, out_proj=proj)
+    torch.cuda.synchronize()
+    p = proj[0].cpu().numpy().astype(np.float64)
+    ref = oracle.project(sc, cams[0], st)
+    vis = ref["visible"]
+    assert np.array_equal(p[:, 0] > 0.5, vis)
+    np.testing.assert_allclose(p[vis, 1:3], ref["mu"][vis], atol=2e-4)
+    np.testing.assert_allclose(p[vis, 3:6], ref["conic"][vis], rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(p[vis, 6:9], ref["rgb"][vis], atol=2e-6)
+    np.testing.assert_allclose(p[vis, 9], ref["u"][vis], atol=2e-6)
+    np.testing.assert_allclose(p[vis, 10], ref["w"][vis], rtol=2e-6)
+    np.testing.assert_allclose(p[:, 11], ref["depth"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_c1_image_and_counts(c1, tile):
+    sc, cams, st = c1
+    st = st.copy(tile=tile)
+    log(f"case: c1 image tile={tile}")
+    ctx, dev, g, (rgb, den, cnt) = gpu_forward(sc, cams, st, count=True)
+    ref = oracle.render(sc, cams[0], st, eta=AMB_ETA)
+    C = to_views(ctx, rgb)[0]
+    compare_image(C, ref, label=f"c1 t{tile}")
+    D = to_views(ctx, den)[0]
+    np.testing.assert_allclose(D, ref["den"], rtol=1e-5, atol=1e-5)
+    n_gpu = to_views(ctx, cnt)[0]
+    differ = n_gpu != ref["count"]
+    assert np.all(ref["amb"][differ] > 0), "count differs away from the cutoff"
+    assert ctx.last_pairs > 0
+
+
+def test_c1_tile_size_invariance(c1):
+    sc, cams, st = c1
+    imgs = []
+    for tile in (8, 16, 32):
+        log(f"case: c1 tile invariance tile={tile}")
+        ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st.copy(tile=tile))
+        imgs.append(rgb.cpu().numpy())
+    assert np.abs(imgs[0] - imgs[1]).max() <= 1e-6
+    assert np.abs(imgs[0] - imgs[2]).max() <= 1e-6
+
+
+def test_c1_gradients(c1):
+    sc, cams, st = c1
+    log("case: c1 gradients")
+    ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st)
+    r = ws.upstream_grad(cams, seed=3)
+    dL = torch.from_numpy(r[0].reshape(-1, 3)).cuda()
+    grad2d = torch.zeros((1, ctx.n, 9), dtype=torch.float32, device="cuda")
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, dL, rgb, den, grad2d=grad2d))
+    gref = oracle.render_bwd(sc, cams[0], st, r[0])
+    compare_grads(gg, gref, _grad_keys(st, 1), label="c1")
+    compare_grads({"grad2d": grad2d[0].cpu().numpy()}, {"grad2d": gref["grad2d"]}, ["grad2d"], label="c1 2d")
+    _check_globals(gg["globals"], _oracle_globals(st, gref["globals"]), "c1")
+
+
+def test_autograd_function_matches_direct_backward(c1):
+    sc, cams, st = c1
+    log("case: autograd wrapper")
+    ctx = WSRContext(sc["means"].shape[1], cams, st)
+    dev = scene_to_device(sc)
+    leaves = {k: v.clone().requires_grad_(True) for k, v in dev.items()}
+    g = globals_tensor(st).requires_grad_(True)
+    rgb, den = render(leaves, g, ctx)
+    r = torch.from_numpy(ws.upstream_grad(cams, seed=4)[0].reshape(-1, 3)).cuda()
+    (rgb * r).sum().backward()
+    direct = ctx.render_bwd(dev, g.detach(), r, rgb.detach(), den)
+    for k in ("means", "log_scales", "quats", "sh", "opacity_logit"):
+        assert torch.allclose(leaves[k].grad, direct[k], rtol=1e-6, atol=1e-7), k
+    assert torch.allclose(g.grad, direct["globals"], rtol=1e-6, atol=1e-7)
+
+
+# ---------------------------------------------------------------- c2 (720p)
+
+@pytest.fixture(scope="module")
+def c2():
+    return ws.make_scene("c2")
+
+
+def test_c2_image_full_frame(c2):
+    sc, cams, st = c2
+    log("case: c2 full-frame image")
+    ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st)
+    ref = oracle.render(sc, cams[0], st, mode="aabb", eta=AMB_ETA)
+    compare_image(to_views(ctx, rgb)[0], ref, label="c2")
+
+
+def test_c2_gradients_on_crop(c2):
+    sc, cams, st = c2
+    log("case: c2 gradients on a crop")
+    ctx, dev, g, (rgb, den, cnt) = gpu_forward(sc, cams, st, count=True)
+    crop = densest_crop(to_views(ctx, cnt)[0])
+    x0, y0, x1, y1 = crop
+    r = np.zeros((720, 1280, 3), np.float32)
+    r[y0:y1, x0:x1] = np.random.default_rng(5).standard_normal((y1 - y0, x1 - x0, 3))
+    dL = torch.from_numpy(r.reshape(-1, 3)).cuda()
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, dL, rgb, den))
+    gref = oracle.render_bwd(sc, cams[0], st, r[y0:y1, x0:x1], crop=crop)
+    compare_grads(gg, gref, _grad_keys(st, 16), label="c2 crop")
+    _check_globals(gg["globals"], _oracle_globals(st, gref["globals"]), "c2 crop")
+
+
+def test_c2_reduced_precision_storage(c2):
+    sc, cams, st = c2
+    for dt in ("f16", "bf16"):
+        log(f"case: c2 storage {dt}")
+        q = ws.quantise(sc, dt)
+        ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st, storage=dt)
+        crop = (600, 320, 664, 384)
+        ref = oracle.render(q["f32"], cams[0], st, crop=crop, eta=AMB_ETA)
+        C = to_views(ctx, rgb)[0][320:384, 600:664]
+        compare_image(C, ref, label=f"c2 {dt} vs dequantised")
+        src = oracle.render(sc, cams[0], st, crop=crop)
+        log(f"[c2 {dt}] end-to-end max-abs vs fp32 source: {np.abs(C - src['C']).max():.3g}")
+
+
+def test_gpu_permutation_invariance(c2):
+    sc, cams, st = c2
+    log("case: permutation invariance")
+    perm = np.random.default_rng(9).permutation(sc["means"].shape[1])
+    _, _, _, (a, _) = gpu_forward(sc, cams, st)
+    _, _, _, (b, _) = gpu_forward(ws.permute(sc, perm), cams, st)
+    assert (a - b).abs().max().item() <= 2e-6
+
+
+# ---------------------------------------------------------------- c3 and the 1M / 1080p configuration
+
+@pytest.mark.parametrize("config", ["c3", "headline"])
+def test_1080p_crops(config):
+    sc, cams, st = ws.make_scene(config)
+    log(f"case: {config} n={sc['means'].shape[1]} 1080p")
+    ctx, dev, g, (rgb, den, cnt) = gpu_forward(sc, cams, st, count=True)
+    C = to_views(ctx, rgb)[0]
+    counts = to_views(ctx, cnt)[0]
+    log(f"[{config}] pairs in support {int(counts.sum())}, binned pairs {ctx.last_pairs}")
+    crops = [densest_crop(counts), (0, 0, 64, 64), (1856, 1016, 1920, 1080), (928, 508, 992, 572)]
+    for crop in crops:
+        x0, y0, x1, y1 = crop
+        ref = oracle.render(sc, cams[0], st, crop=crop, eta=AMB_ETA)
+        compare_image(C[y0:y1, x0:x1], ref, label=f"{config} {crop}")
+    if config == "c3":
+        x0, y0, x1, y1 = crops[0]
+        r = np.zeros((1080, 1920, 3), np.float32)
+        r[y0:y1, x0:x1] = np.random.default_rng(6).standard_normal((y1 - y0, x1 - x0, 3))
+        gg = grads_to_numpy(ctx.render_bwd(dev, g, torch.from_numpy(r.reshape(-1, 3)).cuda(), rgb, den))
+        gref = oracle.render_bwd(sc, cams[0], st, r[y0:y1, x0:x1], crop=crops[0])
+        compare_grads(gg, gref, _grad_keys(st, 16), label="c3 crop")
+
+
+# ---------------------------------------------------------------- several views
+
+def test_multi_view_uneven_sizes():
+    sc, _, st = ws.make_scene("c3", n=40000)
+    rng = np.random.default_rng(3)
+    cams = []
+    for k in range(4):
+        w = int(rng.integers(96, 257))
+        u = rng.standard_normal(3)
+        cams.append(ws.look_at_camera(u / np.linalg.norm(u) * rng.uniform(4, 6), w, int(round(9 * w / 16))))
+    log("case: multi-view " + str([(c["width"], c["height"]) for c in cams]))
+    ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st)
+    imgs = to_views(ctx, rgb)
+    rs = ws.upstream_grad(cams, seed=8)
+    for v, cam in enumerate(cams):
+        compare_image(imgs[v], oracle.render(sc, cam, st, mode="aabb", eta=AMB_ETA), label=f"view {v}")
+    dL = torch.cat([torch.from_numpy(r.reshape(-1, 3)) for r in rs]).cuda()
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, dL, rgb, den))
+    gref = oracle.render_bwd_views(sc, cams, st, rs)
+    compare_grads(gg, gref, _grad_keys(st, 16), label="multi-view")
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_empty_scene_and_all_culled():
+    sc, cams, st = ws.make_scene("c1", n=64)
+    log("case: empty scene")
+    e = empty_like(sc)
+    ctx, dev, g, (rgb, den) = gpu_forward(e, cams, st)
+    assert torch.all(rgb == torch.tensor(st.bg, device="cuda")).item()
+    assert torch.all(den == st.w_bg).item()
+    r = torch.randn_like(rgb)
+    gg = ctx.render_bwd(dev, g, r, rgb, den)
+    gb = gg["globals"].cpu().numpy()
+    np.testing.assert_allclose(gb[3:6], r.sum(0).cpu().numpy() / st.w_bg * st.w_bg, rtol=1e-4)
+    log("case: all behind the camera")
+    b = dict(sc)
+    b["means"] = sc["means"].copy()
+    b["means"][2] = -10.0
+    ctx, dev, g, (rgb, den) = gpu_forward(b, cams, st)
+    assert torch.all(rgb == torch.tensor(st.bg, device="cuda")).item()
+    gg = ctx.render_bwd(dev, g, torch.randn_like(rgb), rgb, den)
+    assert gg["means"].abs().max().item() == 0.0
+
+
+def test_zero_background_weight_and_uncovered_pixels():
+    sc, cams, st = ws.make_scene("c1", n=200)
+    st = st.copy(w_bg=0.0)
+    log("case: w_B = 0")
+    ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st)
+    ref = oracle.render(sc, cams[0], st, eta=AMB_ETA)
+    assert np.any(ref["den"] == 0)
+    C = to_views(ctx, rgb)[0]
+    compare_image(C, ref, label="w_B=0")
+    r = ws.upstream_grad(cams, seed=2)[0]
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, torch.from_numpy(r.reshape(-1, 3)).cuda(), rgb, den))
+    gref = oracle.render_bwd(sc, cams[0], st, r)
+    compare_grads(gg, gref, _grad_keys(st, 1), label="w_B=0")
+    _check_globals(gg["globals"], _oracle_globals(st, gref["globals"]), "w_B=0")
+
+
+def test_ragged_image_and_single_gaussian():
+    sc, _, st = ws.make_scene("c1", n=1)
+    sc["means"][:] = 0.0
+    sc["log_scales"][:] = -1.5
+    for (w, h) in ((100, 37), (1, 1), (33, 65)):
+        cams = [ws.look_at_camera((0.0, 0.0, -4.0), w, h)]
+        for tile in (8, 16, 32):
+            log(f"case: single Gaussian {w}x{h} tile {tile}")
+            ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st.copy(tile=tile))
+            compare_image(to_views(ctx, rgb)[0], oracle.render(sc, cams[0], st, eta=AMB_ETA), label=f"{w}x{h}")
+
+
+def test_huge_and_degenerate_splats():
+    sc, cams, st = ws.make_scene("c1", n=50)
+    sc["log_scales"][:, 0] = 1.0          # covers the whole image
+    sc["quats"][:, 1] = 0.0               # zero quaternion: culled
+    sc["log_scales"][:, 2] = [-30.0, -30.0, -30.0]  # vanishing: only the dilation remains
+    log("case: huge / degenerate splats")
+    ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st)
+    ref = oracle.render(sc, cams[0], st, eta=AMB_ETA)
+    compare_image(to_views(ctx, rgb)[0], ref, label="huge+degenerate")
+    r = ws.upstream_grad(cams, seed=1)[0]
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, torch.from_numpy(r.reshape(-1, 3)).cuda(), rgb, den))
+    gref = oracle.render_bwd(sc, cams[0], st, r)
+    compare_grads(gg, gref, _grad_keys(st, 1), label="huge+degenerate")
+
+
+def test_capacity_overflow_is_reported_then_recovered():
+    sc, cams, st = ws.make_scene("c1")
+    log("case: id-list overflow")
+    ctx = WSRContext(sc["means"].shape[1], cams, st, capacity=1000)
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    ctx.project(dev, g)
+    ctx.bin(grow=False)
+    from paper_2410_18931_amd._lib import WSR_ERR_CAPACITY, WsrError
+    with pytest.raises(WsrError) as ei:
+        ctx.check()
+    assert ei.value.status == WSR_ERR_CAPACITY
+    rgb, den = ctx.render_fwd(g)     # incomplete but memory-safe
+    torch.cuda.synchronize()
+    ctx.bin(grow=True)
+    ctx.check()
+    rgb, den = ctx.render_fwd(g)
+    compare_image(to_views(ctx, rgb)[0], oracle.render(sc, cams[0], st, eta=AMB_ETA), label="after regrow")
