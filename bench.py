@@ -48,7 +48,7 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(n: int, pixels: int, storage: str, nv: int = 1) -> dict:
+def algorithmic_bytes(n: int, pixels: int, storage: str, binned: int, nv: int = 1) -> dict:
     """HBM bytes the method must move per step (SH degree 3 RGBA, LC weights).
     Attributes: means 3, log-scales 3, quaternion 4, SH 16x4 values + v_i."""
     vals = 3 + 3 + 4 + 64
@@ -56,6 +56,7 @@ def algorithmic_bytes(n: int, pixels: int, storage: str, nv: int = 1) -> dict:
     grads = n * (vals + 1) * 4
     return {
         "project": attr + n * nv * 56,                       # attributes in, 2D record + rect out
+        "bin": n * nv * 16 + binned * 4,                     # rects read twice, ids written
         "raster_fwd": pixels * 16,                           # colour + denominator out
         "raster_bwd": pixels * 28,                           # dL/dC, C, D in
         "project_bwd": attr + n * nv * 36 + grads,           # attributes + 2D grads in, grads out
@@ -174,7 +175,7 @@ def main():
     stage_ms = {nm: float(np.mean([ev[j].elapsed_time(ev[j + 1]) for ev in events])) for j, nm in enumerate(names)}
     ms = (t1 - t0) * 1e3 / args.steps
     fps = 1e3 / ms
-    ab = algorithmic_bytes(n, P, args.storage)
+    ab = algorithmic_bytes(n, P, args.storage, binned)
     dominant = max(("raster_fwd", "raster_bwd"), key=lambda s: stage_ms[s])
     flops = pairs * (FWD_FLOPS_PER_PAIR if dominant == "raster_fwd" else BWD_FLOPS_PER_PAIR)
     achieved = flops / (stage_ms[dominant] * 1e-3) / 1e12

@@ -65,7 +65,7 @@ def _load():
         P = C.c_void_p
         lib.ora_project.argtypes = [P, P, P, P]
         lib.ora_render.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
-                                   C.c_int32, C.c_double, P, P, P, P, P, P]
+                                   C.c_int32, C.c_double, P, P, P, P, P, P, P]
         lib.ora_render_bwd.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                        P, P, P, P, P, P, P, P, P]
         lib.ora_sh_basis.argtypes = [P, C.c_int64, C.c_int32, P]
@@ -132,9 +132,11 @@ def _window(cam, crop):
     return x0, y0, x1, y1
 
 
-def render(scene, cam, settings, crop=None, mode: str = "strict", eta: float = 1e-4) -> dict:
+def render(scene, cam, settings, crop=None, mode: str = "strict", eta: float = 1e-6) -> dict:
     """Weighted sum rendering of one view (Sec. 4.2, Eq. 7) over the pixel
-    window ``crop = (x0, y0, x1, y1)`` (whole image by default)."""
+    window ``crop = (x0, y0, x1, y1)`` (whole image by default).  ``amb`` /
+    ``amb_c`` report the pairs within ``eta`` (relative to the magnitude of
+    the terms of q) of the support cutoff; ``abs_den`` is |w_B| + sum |a|."""
     pk = _Packed(scene, cam, settings)
     x0, y0, x1, y1 = _window(cam, crop)
     h, w = max(y1 - y0, 0), max(x1 - x0, 0)
@@ -143,11 +145,12 @@ def render(scene, cam, settings, crop=None, mode: str = "strict", eta: float = 1
     den = np.zeros((h, w))
     amb = np.zeros((h, w))
     ambc = np.zeros((h, w))
+    absden = np.zeros((h, w))
     cnt = np.zeros((h, w), dtype=np.int64)
     _load().ora_render(C.byref(pk.scene), C.byref(pk.cam), C.byref(pk.params), x0, y0, x1, y1,
                        {"strict": 0, "aabb": 1}[mode], float(eta), _ptr(Cimg), _ptr(num),
-                       _ptr(den), _ptr(amb), _ptr(ambc), _ptr(cnt))
-    return {"C": Cimg, "num": num, "den": den, "amb": amb, "amb_c": ambc, "count": cnt}
+                       _ptr(den), _ptr(amb), _ptr(ambc), _ptr(absden), _ptr(cnt))
+    return {"C": Cimg, "num": num, "den": den, "amb": amb, "amb_c": ambc, "abs_den": absden, "count": cnt}
 
 
 def render_bwd(scene, cam, settings, dL_dC, crop=None) -> dict:

@@ -420,16 +420,21 @@ static void free_visible(vis_t *v)
  *   out_C [h][w][3]   colour; den == 0 gives the background colour
  *   out_num [h][w][3] numerator including c_B w_B
  *   out_den [h][w]    denominator including w_B
- *   out_amb [h][w]    sum of |a| over pairs with |q - tau| <= eta*tau (pairs
- *                     whose inclusion a float32 evaluation of q may flip)
+ *   out_amb [h][w]    sum of |a| over the pairs whose support decision a
+ *                     float32 evaluation of q may flip: |q - tau| <= eta * M
+ *                     with M = A dx^2 + 2|B dx dy| + C dy^2, the magnitude of
+ *                     the terms q sums (rounding error scales with M, not q,
+ *                     because the terms cancel for elongated splats)
  *   out_ambc [h][w]   sum over those pairs of |a| * max_c |rgb_c - C_c|
+ *   out_absden [h][w] |w_B| + sum of |a| over pairs with q <= tau (with den,
+ *                     the conditioning of the normalisation)
  *   out_cnt [h][w]    number of pairs with q <= tau
  * Any output pointer may be NULL.
  */
 void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                 int64_t x0, int64_t y0, int64_t x1, int64_t y1, int32_t mode, double eta,
                 double *out_C, double *out_num, double *out_den, double *out_amb,
-                double *out_ambc, int64_t *out_cnt)
+                double *out_ambc, double *out_absden, int64_t *out_cnt)
 {
     const int64_t w = x1 - x0, h = y1 - y0;
     if (w <= 0 || h <= 0) return;
@@ -437,6 +442,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
     collect_visible(S, cam, P, x0, y0, x1, y1, &v);
     double *num = (double *)calloc(w * h * 3, sizeof(double));
     double *den = (double *)calloc(w * h, sizeof(double));
+    double *aden = (double *)calloc(w * h, sizeof(double));
     int64_t *cnt = (int64_t *)calloc(w * h, sizeof(int64_t));
     const double tau = P->tau;
 
@@ -444,7 +450,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
         #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t yy = 0; yy < h; ++yy)
             for (int64_t xx = 0; xx < w; ++xx) {
-                double nr = 0, ng = 0, nb = 0, dd = 0;
+                double nr = 0, ng = 0, nb = 0, dd = 0, ad = 0;
                 int64_t c = 0;
                 for (int64_t j = 0; j < v.m; ++j) {
                     const proj_t *g = &v.g[j];
@@ -455,12 +461,14 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                         ng += a * g->rgb[1];
                         nb += a * g->rgb[2];
                         dd += a;
+                        ad += fabs(a);
                         ++c;
                     }
                 }
                 const int64_t o = yy * w + xx;
                 num[3 * o] = nr; num[3 * o + 1] = ng; num[3 * o + 2] = nb;
                 den[o] = dd;
+                aden[o] = ad;
                 cnt[o] = c;
             }
     } else {
@@ -482,6 +490,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                         num[3 * o + 1] += a * g->rgb[1];
                         num[3 * o + 2] += a * g->rgb[2];
                         den[o] += a;
+                        aden[o] += fabs(a);
                         cnt[o] += 1;
                     }
                 }
@@ -501,6 +510,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
             if (out_C) out_C[3 * o + c] = Cimg[3 * o + c];
         }
         if (out_den) out_den[o] = D;
+        if (out_absden) out_absden[o] = fabs(P->w_bg) + aden[o];
         if (out_cnt) out_cnt[o] = cnt[o];
     }
 
@@ -514,7 +524,11 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                 for (int64_t j = 0; j < v.m; ++j) {
                     const proj_t *g = &v.g[j];
                     const double q = pair_q(g, x0 + xx, y0 + yy);
-                    if (fabs(q - tau) <= eta * tau) {
+                    const double dx = (double)(x0 + xx) + 0.5 - g->mu[0];
+                    const double dy = (double)(y0 + yy) + 0.5 - g->mu[1];
+                    const double M = g->conic[0] * dx * dx + 2.0 * fabs(g->conic[1] * dx * dy) +
+                                     g->conic[2] * dy * dy;
+                    if (fabs(q - tau) <= eta * M) {
                         const double a = fabs(g->u * g->w * exp(-0.5 * q));
                         double md = 0.0;
                         for (int c = 0; c < 3; ++c) {
@@ -532,6 +546,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
     free(Cimg);
     free(num);
     free(den);
+    free(aden);
     free(cnt);
     free_visible(&v);
 }

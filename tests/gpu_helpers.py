@@ -13,8 +13,8 @@ from paper_2410_18931_amd import WSRContext, globals_tensor, scene_to_device
 
 IMG_TOL = 1e-4      # max-abs on [0, 1] colours
 GRAD_TOL = 1e-3     # per tensor: max |g_gpu - g_ref| <= GRAD_TOL * max |g_ref|
-AMB_ETA = 1e-4      # pairs with |q - tau| <= AMB_ETA * tau may flip in float32
-ILL_DEN = 1e-3      # |den| below this: ill-conditioned pixel, counted not gated
+AMB_ETA = 1e-6      # pairs with |q - tau| <= AMB_ETA * (A dx^2 + 2|B dx dy| + C dy^2) may flip in float32
+ILL_COND = 10.0     # (|w_B| + sum|a|) / |den| above this: ill-conditioned pixel, counted not gated
 
 
 def log(msg: str) -> None:
@@ -38,26 +38,31 @@ def to_views(ctx, t):
 
 def compare_image(C_gpu, ref, tol=IMG_TOL, label=""):
     """Max-abs comparison that accounts for pairs whose support decision is
-    within rounding of the cutoff (the reference reports, per pixel, the sum
-    over such pairs of |a| * max|rgb - C|): those pixels may differ by up to
-    2 * that sum / |den| more.  Returns a dict of statistics."""
+    within float32 rounding of the cutoff (the reference reports, per pixel,
+    the sum over such pairs of |a| * max|rgb - C|): those pixels may differ by
+    up to 2 * that sum / |den| more.  Pixels whose denominator cancels
+    ((|w_B| + sum|a|) / |den| > ILL_COND) are counted, not gated.  Returns a
+    dict of statistics."""
     C_ref, den = ref["C"], ref["den"]
     err = np.abs(C_gpu.astype(np.float64) - C_ref).max(axis=-1)
-    ill = np.abs(den) < ILL_DEN
+    zero = den == 0
+    cond = np.where(zero, 1.0, ref["abs_den"] / np.where(zero, 1.0, np.abs(den)))
+    ill = cond > ILL_COND
     amb = ref["amb_c"] > 0
-    bound = tol + 2.0 * ref["amb_c"] / np.maximum(np.abs(den), ILL_DEN)
+    bound = tol + 2.0 * ref["amb_c"] / np.where(zero, 1.0, np.abs(den))
     clean = ~amb & ~ill
+    ok = ~ill
     st = {
         "max_err_clean": float(err[clean].max()) if clean.any() else 0.0,
-        "max_err_all": float(err[~ill].max()) if (~ill).any() else 0.0,
+        "max_err_all": float(err[ok].max()) if ok.any() else 0.0,
         "ambiguous_px": int(amb.sum()), "ill_px": int(ill.sum()), "px": int(err.size),
-        "over_bound": int((err[~ill] > bound[~ill]).sum()),
+        "over_bound": int((err[ok] > bound[ok]).sum()),
     }
     log(f"[image {label}] {st}")
     assert st["max_err_clean"] <= tol, st
     assert st["over_bound"] == 0, st
     assert st["ill_px"] <= max(2, 0.001 * err.size), st
-    assert st["ambiguous_px"] <= max(20, 0.01 * err.size), st
+    assert st["ambiguous_px"] <= max(20, 0.02 * err.size), st
     return st
 
 
