@@ -232,12 +232,22 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
+// Backward: the same staging and per-wave culling as the forward, but each
+// lane owns one splat of the wave's culled list and walks the wave's pixel
+// block, so a splat's nine gradient sums stay in one lane's registers (no
+// cross-lane reduction).  The waves of a tile merge their per-splat partials
+// with LDS float atomics; each (tile, splat) then issues one global atomic per
+// value.  Per-pixel factors gbar = dL/dC / D and s = gbar . C are staged in LDS
+// and read as wave-uniform broadcasts.
 template <int T>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
+  constexpr int kPix = G::kSub * G::kSub;  // pixels of one wave block
   __shared__ SplatRec s_rec[G::kBatch];
   __shared__ uint32_t s_id[G::kBatch];
   __shared__ uint16_t s_list[G::kWaves * G::kBatch];
+  __shared__ float4 s_pix[G::kWaves][kPix];
+  __shared__ float s_acc[9][G::kBatch];
   __shared__ float s_bg[G::kWaves][4];
   TileCtx<T> c;
   const DevCamera* cam;
@@ -245,75 +255,99 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
 
   const float wbg = a.globals[2];
   const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
-  float gr[G::kPpl], gg[G::kPpl], gb[G::kPpl], sf[G::kPpl];
-  float pcx[G::kPpl], pcy[G::kPpl];
   float bacc[4] = {0.f, 0.f, 0.f, 0.f};  // dL/dc_B (rgb), dL/dw_B
 #pragma unroll
   for (int k = 0; k < G::kPpl; ++k) {
-    gr[k] = gg[k] = gb[k] = sf[k] = 0.f;
-    pcx[k] = static_cast<float>(c.px[k]) + 0.5f;
-    pcy[k] = static_cast<float>(c.py[k]) + 0.5f;
-    if (c.px[k] >= cam->width || c.py[k] >= cam->height) continue;
-    const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py[k]) * cam->width + c.px[k];
-    const float D = a.den[pix];
-    const float g0 = a.dL_drgb[3 * pix], g1 = a.dL_drgb[3 * pix + 1], g2 = a.dL_drgb[3 * pix + 2];
-    if (D != 0.f) {
-      const float iD = 1.f / D;
-      gr[k] = g0 * iD;
-      gg[k] = g1 * iD;
-      gb[k] = g2 * iD;
-      sf[k] = gr[k] * a.rgb[3 * pix] + gg[k] * a.rgb[3 * pix + 1] + gb[k] * a.rgb[3 * pix + 2];
-      bacc[0] += wbg * gr[k];
-      bacc[1] += wbg * gg[k];
-      bacc[2] += wbg * gb[k];
-      bacc[3] += gr[k] * bgr + gg[k] * bgg + gb[k] * bgb - sf[k];
-    } else {
-      // C is the background colour where the denominator vanishes
-      bacc[0] += g0;
-      bacc[1] += g1;
-      bacc[2] += g2;
+    float4 pd = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c.px[k] < cam->width && c.py[k] < cam->height) {
+      const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py[k]) * cam->width + c.px[k];
+      const float D = a.den[pix];
+      const float g0 = a.dL_drgb[3 * pix], g1 = a.dL_drgb[3 * pix + 1], g2 = a.dL_drgb[3 * pix + 2];
+      if (D != 0.f) {
+        const float iD = 1.f / D;
+        pd.x = g0 * iD;
+        pd.y = g1 * iD;
+        pd.z = g2 * iD;
+        pd.w = pd.x * a.rgb[3 * pix] + pd.y * a.rgb[3 * pix + 1] + pd.z * a.rgb[3 * pix + 2];
+        bacc[0] += wbg * pd.x;
+        bacc[1] += wbg * pd.y;
+        bacc[2] += wbg * pd.z;
+        bacc[3] += pd.x * bgr + pd.y * bgg + pd.z * bgb - pd.w;
+      } else {
+        // C is the background colour where the denominator vanishes
+        bacc[0] += g0;
+        bacc[1] += g1;
+        bacc[2] += g2;
+      }
     }
+    s_pix[c.wave][(c.py[k] - c.by0) * G::kSub + (c.px[k] - c.bx0)] = pd;
   }
+  for (int k = threadIdx.x; k < 9 * G::kBatch; k += G::kThreads) (&s_acc[0][0])[k] = 0.f;
+
   const float tau = a.tau;
+  const float4* pixw = s_pix[c.wave];
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
     const int m = stage_and_cull<T>(a, c, b, s_rec, s_id, s_list);
     const uint16_t* list = s_list + c.wave * G::kBatch;
-    for (int i = 0; i < m; ++i) {
-      const int k_rec = list[i];
-      const SplatRec r = s_rec[k_rec];
-      float g9[9];
-#pragma unroll
-      for (int j = 0; j < 9; ++j) g9[j] = 0.f;
-      bool any = false;
-#pragma unroll
-      for (int k = 0; k < G::kPpl; ++k) {
+    for (int c0 = 0; c0 < m; c0 += kWave) {
+      const int j = c0 + c.lane;
+      const bool valid = j < m;
+      const int kr = valid ? list[j] : 0;
+      const SplatRec r = s_rec[kr];
+      const float amp = r.r1.w, cr = r.r2.x, cg = r.r2.y, cb = r.r2.z;
+      float g_mx = 0.f, g_my = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
+#pragma unroll 4
+      for (int p = 0; p < kPix; ++p) {
+        const float pcx = static_cast<float>(c.bx0 + (p % G::kSub)) + 0.5f;
+        const float pcy = static_cast<float>(c.by0 + (p / G::kSub)) + 0.5f;
         float dx, dy;
-        const float q = pair_q(r, pcx[k], pcy[k], &dx, &dy);
-        if (q <= tau) {
-          any = true;
+        const float q = pair_q(r, pcx, pcy, &dx, &dy);
+        if (valid && q <= tau) {
+          const float4 pd = pixw[p];
           const float Gq = falloff(q);
-          const float al = r.r1.w * Gq;
-          const float dLda = gr[k] * r.r2.x + gg[k] * r.r2.y + gb[k] * r.r2.z - sf[k];
+          const float al = amp * Gq;
+          const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
           const float dq = -0.5f * al * dLda;
           // q = A dx^2 + B2 dx dy + C dy^2 with dx = px - mu_x
-          g9[0] -= dq * fmaf(2.f * r.r0.z, dx, r.r0.w * dy);
-          g9[1] -= dq * fmaf(2.f * r.r1.x, dy, r.r0.w * dx);
-          g9[2] = fmaf(dq, dx * dx, g9[2]);
-          g9[3] = fmaf(dq, 2.f * dx * dy, g9[3]);
-          g9[4] = fmaf(dq, dy * dy, g9[4]);
-          g9[5] = fmaf(al, gr[k], g9[5]);
-          g9[6] = fmaf(al, gg[k], g9[6]);
-          g9[7] = fmaf(al, gb[k], g9[7]);
-          g9[8] = fmaf(dLda, Gq, g9[8]);
+          g_mx -= dq * fmaf(2.f * r.r0.z, dx, r.r0.w * dy);
+          g_my -= dq * fmaf(2.f * r.r1.x, dy, r.r0.w * dx);
+          gA = fmaf(dq, dx * dx, gA);
+          gB = fmaf(dq, 2.f * dx * dy, gB);
+          gC = fmaf(dq, dy * dy, gC);
+          g_r = fmaf(al, pd.x, g_r);
+          g_g = fmaf(al, pd.y, g_g);
+          g_b = fmaf(al, pd.z, g_b);
+          g_amp = fmaf(dLda, Gq, g_amp);
         }
       }
-      if (__ballot(any) == 0ull) continue;
+      if (valid) {
+        atomicAdd(&s_acc[0][kr], g_mx);
+        atomicAdd(&s_acc[1][kr], g_my);
+        atomicAdd(&s_acc[2][kr], gA);
+        atomicAdd(&s_acc[3][kr], gB);
+        atomicAdd(&s_acc[4][kr], gC);
+        atomicAdd(&s_acc[5][kr], g_r);
+        atomicAdd(&s_acc[6][kr], g_g);
+        atomicAdd(&s_acc[7][kr], g_b);
+        atomicAdd(&s_acc[8][kr], g_amp);
+      }
+    }
+    __syncthreads();
+    const int cnt = static_cast<int>(min(static_cast<uint32_t>(G::kBatch), c.end - b));
+    for (int k = threadIdx.x; k < cnt; k += G::kThreads) {
+      float v9[9];
+      bool nz = false;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) g9[j] = wave_sum(g9[j]);
-      if (c.lane == 0) {
-        float* dst = a.grad2d + (static_cast<int64_t>(c.v) * c.n + s_id[k_rec]) * 9;
+      for (int j = 0; j < 9; ++j) {
+        v9[j] = s_acc[j][k];
+        s_acc[j][k] = 0.f;
+        nz |= v9[j] != 0.f;
+      }
+      if (nz) {
+        float* dst = a.grad2d + (static_cast<int64_t>(c.v) * c.n + s_id[k]) * 9;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) unsafeAtomicAdd(dst + j, g9[j]);
+        for (int j = 0; j < 9; ++j)
+          if (v9[j] != 0.f) unsafeAtomicAdd(dst + j, v9[j]);
       }
     }
   }

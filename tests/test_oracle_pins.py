@@ -170,9 +170,10 @@ def test_view_direction_points_from_camera_to_gaussian():
     sc = scene_from(means, sh=sh)
     p = oracle.project(sc, cam, ws.Settings(opacity_mode="logit"))
     d = (means - cpos) / np.linalg.norm(means - cpos, axis=1, keepdims=True)
-    np.testing.assert_allclose(p["dir"], d, atol=1e-14)
+    # the camera is float32 (its centre is exact only to ~1e-7)
+    np.testing.assert_allclose(p["dir"], d, atol=1e-6)
     k1 = math.sqrt(3 / (4 * math.pi))
-    np.testing.assert_allclose(p["rgb_raw"][:, 0], 0.5 + k1 * d[:, 0], atol=1e-14)
+    np.testing.assert_allclose(p["rgb_raw"][:, 0], 0.5 + k1 * p["dir"][:, 0], atol=1e-14)
 
 
 def test_near_plane_and_degenerate_culling():

@@ -56,9 +56,12 @@ def look_at_camera(position, width: int, height: int, fov_y_deg: float = 60.0,
     rot = np.stack([r, d, f])  # rows: camera x (right), y (down), z (forward)
     trans = -rot @ c
     fy = 0.5 * height / math.tan(math.radians(fov_y_deg) * 0.5)
+    # the renderer's camera is float32: hand out exactly representable values
+    # so that every consumer sees the same camera
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
     return {
-        "viewmat": np.concatenate([rot, trans[:, None]], axis=1),
-        "fx": fy, "fy": fy, "cx": 0.5 * width, "cy": 0.5 * height,
+        "viewmat": np.concatenate([rot, trans[:, None]], axis=1).astype(np.float32).astype(np.float64),
+        "fx": f32(fy), "fy": f32(fy), "cx": f32(0.5 * width), "cy": f32(0.5 * height),
         "width": int(width), "height": int(height),
     }
 
