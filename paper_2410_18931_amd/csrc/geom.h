@@ -63,8 +63,8 @@ __device__ inline void sym_mul(const Sigma3& S, const double v[3], double o[3]) 
 }
 
 // Returns true iff the pair is visible (in front of the near plane, positive
-// definite Sigma2D, centre within +-2^23 px so that it has an exact integer
-// origin in float32).
+// definite Sigma2D, centre within +-2^22 px so that pixel offsets from its integer
+// origin are exact half-integers in float32).
 __device__ inline bool view_geom(const DevCamera& cam, double p0, double p1, double p2, const Sigma3& S,
                                  bool q_ok, float near_z, float dilation, ViewGeom* g) {
 #pragma unroll
@@ -102,7 +102,7 @@ __device__ inline bool view_geom(const DevCamera& cam, double p0, double p1, dou
   g->C = g->c00 * id;
   g->mux = fx * g->tx * g->izt + cam.cx;
   g->muy = fy * g->ty * g->izt + cam.cy;
-  return fabs(g->mux) < 8388608.0 && fabs(g->muy) < 8388608.0;
+  return fabs(g->mux) < 4194304.0 && fabs(g->muy) < 4194304.0;
 }
 
 // Unit direction from the camera centre (-W^T T) to p.

@@ -28,19 +28,26 @@ struct TileGeom {
   static constexpr int kBatch = kThreads;              // records per LDS batch
 };
 
-// The support predicate and the Gaussian falloff.  Forward and backward call
-// exactly this code, so they take the same support decision for every pair,
-// whatever the tile size.
-__device__ __forceinline__ float pair_q(const SplatRec& r, float pcx, float pcy, float* dx_o, float* dy_o) {
-  const float dx = (pcx - r.r1.y) - r.r0.x;   // first difference is exact
-  const float dy = (pcy - r.r1.z) - r.r0.y;
-  const float t = fmaf(r.r0.z, dx, r.r0.w * dy);
-  *dx_o = dx;
-  *dy_o = dy;
-  return fmaf(t, dx, (r.r1.x * dy) * dy);
+// The support predicate and the Gaussian falloff.  Forward and backward
+// evaluate q with exactly this sequence of float operations (the backward
+// hoists the row-constant products B2*dy and (C*dy)*dy, which does not change
+// their values), so both take the same support decision for every pair,
+// whatever the tile size.  dx is formed as (pixel centre - integer origin)
+// - fractional centre; the first difference is exact.
+__device__ __forceinline__ float quad_form(float A, float B2dy, float Cdy2, float dx) {
+  return fmaf(fmaf(A, dx, B2dy), dx, Cdy2);
 }
 
-__device__ __forceinline__ float falloff(float q) { return __expf(-0.5f * q); }
+__device__ __forceinline__ float pair_q(const SplatRec& r, float pcx, float pcy, float* dx_o, float* dy_o) {
+  const float dx = (pcx - r.r1.y) - r.r0.x;
+  const float dy = (pcy - r.r1.z) - r.r0.y;
+  *dx_o = dx;
+  *dy_o = dy;
+  return quad_form(r.r0.z, r.r0.w * dy, (r.r1.x * dy) * dy, dx);
+}
+
+// exp(-q/2) as one hardware exp2 of q * (-log2(e) / 2)
+__device__ __forceinline__ float falloff(float q) { return __builtin_amdgcn_exp2f(q * -0.72134752044448170f); }
 
 __device__ __forceinline__ float2 rec_extent(const SplatRec& r) {
   const uint32_t e = __float_as_uint(r.r2.w);
@@ -49,14 +56,41 @@ __device__ __forceinline__ float2 rec_extent(const SplatRec& r) {
   return make_float2(static_cast<float>(ex), static_cast<float>(ey));
 }
 
-// Does the splat's support box reach the wave block whose first pixel centre
-// is (bx, by) and whose last is (bx + sub - 1, by + sub - 1)?
-__device__ __forceinline__ bool box_hits(const SplatRec& r, float bx, float by, float sub1) {
+// Does the splat's support reach the wave block whose pixel centres span
+// [bx, bx + sub1] x [by, by + sub1]?  First the (conservative) support box;
+// then, unless the conic is badly conditioned, the exact minimum of q over
+// the block (the unconstrained minimum is the centre; otherwise the minimum
+// lies on an edge, at the clamped 1D minimiser of that edge) against tau with
+// a margin far above the float error of q.  For needle-like splats
+// (eigenvalue ratio above ~100) float q loses digits to cancellation, so the
+// box decision is kept.
+__device__ __forceinline__ bool block_hits(const SplatRec& r, float bx, float by, float sub1, float tau) {
   const float2 e = rec_extent(r);
-  const float mx = r.r1.y + r.r0.x, my = r.r1.z + r.r0.y;
+  const float ox = r.r1.y, oy = r.r1.z, fx = r.r0.x, fy = r.r0.y;
+  const float mx = ox + fx, my = oy + fy;
   const float sx = 1e-3f * fabsf(mx) + 1e-2f, sy = 1e-3f * fabsf(my) + 1e-2f;  // rounding slack
-  return (mx + e.x + sx >= bx) && (mx - e.x - sx <= bx + sub1) &&
-         (my + e.y + sy >= by) && (my - e.y - sy <= by + sub1);
+  if (!((mx + e.x + sx >= bx) && (mx - e.x - sx <= bx + sub1) && (my + e.y + sy >= by) &&
+        (my - e.y - sy <= by + sub1)))
+    return false;
+  const float A = r.r0.z, B = 0.5f * r.r0.w, C = r.r1.x;
+  const float tr = A + C, det = A * C - B * B;
+  if (!(tr * tr <= 102.f * det)) return true;
+  // block corners relative to the centre; (corner - origin) is exact
+  const float x0 = (bx - ox) - fx, x1 = (bx + sub1 - ox) - fx;
+  const float y0 = (by - oy) - fy, y1 = (by + sub1 - oy) - fy;
+  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
+  const float iA = 1.f / A, iC = 1.f / C;
+  float qmin = 3.0e38f;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float dy = k ? y1 : y0;
+    const float dx = fminf(fmaxf(-B * dy * iA, x0), x1);
+    qmin = fminf(qmin, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
+    const float ex2 = k ? x1 : x0;
+    const float ey2 = fminf(fmaxf(-B * ex2 * iC, y0), y1);
+    qmin = fminf(qmin, A * ex2 * ex2 + 2.f * B * ex2 * ey2 + C * ey2 * ey2);
+  }
+  return qmin <= tau * 1.002f + 1e-3f;
 }
 
 struct RasterArgs {
@@ -149,7 +183,7 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
   const float bx = c.bx0 + 0.5f, by = c.by0 + 0.5f;
   for (int k0 = 0; k0 < cnt; k0 += kWave) {
     const int k = k0 + c.lane;
-    const bool hit = k < cnt && box_hits(s_rec[k], bx, by, static_cast<float>(G::kSub - 1));
+    const bool hit = k < cnt && block_hits(s_rec[k], bx, by, static_cast<float>(G::kSub - 1), a.tau);
     const uint64_t mask = __ballot(hit);
     if (hit) {
       const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
@@ -296,30 +330,40 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
       const SplatRec r = s_rec[kr];
       const float amp = r.r1.w, cr = r.r2.x, cg = r.r2.y, cb = r.r2.z;
       float g_mx = 0.f, g_my = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
-#pragma unroll 4
-      for (int p = 0; p < kPix; ++p) {
-        const float pcx = static_cast<float>(c.bx0 + (p % G::kSub)) + 0.5f;
-        const float pcy = static_cast<float>(c.by0 + (p / G::kSub)) + 0.5f;
-        float dx, dy;
-        const float q = pair_q(r, pcx, pcy, &dx, &dy);
-        if (valid && q <= tau) {
-          const float4 pd = pixw[p];
-          const float Gq = falloff(q);
-          const float al = amp * Gq;
-          const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
-          const float dq = -0.5f * al * dLda;
-          // q = A dx^2 + B2 dx dy + C dy^2 with dx = px - mu_x
-          g_mx -= dq * fmaf(2.f * r.r0.z, dx, r.r0.w * dy);
-          g_my -= dq * fmaf(2.f * r.r1.x, dy, r.r0.w * dx);
-          gA = fmaf(dq, dx * dx, gA);
-          gB = fmaf(dq, 2.f * dx * dy, gB);
-          gC = fmaf(dq, dy * dy, gC);
-          g_r = fmaf(al, pd.x, g_r);
-          g_g = fmaf(al, pd.y, g_g);
-          g_b = fmaf(al, pd.z, g_b);
-          g_amp = fmaf(dLda, Gq, g_amp);
+      const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
+      // first pixel centre of the block relative to the splat's integer
+      // origin (exact), so dx = (ex0 + col) - fx matches the forward's
+      const float ex0 = (static_cast<float>(c.bx0) + 0.5f) - r.r1.y;
+      const float ey0 = (static_cast<float>(c.by0) + 0.5f) - r.r1.z;
+      for (int row = 0; row < G::kSub; ++row) {
+        const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
+        const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
+        const float4* prow = pixw + row * G::kSub;
+#pragma unroll
+        for (int col = 0; col < G::kSub; ++col) {
+          const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
+          const float q = quad_form(A, B2dy, Cdy2, dx);
+          if (valid && q <= tau) {
+            const float4 pd = prow[col];
+            const float Gq = falloff(q);
+            const float al = amp * Gq;
+            const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
+            const float dq = -0.5f * al * dLda;
+            // q = A dx^2 + B2 dx dy + C dy^2 with dx = px - mu_x
+            g_mx = fmaf(dq, fmaf(2.f * A, dx, B2dy), g_mx);
+            g_my = fmaf(dq, fmaf(B2, dx, 2.f * Cc * dy), g_my);
+            gA = fmaf(dq, dx * dx, gA);
+            gB = fmaf(dq, 2.f * dx * dy, gB);
+            gC = fmaf(dq, dy * dy, gC);
+            g_r = fmaf(al, pd.x, g_r);
+            g_g = fmaf(al, pd.y, g_g);
+            g_b = fmaf(al, pd.z, g_b);
+            g_amp = fmaf(dLda, Gq, g_amp);
+          }
         }
       }
+      g_mx = -g_mx;
+      g_my = -g_my;
       if (valid) {
         atomicAdd(&s_acc[0][kr], g_mx);
         atomicAdd(&s_acc[1][kr], g_my);
