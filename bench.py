@@ -137,21 +137,22 @@ def main():
         if ev:
             ev[1].record(stream)
         _lib.check("wsr_bin", lib.wsr_bin(ctx.cams_c, ctx.nv, C.byref(ctx.params), n, wsp, ctx.ws_bytes,
-                                          ptr(ctx.ids), ctx.capacity, sp))
+                                          ptr(ctx.pairs), ctx.capacity, sp))
         if ev:
             ev[2].record(stream)
         _lib.check("wsr_render_fwd", lib.wsr_render_fwd(ctx.cams_c, ctx.nv, C.byref(ctx.params), n, ptr(g), wsp,
-                                                        ctx.ws_bytes, ptr(ctx.ids), ctx.capacity, ptr(rgb),
+                                                        ctx.ws_bytes, ptr(ctx.pairs), ctx.capacity, ptr(rgb),
                                                         ptr(den), None, sp))
         if ev:
             ev[3].record(stream)
         _lib.check("wsr_raster_bwd", lib.wsr_raster_bwd(ctx.cams_c, ctx.nv, C.byref(ctx.params), n, ptr(g), wsp,
-                                                        ctx.ws_bytes, ptr(ctx.ids), ctx.capacity, ptr(dL),
+                                                        ctx.ws_bytes, ptr(ctx.pairs), ctx.capacity, ptr(dL),
                                                         ptr(rgb), ptr(den), sp))
         if ev:
             ev[4].record(stream)
         _lib.check("wsr_project_bwd", lib.wsr_project_bwd(C.byref(sc), ctx.cams_c, ctx.nv, C.byref(ctx.params),
-                                                          ptr(g), wsp, ctx.ws_bytes, C.byref(gs), None, sp))
+                                                          ptr(g), wsp, ctx.ws_bytes, ptr(ctx.pairs), ctx.capacity,
+                                                          C.byref(gs), None, sp))
         if ev:
             ev[5].record(stream)
 

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define WSR_ABI_VERSION 1
+#define WSR_ABI_VERSION 2
 #define WSR_MAX_VIEWS 256
 
 typedef enum {
@@ -126,7 +126,7 @@ int32_t wsr_abi_version(void);
 const char* wsr_status_string(int32_t status);
 
 /* Bytes of the workspace needed for n Gaussians over the given views and
- * tile size (does not include the per-tile id list, see wsr_bin).
+ * tile size (does not include the per-pair buffer, see wsr_bin).
  * Returns -1 on invalid arguments. */
 int64_t wsr_workspace_bytes(int64_t n, const wsr_camera* cams, int32_t n_views, int32_t tile);
 
@@ -140,19 +140,26 @@ int32_t wsr_project(const wsr_scene* scene, const wsr_camera* cams, int32_t n_vi
                     const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
                     float* out_proj, void* stream);
 
+/* Bytes per entry of the pair buffer (see wsr_bin). */
+int64_t wsr_pair_bytes(void);
+
 /* Step a6 (Sec. 4.1): build per-tile lists of Gaussian ids for every view,
  * with no depth key (Eq. 7 is a commutative sum, so order is irrelevant).
- * ids is a DEVICE uint32 array of `capacity` entries.  If the number of
- * (tile, Gaussian) pairs exceeds capacity the overflow flag is set. */
+ * `pairs` is a DEVICE buffer of capacity * wsr_pair_bytes() bytes, aligned
+ * to 256 bytes, that holds one entry per (tile, Gaussian) pair: the id lists
+ * and the per-pair scratch of the backward.  It is owned by the caller and
+ * must be passed unchanged to the later steps of the same frame.  If the
+ * number of pairs exceeds capacity the overflow flag is set (wsr_check,
+ * wsr_pair_count give the needed capacity). */
 int32_t wsr_bin(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
-                void* ws, int64_t ws_bytes, uint32_t* ids, int64_t capacity, void* stream);
+                void* ws, int64_t ws_bytes, void* pairs, int64_t capacity, void* stream);
 
 /* Step a7 (Eq. 7): per-pixel FP32 sums and normalisation with the weighted
  * background.  out_rgb: concatenated [H][W][3]; out_den: concatenated
  * [H][W] (w_B + sum a_i); out_count (nullable, int32 [H][W]): the number of
  * in-support pairs per pixel. */
 int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
-                       const float* globals, const void* ws, int64_t ws_bytes, const uint32_t* ids,
+                       const float* globals, void* ws, int64_t ws_bytes, const void* pairs,
                        int64_t capacity, float* out_rgb, float* out_den, int32_t* out_count,
                        void* stream);
 
@@ -162,25 +169,28 @@ int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params
  * grads (they are overwritten, not accumulated).  out_grad2d (nullable,
  * DEVICE [n_views][n][9]) receives the per-(view, Gaussian) gradient with
  * respect to (mu_x, mu_y, A, B, C, r, g, b, a) where (A, B, C) is the conic
- * (q = A dx^2 + 2B dx dy + C dy^2) and a = u w the amplitude. */
+ * (q = A dx^2 + 2B dx dy + C dy^2) and a = u w the amplitude.  No atomics:
+ * the result is bitwise reproducible for a given binning. */
 int32_t wsr_render_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views,
                        const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
-                       const uint32_t* ids, int64_t capacity, const float* dL_drgb, const float* rgb,
+                       void* pairs, int64_t capacity, const float* dL_drgb, const float* rgb,
                        const float* den, const wsr_grads* grads, float* out_grad2d, void* stream);
 
 /* The two halves of wsr_render_bwd, for callers that schedule or time them
  * separately; wsr_render_bwd is exactly wsr_raster_bwd then wsr_project_bwd.
- * wsr_raster_bwd (step a8, Eq. 7 differentiated) leaves the per-(view,
- * Gaussian) 2D gradients and per-tile background partial sums in the
- * workspace; wsr_project_bwd (step a9) chains them to the scene parameters
- * (Eqs. 3-11 differentiated) and writes `grads`. */
+ * wsr_raster_bwd (step a8, Eq. 7 differentiated) leaves one partial 2D
+ * gradient per (tile, Gaussian) pair in `pairs` and per-tile background
+ * partial sums in the workspace; wsr_project_bwd (step a9) sums each
+ * Gaussian's partials and chains them to the scene parameters (Eqs. 3-11
+ * differentiated), writing `grads`. */
 int32_t wsr_raster_bwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
-                       const float* globals, void* ws, int64_t ws_bytes, const uint32_t* ids,
+                       const float* globals, void* ws, int64_t ws_bytes, void* pairs,
                        int64_t capacity, const float* dL_drgb, const float* rgb, const float* den,
                        void* stream);
 int32_t wsr_project_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views,
                         const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
-                        const wsr_grads* grads, float* out_grad2d, void* stream);
+                        const void* pairs, int64_t capacity, const wsr_grads* grads,
+                        float* out_grad2d, void* stream);
 
 /* Synchronises `stream` and returns, in *out_total, the number of
  * (tile, Gaussian) pairs the last wsr_bin on this workspace produced (the

@@ -16,9 +16,9 @@ WEIGHT_KINDS = {"dir": 0, "exp": 1, "lc": 2}
 OPACITY_MODES = {"logit": 0, "sh": 1}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 MAX_VIEWS = 256
-ABI_VERSION = 1
+ABI_VERSION = 2
 
-EXPORTED = ("wsr_abi_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_project", "wsr_bin",
+EXPORTED = ("wsr_abi_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_pair_bytes", "wsr_project", "wsr_bin",
             "wsr_render_fwd", "wsr_render_bwd", "wsr_raster_bwd", "wsr_project_bwd", "wsr_pair_count",
             "wsr_check")
 
@@ -69,6 +69,7 @@ def load():
     lib.wsr_status_string.argtypes = [I32]
     lib.wsr_workspace_bytes.restype = I64
     lib.wsr_workspace_bytes.argtypes = [I64, P, I32, I32]
+    lib.wsr_pair_bytes.restype = I64
     lib.wsr_project.restype = I32
     lib.wsr_project.argtypes = [P, P, I32, P, P, P, I64, P, P]
     lib.wsr_bin.restype = I32
@@ -80,7 +81,7 @@ def load():
     lib.wsr_raster_bwd.restype = I32
     lib.wsr_raster_bwd.argtypes = [P, I32, P, I64, P, P, I64, P, I64, P, P, P, P]
     lib.wsr_project_bwd.restype = I32
-    lib.wsr_project_bwd.argtypes = [P, P, I32, P, P, P, I64, P, P, P]
+    lib.wsr_project_bwd.argtypes = [P, P, I32, P, P, P, I64, P, I64, P, P, P]
     lib.wsr_pair_count.restype = I32
     lib.wsr_pair_count.argtypes = [P, I64, C.POINTER(C.c_int64), P]
     lib.wsr_check.restype = I32

@@ -56,7 +56,10 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   L->total_tiles = tiles;
   L->total_pixels = pixels;
   L->hist_len = hist;
-  L->scan_parts = (hist + 1 + kScanItems - 1) / kScanItems;
+  {
+    const int64_t longest = hist + 1 > n * nv + 1 ? hist + 1 : n * nv + 1;
+    L->scan_parts = (longest + kScanItems - 1) / kScanItems;
+  }
   L->gpart_blocks = project_bwd_blocks(n);
   const int64_t slots = n * nv;
   size_t off = 0;
@@ -66,9 +69,12 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   L->off_rect = off;     off = align256(off + sizeof(uint2) * slots);
   L->off_hist = off;     off = align256(off + sizeof(uint32_t) * (hist + 1));
   L->off_scan = off;     off = align256(off + sizeof(uint32_t) * L->scan_parts);
+  L->off_goff = off;     off = align256(off + sizeof(uint32_t) * (slots + 1));
   L->off_grad2d = off;   off = align256(off + sizeof(float) * 9 * slots);
   L->off_tilepart = off; off = align256(off + sizeof(float) * 4 * tiles);
   L->off_gpart = off;    off = align256(off + sizeof(double) * 2 * L->gpart_blocks);
+  L->off_items = off;    off = align256(off + sizeof(uint32_t) * (tiles + 1));
+  L->off_acc = off;      off = align256(off + sizeof(float) * 4 * pixels);
   L->bytes = off;
   return true;
 }
@@ -132,64 +138,72 @@ int32_t wsr_project(const wsr_scene* scene, const wsr_camera* cams, int32_t n_vi
   return to_status(e);
 }
 
+int64_t wsr_pair_bytes(void) { return kPairBytes; }
+
+static bool pairs_ok(const void* pairs, int64_t capacity) {
+  return capacity >= 0 && capacity <= 0xffffffffLL &&
+         (capacity == 0 || (pairs && (reinterpret_cast<uintptr_t>(pairs) & 255u) == 0));
+}
+
 int32_t wsr_bin(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n, void* ws,
-                int64_t ws_bytes, uint32_t* ids, int64_t capacity, void* stream) {
-  if (!params_ok(params) || !ws || capacity < 0 || (capacity > 0 && !ids)) return WSR_ERR_INVALID;
+                int64_t ws_bytes, void* pairs, int64_t capacity, void* stream) {
+  if (!params_ok(params) || !ws || !pairs_ok(pairs, capacity)) return WSR_ERR_INVALID;
   Layout L;
   if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
   if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
-  return to_status(launch_bin(L, ws, ids, capacity, static_cast<hipStream_t>(stream)));
+  return to_status(launch_bin(L, ws, pairs, capacity, static_cast<hipStream_t>(stream)));
 }
 
 int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
-                       const float* globals, const void* ws, int64_t ws_bytes, const uint32_t* ids,
+                       const float* globals, void* ws, int64_t ws_bytes, const void* pairs,
                        int64_t capacity, float* out_rgb, float* out_den, int32_t* out_count, void* stream) {
-  if (!params_ok(params) || !globals || !ws || !out_rgb || !out_den || capacity < 0 || (capacity > 0 && !ids))
+  if (!params_ok(params) || !globals || !ws || !out_rgb || !out_den || !pairs_ok(pairs, capacity))
     return WSR_ERR_INVALID;
   Layout L;
   if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
   if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
-  return to_status(launch_raster_fwd(L, ws, ids, capacity, params, globals, out_rgb, out_den, out_count,
+  return to_status(launch_raster_fwd(L, ws, pairs, capacity, params, globals, out_rgb, out_den, out_count,
                                      static_cast<hipStream_t>(stream)));
 }
 
 int32_t wsr_raster_bwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
-                       const float* globals, void* ws, int64_t ws_bytes, const uint32_t* ids, int64_t capacity,
+                       const float* globals, void* ws, int64_t ws_bytes, void* pairs, int64_t capacity,
                        const float* dL_drgb, const float* rgb, const float* den, void* stream) {
-  if (!params_ok(params) || !globals || !ws || !dL_drgb || !rgb || !den || capacity < 0 || (capacity > 0 && !ids))
+  if (!params_ok(params) || !globals || !ws || !dL_drgb || !rgb || !den || !pairs_ok(pairs, capacity))
     return WSR_ERR_INVALID;
   Layout L;
   if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
   if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_fill_zero(at<float>(ws, L.off_grad2d), sizeof(float) * 9 * L.n * L.nv, st);
-  if (e == hipSuccess) e = launch_raster_bwd(L, ws, ids, capacity, params, globals, dL_drgb, rgb, den, st);
-  return to_status(e);
+  return to_status(launch_raster_bwd(L, ws, pairs, capacity, params, globals, dL_drgb, rgb, den,
+                                     static_cast<hipStream_t>(stream)));
 }
 
 int32_t wsr_project_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views, const wsr_params* params,
-                        const float* globals, void* ws, int64_t ws_bytes, const wsr_grads* grads, float* out_grad2d,
-                        void* stream) {
-  if (!params_ok(params) || !scene_ok(scene, params->weight_kind) || !globals || !ws || !grads || !grads->globals)
+                        const float* globals, void* ws, int64_t ws_bytes, const void* pairs, int64_t capacity,
+                        const wsr_grads* grads, float* out_grad2d, void* stream) {
+  if (!params_ok(params) || !scene_ok(scene, params->weight_kind) || !globals || !ws || !grads || !grads->globals ||
+      !pairs_ok(pairs, capacity))
     return WSR_ERR_INVALID;
   if (scene->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->sh)) return WSR_ERR_INVALID;
   Layout L;
   if (!make_layout(scene->n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
   if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
-  return to_status(launch_project_bwd(scene, params, globals, L, ws, grads, out_grad2d, static_cast<hipStream_t>(stream)));
+  return to_status(launch_project_bwd(scene, params, globals, L, ws, pairs, capacity, grads, out_grad2d,
+                                      static_cast<hipStream_t>(stream)));
 }
 
 int32_t wsr_render_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views, const wsr_params* params,
-                       const float* globals, void* ws, int64_t ws_bytes, const uint32_t* ids, int64_t capacity,
+                       const float* globals, void* ws, int64_t ws_bytes, void* pairs, int64_t capacity,
                        const float* dL_drgb, const float* rgb, const float* den, const wsr_grads* grads,
                        float* out_grad2d, void* stream) {
   if (!params_ok(params) || !scene_ok(scene, params->weight_kind) || !grads || !grads->globals)
     return WSR_ERR_INVALID;
   if (scene->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->sh)) return WSR_ERR_INVALID;
-  const int32_t s = wsr_raster_bwd(cams, n_views, params, scene->n, globals, ws, ws_bytes, ids, capacity, dL_drgb,
-                                   rgb, den, stream);
+  const int32_t s = wsr_raster_bwd(cams, n_views, params, scene->n, globals, ws, ws_bytes, pairs, capacity,
+                                   dL_drgb, rgb, den, stream);
   if (s != WSR_OK) return s;
-  return wsr_project_bwd(scene, cams, n_views, params, globals, ws, ws_bytes, grads, out_grad2d, stream);
+  return wsr_project_bwd(scene, cams, n_views, params, globals, ws, ws_bytes, pairs, capacity, grads, out_grad2d,
+                         stream);
 }
 
 int32_t wsr_pair_count(const void* ws, int64_t ws_bytes, int64_t* out_total, void* stream) {

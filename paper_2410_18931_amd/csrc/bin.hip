@@ -51,7 +51,9 @@ struct BinArgs {
   const DevCamera* cams;
   const uint2* rect;
   uint32_t* hist;
+  const uint32_t* goff;   // Gaussian-major pair offsets per (view, Gaussian)
   uint32_t* ids;
+  uint32_t* slot;
   int64_t n;
   int64_t capacity;
   int32_t nblk;
@@ -63,7 +65,7 @@ template <bool SCATTER>
 __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t s_off[kBinThreads + 1];
-  __shared__ uint32_t s_x0[kBinThreads], s_w[kBinThreads], s_y0[kBinThreads];
+  __shared__ uint32_t s_x0[kBinThreads], s_w[kBinThreads], s_y0[kBinThreads], s_goff[kBinThreads];
   __shared__ uint32_t s_scan[4];
 
   const int b = blockIdx.x, z = blockIdx.y, v = blockIdx.z;
@@ -103,6 +105,14 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
     s_x0[threadIdx.x] = x0;
     s_w[threadIdx.x] = w;
     s_y0[threadIdx.x] = y0;
+    // first Gaussian-major slot of this Gaussian's pairs in this chunk: its
+    // pairs are enumerated row by row over its rectangle, so the rows of the
+    // chunk start after (yl - y0_rect) * w of them
+    if (SCATTER && i < g1) {
+      const uint2 r = rect[i];
+      const uint32_t yr = r.y & 0xffffu;
+      s_goff[threadIdx.x] = a.goff[static_cast<int64_t>(v) * a.n + i] + (y0 > yr ? (y0 - yr) * w : 0u);
+    }
     __syncthreads();
     for (uint32_t p = threadIdx.x; p < total; p += kBinThreads) {
       // largest g with s_off[g] <= p (it has a non-zero count)
@@ -120,7 +130,10 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
         atomicAdd(&lds[t], 1u);
       } else {
         const uint32_t pos = atomicAdd(&lds[t], 1u);
-        if (pos < a.capacity) a.ids[pos] = static_cast<uint32_t>(base + lo);
+        if (pos < a.capacity) {
+          a.ids[pos] = static_cast<uint32_t>(base + lo);
+          a.slot[pos] = s_goff[lo] + local;
+        }
       }
     }
     __syncthreads();
@@ -171,7 +184,7 @@ __global__ __launch_bounds__(1024) void scan_parts(uint32_t* parts, int64_t npar
     carry += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && flags) {
     flags->total_pairs = carry;
     flags->wrapped = carry > 0xffffffffull ? 1u : 0u;
     flags->overflow = (carry > static_cast<uint64_t>(capacity) || carry > 0xffffffffull) ? 1u : 0u;
@@ -197,19 +210,63 @@ __global__ __launch_bounds__(256) void scan_apply(uint32_t* x, int64_t len, cons
   }
 }
 
+// Number of (tile, Gaussian) pairs of every (view, Gaussian) slot, the
+// input of the scan that gives each Gaussian a contiguous range of
+// Gaussian-major pair slots (the raster backward writes a partial gradient
+// per pair there; the projection backward sums the range).
+__global__ __launch_bounds__(256) void gauss_counts(const uint2* rect, int64_t slots, uint32_t* goff) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (k > slots) return;
+  if (k == slots) {
+    goff[k] = 0u;
+    return;
+  }
+  const uint2 r = rect[k];
+  const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
+  goff[k] = (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
+}
+
+// Raster work items: tile t's list is cut into max(1, ceil(L / kItemSplats))
+// items, so no single workgroup carries a tile many times heavier than the
+// mean.  items[t] receives the count here and its exclusive prefix after the
+// scan; items[total_tiles] ends up holding the number of items.
+__global__ __launch_bounds__(256) void make_items(const DevCamera* cams, int32_t nv, const uint32_t* hist,
+                                                  int32_t nblk, int64_t capacity, int64_t total_tiles,
+                                                  uint32_t* items) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (t > total_tiles) return;
+  if (t == total_tiles) {
+    items[t] = 0u;
+    return;
+  }
+  int v = 0;
+  while (v + 1 < nv && cams[v + 1].tile_base <= t) ++v;
+  const int64_t hb = cams[v].hist_base + (t - cams[v].tile_base) * nblk;
+  const uint64_t cap = static_cast<uint64_t>(capacity);
+  uint64_t s = hist[hb], e = hist[hb + nblk];
+  s = s < cap ? s : cap;
+  e = e < cap ? e : cap;
+  const uint64_t len = e > s ? e - s : 0;
+  items[t] = static_cast<uint32_t>(len == 0 ? 1 : (len + kItemSplats - 1) / kItemSplats);
+}
+
 }  // namespace
 
-hipError_t launch_bin(const Layout& L, void* ws, uint32_t* ids, int64_t capacity, hipStream_t st) {
+hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, hipStream_t st) {
   DevFlags* flags = at<DevFlags>(ws, L.off_flags);
   uint32_t* hist = at<uint32_t>(ws, L.off_hist);
   uint32_t* parts = at<uint32_t>(ws, L.off_scan);
+  uint32_t* goff = at<uint32_t>(ws, L.off_goff);
   const int64_t len = L.hist_len + 1;  // trailing entry becomes the total
+  const PairView pv = pair_view(pairs, capacity);
 
   BinArgs a;
   a.cams = at<DevCamera>(ws, L.off_cams);
   a.rect = at<uint2>(ws, L.off_rect);
   a.hist = hist;
-  a.ids = ids;
+  a.goff = goff;
+  a.ids = pv.ids;
+  a.slot = pv.slot;
   a.n = L.n;
   a.capacity = capacity;
   a.nblk = L.nblk;
@@ -222,14 +279,39 @@ hipError_t launch_bin(const Layout& L, void* ws, uint32_t* ids, int64_t capacity
 
   hipError_t e = launch_fill_zero(hist + L.hist_len, sizeof(uint32_t), st);
   if (e != hipSuccess) return e;
+  // split-tile accumulator of the forward raster starts at zero
+  e = launch_fill_zero(at<float>(ws, L.off_acc), sizeof(float) * 4 * L.total_pixels, st);
+  if (e != hipSuccess) return e;
   bin_pass<false><<<grid, kBinThreads, lds, st>>>(a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // Gaussian-major pair offsets (exclusive scan of the rectangle sizes)
+  {
+    const int64_t slots = L.n * L.nv;
+    const int64_t glen = slots + 1;
+    gauss_counts<<<static_cast<unsigned>((glen + 255) / 256), 256, 0, st>>>(a.rect, slots, goff);
+    const unsigned gparts = static_cast<unsigned>((glen + kScanItems - 1) / kScanItems);
+    scan_reduce<<<gparts, 256, 0, st>>>(goff, glen, parts);
+    scan_parts<<<1, 1024, 0, st>>>(parts, gparts, nullptr, 0);
+    scan_apply<<<gparts, 256, 0, st>>>(goff, glen, parts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const unsigned nparts = static_cast<unsigned>((len + kScanItems - 1) / kScanItems);
   scan_reduce<<<nparts, 256, 0, st>>>(hist, len, parts);
   scan_parts<<<1, 1024, 0, st>>>(parts, nparts, flags, capacity);
   scan_apply<<<nparts, 256, 0, st>>>(hist, len, parts);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   bin_pass<true><<<grid, kBinThreads, lds, st>>>(a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+
+  // raster work items per tile, then their exclusive prefix
+  uint32_t* items = at<uint32_t>(ws, L.off_items);
+  const int64_t ilen = L.total_tiles + 1;
+  make_items<<<static_cast<unsigned>((ilen + 255) / 256), 256, 0, st>>>(a.cams, L.nv, hist, L.nblk, capacity,
+                                                                       L.total_tiles, items);
+  const unsigned iparts = static_cast<unsigned>((ilen + kScanItems - 1) / kScanItems);
+  scan_reduce<<<iparts, 256, 0, st>>>(items, ilen, parts);
+  scan_parts<<<1, 1024, 0, st>>>(parts, iparts, nullptr, 0);
+  scan_apply<<<iparts, 256, 0, st>>>(items, ilen, parts);
   return hipGetLastError();
 }
 

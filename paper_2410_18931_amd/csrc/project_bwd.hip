@@ -27,7 +27,7 @@ struct BwdArgs {
   const float* lc_v;
   const float* globals;
   const DevCamera* cams;
-  const float* grad2d;
+  const float* grad2d;       // per-(view, Gaussian) 2D gradients [nv][n][9]
   wsr_grads g;
   double* gpart;      // [blocks][2] = sigma, beta
   int64_t n;
@@ -70,12 +70,11 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
     for (int v = 0; v < a.nv; ++v) {
       const float* g2 = a.grad2d + (static_cast<int64_t>(v) * n + i) * 9;
       float gv[9];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) gv[j] = g2[j];
       bool nz = false;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) {
-        gv[j] = g2[j];
-        nz |= gv[j] != 0.f;
-      }
+      for (int j = 0; j < 9; ++j) nz |= gv[j] != 0.f;
       if (!nz) continue;
       const DevCamera& cam = a.cams[v];
       ViewGeom g;
@@ -268,6 +267,45 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
   }
 }
 
+// Sum of each (view, Gaussian)'s per-tile partial 2D gradients: its pairs
+// occupy a contiguous range of Gaussian-major slots.  A light kernel of its
+// own (high occupancy, several independent loads in flight per thread), so
+// the register-heavy chain below reads one 9-float gradient per slot.
+__global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, const float3* part, uint32_t capacity,
+                                                         int64_t slots, float* grad2d, float* out_grad2d) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (k >= slots) return;
+  uint32_t s0 = goff[k], s1 = goff[k + 1];
+  s0 = s0 < capacity ? s0 : capacity;
+  s1 = s1 < capacity ? s1 : capacity;
+  float3 a0 = make_float3(0.f, 0.f, 0.f), a1 = a0, a2 = a0;
+  float3 b0 = a0, b1 = a0, b2 = a0;
+  uint32_t j = s0;
+  for (; j + 1 < s1; j += 2) {
+    const float3* p = part + 3 * static_cast<int64_t>(j);
+    const float3 x0 = p[0], x1 = p[1], x2 = p[2], y0 = p[3], y1 = p[4], y2 = p[5];
+    a0.x += x0.x; a0.y += x0.y; a0.z += x0.z; a1.x += x1.x; a1.y += x1.y; a1.z += x1.z;
+    a2.x += x2.x; a2.y += x2.y; a2.z += x2.z;
+    b0.x += y0.x; b0.y += y0.y; b0.z += y0.z; b1.x += y1.x; b1.y += y1.y; b1.z += y1.z;
+    b2.x += y2.x; b2.y += y2.y; b2.z += y2.z;
+  }
+  if (j < s1) {
+    const float3* p = part + 3 * static_cast<int64_t>(j);
+    const float3 x0 = p[0], x1 = p[1], x2 = p[2];
+    a0.x += x0.x; a0.y += x0.y; a0.z += x0.z; a1.x += x1.x; a1.y += x1.y; a1.z += x1.z;
+    a2.x += x2.x; a2.y += x2.y; a2.z += x2.z;
+  }
+  const float g[9] = {a0.x + b0.x, a0.y + b0.y, a0.z + b0.z, a1.x + b1.x, a1.y + b1.y,
+                      a1.z + b1.z, a2.x + b2.x, a2.y + b2.y, a2.z + b2.z};
+  float* d = grad2d + 9 * k;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) d[q] = g[q];
+  if (out_grad2d) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out_grad2d[9 * k + q] = g[q];
+  }
+}
+
 // Final reduction of the global parameters: dL/dsigma, dL/dbeta from the
 // per-block partials, dL/dw_B and dL/dc_B from the per-tile partials.
 __global__ __launch_bounds__(256) void reduce_globals(const double* gpart, int64_t nblocks,
@@ -324,12 +362,18 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
 }
 
 hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const float* globals,
-                              const Layout& L, void* ws, const wsr_grads* g, float* out_grad2d,
-                              hipStream_t st) {
+                              const Layout& L, void* ws, const void* pairs, int64_t capacity,
+                              const wsr_grads* g, float* out_grad2d, hipStream_t st) {
   double* gpart = at<double>(ws, L.off_gpart);
   const unsigned blocks = static_cast<unsigned>(project_bwd_blocks(L.n));
   hipError_t e = hipSuccess;
   if (L.n > 0) {
+    const PairView pv = pair_view(pairs, capacity);
+    const int64_t slots = L.n * L.nv;
+    sum_pair_partials<<<static_cast<unsigned>((slots + 255) / 256), 256, 0, st>>>(
+        at<uint32_t>(ws, L.off_goff), pv.part, static_cast<uint32_t>(capacity), slots, at<float>(ws, L.off_grad2d),
+        out_grad2d);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     BwdArgs a;
     a.means = sc->means;
     a.log_scales = sc->log_scales;
@@ -358,11 +402,6 @@ hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const fl
     e = launch_fill_zero(gpart, 2 * sizeof(double), st);
   }
   if (e != hipSuccess) return e;
-  if (out_grad2d && L.n > 0) {
-    e = hipMemcpyAsync(out_grad2d, at<float>(ws, L.off_grad2d), sizeof(float) * 9 * L.n * L.nv,
-                       hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return e;
-  }
   reduce_globals<<<1, 256, 0, st>>>(gpart, static_cast<int64_t>(blocks), at<float>(ws, L.off_tilepart),
                                     L.total_tiles, g->globals);
   return hipGetLastError();

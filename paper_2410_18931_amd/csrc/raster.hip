@@ -112,8 +112,13 @@ struct RasterArgs {
   const float* dL_drgb;
   const float* rgb;
   const float* den;
-  float* grad2d;
+  const uint32_t* slot;   // Gaussian-major slot of each list position
+  float3* part;           // per-pair partial 2D gradients, 3 float3 per slot
   float* tilepart;
+  // work items (see make_items) and the split-tile accumulator
+  const uint32_t* items;
+  int64_t total_tiles;
+  float* acc;
 };
 
 __device__ __forceinline__ int find_view(const DevCamera* cams, int nv, int tile) {
@@ -122,22 +127,36 @@ __device__ __forceinline__ int find_view(const DevCamera* cams, int nv, int tile
   return v;
 }
 
-// Common tile set-up: view, tile coordinates, this lane's pixels, and the
-// [start, end) range of the tile's id list.
+// Common set-up of one work item: its tile (view, tile coordinates), the
+// sub-range [start, end) of the tile's id list it covers, and this lane's
+// pixels.  Returns false for blocks beyond the last item.
 template <int T>
 struct TileCtx {
   int v, tx, ty;
+  int64_t tile;
   int64_t n;
   uint32_t start, end;
+  uint32_t k, nk;                 // item index within the tile, items of the tile
   int wave, lane;
   int bx0, by0;                   // first pixel of this wave's block
   int px[TileGeom<T>::kPpl], py[TileGeom<T>::kPpl];
 };
 
 template <int T>
-__device__ __forceinline__ void tile_setup(const RasterArgs& a, TileCtx<T>& c, const DevCamera*& cam) {
+__device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, const DevCamera*& cam) {
   using G = TileGeom<T>;
-  const int tile = blockIdx.x;
+  const uint32_t item = blockIdx.x;
+  if (item >= a.items[a.total_tiles]) return false;
+  // largest tile t with items[t] <= item (items is strictly increasing)
+  int64_t lo = 0, hi = a.total_tiles - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (a.items[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  c.tile = lo;
+  c.k = item - a.items[lo];
+  c.nk = a.items[lo + 1] - a.items[lo];
+  const int tile = static_cast<int>(lo);
   c.v = find_view(a.cams, a.nv, tile);
   cam = &a.cams[c.v];
   const int local = tile - cam->tile_base;
@@ -149,8 +168,11 @@ __device__ __forceinline__ void tile_setup(const RasterArgs& a, TileCtx<T>& c, c
   uint64_t s = a.hist[hb], e = a.hist[hb + a.nblk];
   s = s < cap ? s : cap;
   e = e < cap ? e : cap;
-  c.start = static_cast<uint32_t>(s);
-  c.end = static_cast<uint32_t>(e > s ? e : s);
+  if (e < s) e = s;
+  const uint64_t ss = s + static_cast<uint64_t>(c.k) * kItemSplats;
+  const uint64_t ee = ss + kItemSplats;
+  c.start = static_cast<uint32_t>(ss < e ? ss : e);
+  c.end = static_cast<uint32_t>(ee < e ? ee : e);
   c.wave = threadIdx.x / kWave;
   c.lane = threadIdx.x % kWave;
   c.bx0 = c.tx * T + (G::kWaves == 4 ? (c.wave & 1) * G::kSub : 0);
@@ -161,6 +183,7 @@ __device__ __forceinline__ void tile_setup(const RasterArgs& a, TileCtx<T>& c, c
     c.px[k] = c.bx0 + lx + 8 * (k & 1);
     c.py[k] = c.by0 + ly + 8 * (k >> 1);
   }
+  return true;
 }
 
 // Stage one batch of records into LDS and build this wave's culled list.
@@ -205,7 +228,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   __shared__ uint16_t s_list[G::kWaves * G::kBatch];
   TileCtx<T> c;
   const DevCamera* cam;
-  tile_setup<T>(a, c, cam);
+  if (!tile_setup<T>(a, c, cam)) return;
 
   float nr[G::kPpl], ng[G::kPpl], nb[G::kPpl], dd[G::kPpl];
   int cntp[G::kPpl];
@@ -244,6 +267,16 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   for (int k = 0; k < G::kPpl; ++k) {
     if (c.px[k] >= cam->width || c.py[k] >= cam->height) continue;
     const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py[k]) * cam->width + c.px[k];
+    if (COUNT) atomicAdd(a.out_count + pix, cntp[k]);
+    if (c.nk > 1) {
+      // split tile: partial sums, normalised by raster_fwd_finalize
+      float* ac = a.acc + 4 * pix;
+      unsafeAtomicAdd(ac, nr[k]);
+      unsafeAtomicAdd(ac + 1, ng[k]);
+      unsafeAtomicAdd(ac + 2, nb[k]);
+      unsafeAtomicAdd(ac + 3, dd[k]);
+      continue;
+    }
     const float D = wbg + dd[k];
     const float Nr = fmaf(bgr, wbg, nr[k]), Ng = fmaf(bgg, wbg, ng[k]), Nb = fmaf(bgb, wbg, nb[k]);
     float Cr = bgr, Cg = bgg, Cb = bgb;
@@ -256,7 +289,41 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
     a.out_rgb[3 * pix + 1] = Cg;
     a.out_rgb[3 * pix + 2] = Cb;
     a.out_den[pix] = D;
-    if (COUNT) a.out_count[pix] = cntp[k];
+  }
+}
+
+// Normalisation of the tiles whose list was split over several work items:
+// their partial sums were accumulated in `acc`, which is cleared again here.
+template <int T>
+__global__ __launch_bounds__(256) void raster_fwd_finalize(RasterArgs a) {
+  const int64_t t = blockIdx.x;
+  if (a.items[t + 1] - a.items[t] <= 1) return;
+  const int tile = static_cast<int>(t);
+  const int v = find_view(a.cams, a.nv, tile);
+  const DevCamera& cam = a.cams[v];
+  const int local = tile - cam.tile_base;
+  const int tx = local % cam.tiles_x, ty = local / cam.tiles_x;
+  const float wbg = a.globals[2];
+  const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
+  for (int q = threadIdx.x; q < T * T; q += 256) {
+    const int px = tx * T + q % T, py = ty * T + q / T;
+    if (px >= cam.width || py >= cam.height) continue;
+    const int64_t pix = cam.pix_base + static_cast<int64_t>(py) * cam.width + px;
+    float4* ac = reinterpret_cast<float4*>(a.acc) + pix;
+    const float4 s = *ac;
+    *ac = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float D = wbg + s.w;
+    const float Nr = fmaf(bgr, wbg, s.x), Ng = fmaf(bgg, wbg, s.y), Nb = fmaf(bgb, wbg, s.z);
+    float Cr = bgr, Cg = bgg, Cb = bgb;
+    if (D != 0.f) {
+      Cr = Nr / D;
+      Cg = Ng / D;
+      Cb = Nb / D;
+    }
+    a.out_rgb[3 * pix] = Cr;
+    a.out_rgb[3 * pix + 1] = Cg;
+    a.out_rgb[3 * pix + 2] = Cb;
+    a.out_den[pix] = D;
   }
 }
 
@@ -276,20 +343,21 @@ __device__ __forceinline__ float wave_sum(float x) {
 template <int T>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
-  constexpr int kPix = G::kSub * G::kSub;  // pixels of one wave block
   __shared__ SplatRec s_rec[G::kBatch];
   __shared__ uint32_t s_id[G::kBatch];
   __shared__ uint16_t s_list[G::kWaves * G::kBatch];
-  __shared__ float4 s_pix[G::kWaves][kPix];
   __shared__ float s_acc[9][G::kBatch];
   __shared__ float s_bg[G::kWaves][4];
   TileCtx<T> c;
   const DevCamera* cam;
-  tile_setup<T>(a, c, cam);
+  if (!tile_setup<T>(a, c, cam)) return;
 
   const float wbg = a.globals[2];
   const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
   float bacc[4] = {0.f, 0.f, 0.f, 0.f};  // dL/dc_B (rgb), dL/dw_B
+  // per-pixel factors of this lane's pixel(s); other lanes fetch them with
+  // v_readlane (wave-uniform lane index, no memory round trip)
+  float4 pdv[G::kPpl];
 #pragma unroll
   for (int k = 0; k < G::kPpl; ++k) {
     float4 pd = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -314,12 +382,11 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
         bacc[2] += g2;
       }
     }
-    s_pix[c.wave][(c.py[k] - c.by0) * G::kSub + (c.px[k] - c.bx0)] = pd;
+    pdv[k] = pd;
   }
   for (int k = threadIdx.x; k < 9 * G::kBatch; k += G::kThreads) (&s_acc[0][0])[k] = 0.f;
 
   const float tau = a.tau;
-  const float4* pixw = s_pix[c.wave];
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
     const int m = stage_and_cull<T>(a, c, b, s_rec, s_id, s_list);
     const uint16_t* list = s_list + c.wave * G::kBatch;
@@ -329,7 +396,12 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
       const int kr = valid ? list[j] : 0;
       const SplatRec r = s_rec[kr];
       const float amp = r.r1.w, cr = r.r2.x, cg = r.r2.y, cb = r.r2.z;
-      float g_mx = 0.f, g_my = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
+      // Moments of e = a * dL/da over the block's pixels (dq = -e / 2):
+      // Mx = sum e dx, My = sum e dy, Mxx = sum e dx^2, Mxy = sum e dx dy,
+      // Myy = sum e dy^2.  Each row keeps S0 = sum e, S1 = sum e dx and
+      // S2 = sum e dx^2 and folds dy in once, so a pixel costs three FMAs.
+      float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+      float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
       const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
       // first pixel centre of the block relative to the splat's integer
       // origin (exact), so dx = (ex0 + col) - fx matches the forward's
@@ -338,32 +410,45 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
       for (int row = 0; row < G::kSub; ++row) {
         const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
         const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
-        const float4* prow = pixw + row * G::kSub;
+        const int lrow = (row & 7) * 8;
+        const int krow = (row >> 3) * 2;
+        float S0 = 0.f, S1 = 0.f, S2 = 0.f;
 #pragma unroll
         for (int col = 0; col < G::kSub; ++col) {
           const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
           const float q = quad_form(A, B2dy, Cdy2, dx);
           if (valid && q <= tau) {
-            const float4 pd = prow[col];
+            // pixel (row, col) of the block lives in lane (row%8)*8 + col%8, slot (row/8)*2 + col/8
+            const float4 pv = (G::kPpl == 1 || krow == 0) ? pdv[col >> 3] : pdv[(G::kPpl == 1 ? 0 : 2) + (col >> 3)];
+            const int src = lrow + (col & 7);
+            const float pdx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.x), src));
+            const float pdy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.y), src));
+            const float pdz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.z), src));
+            const float pdw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.w), src));
             const float Gq = falloff(q);
             const float al = amp * Gq;
-            const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
-            const float dq = -0.5f * al * dLda;
-            // q = A dx^2 + B2 dx dy + C dy^2 with dx = px - mu_x
-            g_mx = fmaf(dq, fmaf(2.f * A, dx, B2dy), g_mx);
-            g_my = fmaf(dq, fmaf(B2, dx, 2.f * Cc * dy), g_my);
-            gA = fmaf(dq, dx * dx, gA);
-            gB = fmaf(dq, 2.f * dx * dy, gB);
-            gC = fmaf(dq, dy * dy, gC);
-            g_r = fmaf(al, pd.x, g_r);
-            g_g = fmaf(al, pd.y, g_g);
-            g_b = fmaf(al, pd.z, g_b);
+            const float dLda = fmaf(pdx, cr, fmaf(pdy, cg, fmaf(pdz, cb, -pdw)));
+            const float e = al * dLda;
+            S0 += e;
+            S1 = fmaf(e, dx, S1);
+            S2 = fmaf(e, dx * dx, S2);
+            g_r = fmaf(al, pdx, g_r);
+            g_g = fmaf(al, pdy, g_g);
+            g_b = fmaf(al, pdz, g_b);
             g_amp = fmaf(dLda, Gq, g_amp);
           }
         }
+        Mx += S1;
+        My = fmaf(dy, S0, My);
+        Mxx += S2;
+        Mxy = fmaf(dy, S1, Mxy);
+        Myy = fmaf(dy * dy, S0, Myy);
       }
-      g_mx = -g_mx;
-      g_my = -g_my;
+      // dq = -e/2; q = A dx^2 + B2 dx dy + C dy^2 with dx = px - mu_x, so
+      // dL/dmu_x = -sum dq (2A dx + B2 dy) = A Mx + (B2/2) My, and so on
+      const float g_mx = A * Mx + 0.5f * B2 * My;
+      const float g_my = 0.5f * B2 * Mx + Cc * My;
+      const float gA = -0.5f * Mxx, gB = -Mxy, gC = -0.5f * Myy;
       if (valid) {
         atomicAdd(&s_acc[0][kr], g_mx);
         atomicAdd(&s_acc[1][kr], g_my);
@@ -377,21 +462,23 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
       }
     }
     __syncthreads();
+    // one plain store per (tile, splat) pair, at the pair's Gaussian-major
+    // slot (every pair of the batch is written, zeros included, so the
+    // projection backward can sum each Gaussian's slot range blindly)
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(G::kBatch), c.end - b));
     for (int k = threadIdx.x; k < cnt; k += G::kThreads) {
       float v9[9];
-      bool nz = false;
 #pragma unroll
       for (int j = 0; j < 9; ++j) {
         v9[j] = s_acc[j][k];
         s_acc[j][k] = 0.f;
-        nz |= v9[j] != 0.f;
       }
-      if (nz) {
-        float* dst = a.grad2d + (static_cast<int64_t>(c.v) * c.n + s_id[k]) * 9;
-#pragma unroll
-        for (int j = 0; j < 9; ++j)
-          if (v9[j] != 0.f) unsafeAtomicAdd(dst + j, v9[j]);
+      const uint32_t sl = a.slot[b + k];
+      if (sl < a.capacity) {
+        float3* dst = a.part + 3 * static_cast<int64_t>(sl);
+        dst[0] = make_float3(v9[0], v9[1], v9[2]);
+        dst[1] = make_float3(v9[3], v9[4], v9[5]);
+        dst[2] = make_float3(v9[6], v9[7], v9[8]);
       }
     }
   }
@@ -402,78 +489,89 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
     if (c.lane == 0) s_bg[c.wave][j] = s;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < 4 && c.k == 0) {
     float s = 0.f;
 #pragma unroll
     for (int w = 0; w < G::kWaves; ++w) s += s_bg[w][threadIdx.x];
-    a.tilepart[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = s;
+    a.tilepart[c.tile * 4 + threadIdx.x] = s;
   }
 }
 
-RasterArgs make_args(const Layout& L, const void* ws, const uint32_t* ids, int64_t capacity,
+RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capacity,
                      const wsr_params* P, const float* globals) {
   RasterArgs a = {};
+  const PairView pv = pair_view(pairs, capacity);
   a.cams = at<DevCamera>(ws, L.off_cams);
   a.rec = at<SplatRec>(ws, L.off_rec);
   a.hist = at<uint32_t>(ws, L.off_hist);
-  a.ids = ids;
+  a.ids = pv.ids;
+  a.slot = pv.slot;
+  a.part = pv.part;
   a.n = L.n;
   a.capacity = capacity;
   a.nv = L.nv;
   a.nblk = L.nblk;
   a.tau = P->tau;
   a.globals = globals;
+  a.items = at<uint32_t>(ws, L.off_items);
+  a.total_tiles = L.total_tiles;
+  a.acc = at<float>(ws, L.off_acc);
   return a;
 }
 
 template <int T>
-hipError_t fwd_t(const RasterArgs& a, int64_t tiles, bool count, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>(tiles));
+hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, bool count, hipStream_t st) {
   if (count)
-    raster_fwd_kernel<T, true><<<grid, TileGeom<T>::kThreads, 0, st>>>(a);
+    raster_fwd_kernel<T, true><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a);
   else
-    raster_fwd_kernel<T, false><<<grid, TileGeom<T>::kThreads, 0, st>>>(a);
+    raster_fwd_kernel<T, false><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a);
+  raster_fwd_finalize<T><<<dim3(static_cast<unsigned>(tiles)), 256, 0, st>>>(a);
   return hipGetLastError();
 }
 
 template <int T>
-hipError_t bwd_t(const RasterArgs& a, int64_t tiles, hipStream_t st) {
-  raster_bwd_kernel<T><<<dim3(static_cast<unsigned>(tiles)), TileGeom<T>::kThreads, 0, st>>>(a);
+hipError_t bwd_t(const RasterArgs& a, int64_t grid, hipStream_t st) {
+  raster_bwd_kernel<T><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_raster_fwd(const Layout& L, const void* ws, const uint32_t* ids, int64_t capacity,
+hipError_t launch_raster_fwd(const Layout& L, void* ws, const void* pairs, int64_t capacity,
                              const wsr_params* P, const float* globals, float* out_rgb,
                              float* out_den, int32_t* out_count, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
-  RasterArgs a = make_args(L, ws, ids, capacity, P, globals);
+  RasterArgs a = make_args(L, ws, pairs, capacity, P, globals);
   a.out_rgb = out_rgb;
   a.out_den = out_den;
   a.out_count = out_count;
   const bool cnt = out_count != nullptr;
+  if (cnt) {
+    const hipError_t e = launch_fill_zero(out_count, sizeof(int32_t) * L.total_pixels, st);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t grid = max_raster_items(L, capacity);
   switch (L.tile) {
-    case 8: return fwd_t<8>(a, L.total_tiles, cnt, st);
-    case 32: return fwd_t<32>(a, L.total_tiles, cnt, st);
-    default: return fwd_t<16>(a, L.total_tiles, cnt, st);
+    case 8: return fwd_t<8>(a, grid, L.total_tiles, cnt, st);
+    case 32: return fwd_t<32>(a, grid, L.total_tiles, cnt, st);
+    default: return fwd_t<16>(a, grid, L.total_tiles, cnt, st);
   }
 }
 
-hipError_t launch_raster_bwd(const Layout& L, void* ws, const uint32_t* ids, int64_t capacity,
+hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t capacity,
                              const wsr_params* P, const float* globals, const float* dL_drgb,
                              const float* rgb, const float* den, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
-  RasterArgs a = make_args(L, ws, ids, capacity, P, globals);
+  RasterArgs a = make_args(L, ws, pairs, capacity, P, globals);
   a.dL_drgb = dL_drgb;
   a.rgb = rgb;
   a.den = den;
-  a.grad2d = at<float>(ws, L.off_grad2d);
   a.tilepart = at<float>(ws, L.off_tilepart);
+  const int64_t grid = max_raster_items(L, capacity);
   switch (L.tile) {
-    case 8: return bwd_t<8>(a, L.total_tiles, st);
-    case 32: return bwd_t<32>(a, L.total_tiles, st);
-    default: return bwd_t<16>(a, L.total_tiles, st);
+    case 8: return bwd_t<8>(a, grid, st);
+    case 32: return bwd_t<32>(a, grid, st);
+    default: return bwd_t<16>(a, grid, st);
   }
 }
 

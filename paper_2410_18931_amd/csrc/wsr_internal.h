@@ -14,6 +14,7 @@ constexpr int kBinChunk = 8192;       // Gaussians per binning block
 constexpr int kTileChunk = 14336;     // tiles per binning LDS histogram (56 KB + static < 64 KB)
 constexpr int kScanItems = 4096;      // elements per scan block (256 threads x 16)
 constexpr int kRasterBatch = 256;     // splats staged in LDS per batch
+constexpr int kItemSplats = 1024;     // a tile's list is split into raster work items of at most this many
 constexpr int kProjBlock = 256;
 
 // Camera as the kernels see it, with the per-view offsets into the
@@ -38,6 +39,26 @@ struct __align__(16) SplatRec {
   float4 r0, r1, r2;
 };
 
+// The caller's pair buffer (capacity entries of kPairBytes bytes): per
+// (tile, Gaussian) pair a 36-byte partial 2D gradient (written by the raster
+// backward at the pair's Gaussian-major slot), the Gaussian id at each
+// position of the per-tile lists, and the Gaussian-major slot of each
+// position.
+constexpr int64_t kPairBytes = 44;
+struct PairView {
+  float3* part;        // [capacity][3] float3: (mu_x, mu_y, A) (B, C, r) (g, b, a)
+  uint32_t* ids;       // [capacity]
+  uint32_t* slot;      // [capacity]
+};
+__host__ __device__ inline PairView pair_view(const void* pairs, int64_t capacity) {
+  char* b = static_cast<char*>(const_cast<void*>(pairs));
+  PairView v;
+  v.part = reinterpret_cast<float3*>(b);
+  v.ids = reinterpret_cast<uint32_t*>(b + 36 * capacity);
+  v.slot = reinterpret_cast<uint32_t*>(b + 40 * capacity);
+  return v;
+}
+
 // Device-side status words (in the workspace).
 struct DevFlags {
   uint32_t overflow;        // id-list capacity exceeded
@@ -57,7 +78,7 @@ struct Layout {
   int64_t hist_len = 0;      // entries of the count matrix (without the trailing total)
   int64_t scan_parts = 0;
   size_t off_cams = 0, off_flags = 0, off_rec = 0, off_rect = 0, off_hist = 0, off_scan = 0,
-         off_grad2d = 0, off_tilepart = 0, off_gpart = 0;
+         off_goff = 0, off_grad2d = 0, off_tilepart = 0, off_gpart = 0, off_items = 0, off_acc = 0;
   int64_t gpart_blocks = 0;
   size_t bytes = 0;
 };
@@ -118,16 +139,20 @@ hipError_t launch_project(const wsr_scene* sc, const wsr_params* P, const float*
                           const Layout& L, void* ws, float* out_proj, hipStream_t st);
 hipError_t launch_upload_cameras(const DevCamera* dc, int32_t nv, void* ws, const Layout& L,
                                  hipStream_t st);
-hipError_t launch_bin(const Layout& L, void* ws, uint32_t* ids, int64_t capacity, hipStream_t st);
-hipError_t launch_raster_fwd(const Layout& L, const void* ws, const uint32_t* ids, int64_t capacity,
+hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, hipStream_t st);
+hipError_t launch_raster_fwd(const Layout& L, void* ws, const void* pairs, int64_t capacity,
                              const wsr_params* P, const float* globals, float* out_rgb,
                              float* out_den, int32_t* out_count, hipStream_t st);
-hipError_t launch_raster_bwd(const Layout& L, void* ws, const uint32_t* ids, int64_t capacity,
+hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t capacity,
                              const wsr_params* P, const float* globals, const float* dL_drgb,
                              const float* rgb, const float* den, hipStream_t st);
 hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const float* globals,
-                              const Layout& L, void* ws, const wsr_grads* g, float* out_grad2d,
-                              hipStream_t st);
+                              const Layout& L, void* ws, const void* pairs, int64_t capacity,
+                              const wsr_grads* g, float* out_grad2d, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+// Upper bound of the raster work items for an id list of `capacity` entries.
+inline int64_t max_raster_items(const Layout& L, int64_t capacity) {
+  return L.total_tiles + (capacity + kItemSplats - 1) / kItemSplats;
+}
 
 }  // namespace wsr

@@ -76,12 +76,17 @@ class WSRContext:
         self.total_pixels = sum(self.pix_counts)
         if capacity is None:
             capacity = max(1 << 16, 4 * self.total_pixels)
-        self.capacity = int(capacity)
-        self.ids = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=self.device)
+        self.pair_bytes = int(self.lib.wsr_pair_bytes())
+        self._alloc_pairs(int(capacity))
         self.generation = 0      # bumps on every projection
         self.last_pairs = None
 
     # ---------------------------------------------------------------- helpers
+    def _alloc_pairs(self, capacity: int) -> None:
+        """Per-pair buffer (id lists + backward scratch), 256-byte aligned."""
+        self.capacity = int(capacity)
+        self.pairs = torch.empty(max(self.capacity, 1) * self.pair_bytes, dtype=torch.uint8, device=self.device)
+
     def views(self, img: torch.Tensor) -> list:
         """Split a concatenated per-pixel tensor into per-view [H][W][...] tensors."""
         out, o = [], 0
@@ -121,16 +126,15 @@ class WSRContext:
         if it overflowed; without it, an overflow is only recorded in the
         workspace flag (see ``check``)."""
         st = self.lib.wsr_bin(self.cams_c, self.nv, C.byref(self.params), self.n, _ptr(self.ws), self.ws_bytes,
-                              _ptr(self.ids), self.capacity, _stream())
+                              _ptr(self.pairs), self.capacity, _stream())
         _lib.check("wsr_bin", st)
         if grow:
             total = self.pair_count()
             self.last_pairs = total
             if total > self.capacity:
-                self.capacity = int(total * 1.25) + 1024
-                self.ids = torch.empty(self.capacity, dtype=torch.int32, device=self.device)
+                self._alloc_pairs(int(total * 1.25) + 1024)
                 st = self.lib.wsr_bin(self.cams_c, self.nv, C.byref(self.params), self.n, _ptr(self.ws),
-                                      self.ws_bytes, _ptr(self.ids), self.capacity, _stream())
+                                      self.ws_bytes, _ptr(self.pairs), self.capacity, _stream())
                 _lib.check("wsr_bin", st)
 
     def pair_count(self) -> int:
@@ -149,7 +153,7 @@ class WSRContext:
             rgb, den = out
         cnt = torch.empty((self.total_pixels,), dtype=torch.int32, device=self.device) if count else None
         st = self.lib.wsr_render_fwd(self.cams_c, self.nv, C.byref(self.params), self.n, _ptr(globals_),
-                                     _ptr(self.ws), self.ws_bytes, _ptr(self.ids), self.capacity,
+                                     _ptr(self.ws), self.ws_bytes, _ptr(self.pairs), self.capacity,
                                      _ptr(rgb), _ptr(den), _ptr(cnt), _stream())
         _lib.check("wsr_render_fwd", st)
         return (rgb, den, cnt) if count else (rgb, den)
@@ -176,7 +180,7 @@ class WSRContext:
                            g["globals"].data_ptr())
         dL = dL_drgb.contiguous()
         st = self.lib.wsr_render_bwd(C.byref(sc), self.cams_c, self.nv, C.byref(self.params), _ptr(globals_),
-                                     _ptr(self.ws), self.ws_bytes, _ptr(self.ids), self.capacity, _ptr(dL),
+                                     _ptr(self.ws), self.ws_bytes, _ptr(self.pairs), self.capacity, _ptr(dL),
                                      _ptr(rgb), _ptr(den), C.byref(gs), _ptr(grad2d), _stream())
         _lib.check("wsr_render_bwd", st)
         return g
