@@ -57,7 +57,7 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   L->total_pixels = pixels;
   L->hist_len = hist;
   {
-    const int64_t longest = hist + 1 > n * nv + 1 ? hist + 1 : n * nv + 1;
+    const int64_t longest = tiles + 1 > n * nv + 1 ? tiles + 1 : n * nv + 1;
     L->scan_parts = (longest + kScanItems - 1) / kScanItems;
   }
   L->gpart_blocks = project_bwd_blocks(n);
@@ -71,6 +71,7 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   L->off_scan = off;     off = align256(off + sizeof(uint32_t) * L->scan_parts);
   L->off_goff = off;     off = align256(off + sizeof(uint32_t) * (slots + 1));
   L->off_grad2d = off;   off = align256(off + sizeof(float) * 9 * slots);
+  L->off_tstart = off;   off = align256(off + sizeof(uint32_t) * (tiles + 1));
   L->off_tilepart = off; off = align256(off + sizeof(float) * 4 * tiles);
   L->off_gpart = off;    off = align256(off + sizeof(double) * 2 * L->gpart_blocks);
   L->off_items = off;    off = align256(off + sizeof(uint32_t) * (tiles + 1));

@@ -2,19 +2,26 @@
 // Eq. 7 is a commutative sum (Sec. 4.2), so only membership matters; this is
 // the step that replaces the per-tile depth sort of 3DGS (Sec. 4.1).
 //
-// A counting sort by tile, built from LDS histograms instead of global
-// atomics:
-//   1. bin_count: block (b, z, v) takes Gaussians [b*kBinChunk, ...) of view v
-//      and counts their (tile, Gaussian) pairs into an LDS histogram of the
-//      tile rows of chunk z.  The histogram is stored as column b of a
-//      tile-major count matrix M[v][tile][b].
-//   2. an exclusive scan over M (tile-major) gives every (tile, block) segment
-//      its start; tile t of view v spans [M[v][t][0], M[v][t+1][0]).
-//   3. bin_scatter: the same blocks re-expand their pairs and place ids at
-//      start + LDS-atomic cursor.
+// A counting sort by tile built from LDS histograms, with no global atomics:
+//   1. bin_pass<count>: block (b, z, v) takes Gaussians [b*kBinChunk, ...) of
+//      view v and counts their (tile, Gaussian) pairs into an LDS histogram
+//      of the tile rows of chunk z, written contiguously as row b of the
+//      block-major count matrix M[v][b][tile].
+//   2. column_scan: one thread per tile turns its column of M into exclusive
+//      prefixes over the blocks and produces the tile's total; a scan of the
+//      totals gives every tile the start of its list (tile_start).
+//   3. bin_pass<scatter>: the same blocks re-expand their pairs and place ids
+//      at tile_start[t] + M[v][b][t] + an LDS-atomic cursor.
 // Pairs are expanded load-balanced: per round of 256 Gaussians a block-wide
 // scan of the pair counts lets every thread take every 256th pair, so one
-// huge splat does not serialise on one thread.
+// huge splat does not serialise on one thread.  The order of ids inside a
+// tile is irrelevant to the sums (and the sums are order-insensitive up to
+// float rounding).
+//
+// The same step also lays out the backward's per-pair scratch: every
+// (view, Gaussian) gets a contiguous range of "Gaussian-major" slots, one per
+// tile of its rectangle in row-major order (gauss_counts + scan), and the
+// raster work items that split long tile lists (make_items + scan).
 #include "wsr_internal.h"
 
 namespace wsr {
@@ -50,35 +57,34 @@ __device__ inline uint32_t block_scan_256(uint32_t v, uint32_t* sh, uint32_t* to
 struct BinArgs {
   const DevCamera* cams;
   const uint2* rect;
-  uint32_t* hist;
-  const uint32_t* goff;   // Gaussian-major pair offsets per (view, Gaussian)
+  uint32_t* hist;              // block-major count matrix, then its column prefixes
+  const uint32_t* tile_start;  // start of every tile's list (scatter pass)
   uint32_t* ids;
-  uint32_t* slot;
   int64_t n;
   int64_t capacity;
-  int32_t nblk;
   int32_t rows_per_chunk;
 };
 
-// Shared expansion loop.  SCATTER = false counts, true places ids.
 template <bool SCATTER>
 __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
   extern __shared__ uint32_t lds[];
-  __shared__ uint32_t s_off[kBinThreads + 1];
-  __shared__ uint32_t s_x0[kBinThreads], s_w[kBinThreads], s_y0[kBinThreads], s_goff[kBinThreads];
+  __shared__ uint32_t s_off[kBinThreads];
+  __shared__ uint32_t s_x0[kBinThreads], s_w[kBinThreads], s_y0[kBinThreads];
   __shared__ uint32_t s_scan[4];
 
   const int b = blockIdx.x, z = blockIdx.y, v = blockIdx.z;
   const DevCamera& cam = a.cams[v];
   const int tiles_x = cam.tiles_x;
+  const int tiles_v = cam.tiles_x * cam.tiles_y;
   const int ry0 = z * a.rows_per_chunk;
   if (ry0 >= cam.tiles_y) return;
   const int ry1 = min(ry0 + a.rows_per_chunk, cam.tiles_y);
   const int chunk_tiles = (ry1 - ry0) * tiles_x;
-  uint32_t* col = a.hist + cam.hist_base + static_cast<int64_t>(ry0) * tiles_x * a.nblk + b;
+  const int t0 = ry0 * tiles_x;  // first tile (view-local) of the chunk
+  uint32_t* row = a.hist + cam.hist_base + static_cast<int64_t>(b) * tiles_v + t0;
 
   for (int t = threadIdx.x; t < chunk_tiles; t += kBinThreads)
-    lds[t] = SCATTER ? col[static_cast<int64_t>(t) * a.nblk] : 0u;
+    lds[t] = SCATTER ? a.tile_start[cam.tile_base + t0 + t] + row[t] : 0u;
   __syncthreads();
 
   const int64_t g0 = static_cast<int64_t>(b) * kBinChunk;
@@ -105,14 +111,6 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
     s_x0[threadIdx.x] = x0;
     s_w[threadIdx.x] = w;
     s_y0[threadIdx.x] = y0;
-    // first Gaussian-major slot of this Gaussian's pairs in this chunk: its
-    // pairs are enumerated row by row over its rectangle, so the rows of the
-    // chunk start after (yl - y0_rect) * w of them
-    if (SCATTER && i < g1) {
-      const uint2 r = rect[i];
-      const uint32_t yr = r.y & 0xffffu;
-      s_goff[threadIdx.x] = a.goff[static_cast<int64_t>(v) * a.n + i] + (y0 > yr ? (y0 - yr) * w : 0u);
-    }
     __syncthreads();
     for (uint32_t p = threadIdx.x; p < total; p += kBinThreads) {
       // largest g with s_off[g] <= p (it has a non-zero count)
@@ -130,18 +128,38 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
         atomicAdd(&lds[t], 1u);
       } else {
         const uint32_t pos = atomicAdd(&lds[t], 1u);
-        if (pos < a.capacity) {
-          a.ids[pos] = static_cast<uint32_t>(base + lo);
-          a.slot[pos] = s_goff[lo] + local;
-        }
+        if (pos < a.capacity) a.ids[pos] = static_cast<uint32_t>(base + lo);
       }
     }
     __syncthreads();
   }
   if (!SCATTER) {
-    for (int t = threadIdx.x; t < chunk_tiles; t += kBinThreads)
-      col[static_cast<int64_t>(t) * a.nblk] = lds[t];
+    for (int t = threadIdx.x; t < chunk_tiles; t += kBinThreads) row[t] = lds[t];
   }
+}
+
+// One thread per tile: exclusive prefix of the tile's column of counts over
+// the blocks (in place), and the tile's total into tile_start[t].
+__global__ __launch_bounds__(256) void column_scan(const DevCamera* cams, int32_t nv, int32_t nblk,
+                                                   int64_t total_tiles, uint32_t* hist, uint32_t* tile_start) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (t > total_tiles) return;
+  if (t == total_tiles) {
+    tile_start[t] = 0u;
+    return;
+  }
+  int v = 0;
+  while (v + 1 < nv && cams[v + 1].tile_base <= t) ++v;
+  const DevCamera& cam = cams[v];
+  const int64_t tiles_v = static_cast<int64_t>(cam.tiles_x) * cam.tiles_y;
+  uint32_t* col = hist + cam.hist_base + (t - cam.tile_base);
+  uint32_t run = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const uint32_t c = col[b * tiles_v];
+    col[b * tiles_v] = run;
+    run += c;
+  }
+  tile_start[t] = run;
 }
 
 // ---- device-wide exclusive scan of uint32 (in place), 3 phases ----
@@ -158,6 +176,8 @@ __global__ __launch_bounds__(256) void scan_reduce(const uint32_t* x, int64_t le
   if (threadIdx.x == 0) parts[blockIdx.x] = total;
 }
 
+// Scans the per-block partial sums; with `flags`, also records the grand
+// total and whether it exceeds `capacity` or 32 bits.
 __global__ __launch_bounds__(1024) void scan_parts(uint32_t* parts, int64_t nparts, DevFlags* flags,
                                                    int64_t capacity) {
   __shared__ uint32_t sh[16];
@@ -210,6 +230,15 @@ __global__ __launch_bounds__(256) void scan_apply(uint32_t* x, int64_t len, cons
   }
 }
 
+hipError_t scan_in_place(uint32_t* x, int64_t len, uint32_t* parts, DevFlags* flags, int64_t capacity,
+                         hipStream_t st) {
+  const unsigned np = static_cast<unsigned>((len + kScanItems - 1) / kScanItems);
+  scan_reduce<<<np, 256, 0, st>>>(x, len, parts);
+  scan_parts<<<1, 1024, 0, st>>>(parts, np, flags, capacity);
+  scan_apply<<<np, 256, 0, st>>>(x, len, parts);
+  return hipGetLastError();
+}
+
 // Number of (tile, Gaussian) pairs of every (view, Gaussian) slot, the
 // input of the scan that gives each Gaussian a contiguous range of
 // Gaussian-major pair slots (the raster backward writes a partial gradient
@@ -230,8 +259,7 @@ __global__ __launch_bounds__(256) void gauss_counts(const uint2* rect, int64_t s
 // items, so no single workgroup carries a tile many times heavier than the
 // mean.  items[t] receives the count here and its exclusive prefix after the
 // scan; items[total_tiles] ends up holding the number of items.
-__global__ __launch_bounds__(256) void make_items(const DevCamera* cams, int32_t nv, const uint32_t* hist,
-                                                  int32_t nblk, int64_t capacity, int64_t total_tiles,
+__global__ __launch_bounds__(256) void make_items(const uint32_t* tile_start, int64_t capacity, int64_t total_tiles,
                                                   uint32_t* items) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (t > total_tiles) return;
@@ -239,11 +267,8 @@ __global__ __launch_bounds__(256) void make_items(const DevCamera* cams, int32_t
     items[t] = 0u;
     return;
   }
-  int v = 0;
-  while (v + 1 < nv && cams[v + 1].tile_base <= t) ++v;
-  const int64_t hb = cams[v].hist_base + (t - cams[v].tile_base) * nblk;
   const uint64_t cap = static_cast<uint64_t>(capacity);
-  uint64_t s = hist[hb], e = hist[hb + nblk];
+  uint64_t s = tile_start[t], e = tile_start[t + 1];
   s = s < cap ? s : cap;
   e = e < cap ? e : cap;
   const uint64_t len = e > s ? e - s : 0;
@@ -257,19 +282,18 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
   uint32_t* hist = at<uint32_t>(ws, L.off_hist);
   uint32_t* parts = at<uint32_t>(ws, L.off_scan);
   uint32_t* goff = at<uint32_t>(ws, L.off_goff);
-  const int64_t len = L.hist_len + 1;  // trailing entry becomes the total
+  uint32_t* tstart = at<uint32_t>(ws, L.off_tstart);
+  uint32_t* items = at<uint32_t>(ws, L.off_items);
   const PairView pv = pair_view(pairs, capacity);
 
   BinArgs a;
   a.cams = at<DevCamera>(ws, L.off_cams);
   a.rect = at<uint2>(ws, L.off_rect);
   a.hist = hist;
-  a.goff = goff;
+  a.tile_start = tstart;
   a.ids = pv.ids;
-  a.slot = pv.slot;
   a.n = L.n;
   a.capacity = capacity;
-  a.nblk = L.nblk;
   // whole tile rows per LDS chunk, at most kTileChunk tiles
   a.rows_per_chunk = kTileChunk / L.max_tiles_x;
   if (a.rows_per_chunk < 1) return hipErrorInvalidValue;
@@ -277,42 +301,28 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
   const size_t lds = static_cast<size_t>(a.rows_per_chunk) * L.max_tiles_x * sizeof(uint32_t);
   const dim3 grid(static_cast<unsigned>(L.nblk), static_cast<unsigned>(nchunks), static_cast<unsigned>(L.nv));
 
-  hipError_t e = launch_fill_zero(hist + L.hist_len, sizeof(uint32_t), st);
-  if (e != hipSuccess) return e;
   // split-tile accumulator of the forward raster starts at zero
-  e = launch_fill_zero(at<float>(ws, L.off_acc), sizeof(float) * 4 * L.total_pixels, st);
+  hipError_t e = launch_fill_zero(at<float>(ws, L.off_acc), sizeof(float) * 4 * L.total_pixels, st);
   if (e != hipSuccess) return e;
   bin_pass<false><<<grid, kBinThreads, lds, st>>>(a);
+  const int64_t tl = L.total_tiles + 1;
+  column_scan<<<static_cast<unsigned>((tl + 255) / 256), 256, 0, st>>>(a.cams, L.nv, L.nblk, L.total_tiles, hist,
+                                                                      tstart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // Gaussian-major pair offsets (exclusive scan of the rectangle sizes)
-  {
-    const int64_t slots = L.n * L.nv;
-    const int64_t glen = slots + 1;
-    gauss_counts<<<static_cast<unsigned>((glen + 255) / 256), 256, 0, st>>>(a.rect, slots, goff);
-    const unsigned gparts = static_cast<unsigned>((glen + kScanItems - 1) / kScanItems);
-    scan_reduce<<<gparts, 256, 0, st>>>(goff, glen, parts);
-    scan_parts<<<1, 1024, 0, st>>>(parts, gparts, nullptr, 0);
-    scan_apply<<<gparts, 256, 0, st>>>(goff, glen, parts);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  const unsigned nparts = static_cast<unsigned>((len + kScanItems - 1) / kScanItems);
-  scan_reduce<<<nparts, 256, 0, st>>>(hist, len, parts);
-  scan_parts<<<1, 1024, 0, st>>>(parts, nparts, flags, capacity);
-  scan_apply<<<nparts, 256, 0, st>>>(hist, len, parts);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_in_place(tstart, tl, parts, flags, capacity, st)) != hipSuccess) return e;
   bin_pass<true><<<grid, kBinThreads, lds, st>>>(a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
 
+  // Gaussian-major pair offsets (exclusive scan of the rectangle sizes)
+  const int64_t glen = L.n * L.nv + 1;
+  gauss_counts<<<static_cast<unsigned>((glen + 255) / 256), 256, 0, st>>>(a.rect, L.n * L.nv, goff);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_in_place(goff, glen, parts, nullptr, 0, st)) != hipSuccess) return e;
+
   // raster work items per tile, then their exclusive prefix
-  uint32_t* items = at<uint32_t>(ws, L.off_items);
-  const int64_t ilen = L.total_tiles + 1;
-  make_items<<<static_cast<unsigned>((ilen + 255) / 256), 256, 0, st>>>(a.cams, L.nv, hist, L.nblk, capacity,
-                                                                       L.total_tiles, items);
-  const unsigned iparts = static_cast<unsigned>((ilen + kScanItems - 1) / kScanItems);
-  scan_reduce<<<iparts, 256, 0, st>>>(items, ilen, parts);
-  scan_parts<<<1, 1024, 0, st>>>(parts, iparts, nullptr, 0);
-  scan_apply<<<iparts, 256, 0, st>>>(items, ilen, parts);
-  return hipGetLastError();
+  make_items<<<static_cast<unsigned>((tl + 255) / 256), 256, 0, st>>>(tstart, capacity, L.total_tiles, items);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return scan_in_place(items, tl, parts, nullptr, 0, st);
 }
 
 }  // namespace wsr

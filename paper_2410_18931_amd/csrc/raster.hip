@@ -96,12 +96,11 @@ __device__ __forceinline__ bool block_hits(const SplatRec& r, float bx, float by
 struct RasterArgs {
   const DevCamera* cams;
   const SplatRec* rec;
-  const uint32_t* hist;
+  const uint32_t* tile_start;  // start of every tile's id list
   const uint32_t* ids;
   int64_t n;
   int64_t capacity;
   int32_t nv;
-  int32_t nblk;
   float tau;
   const float* globals;
   // forward outputs
@@ -112,7 +111,8 @@ struct RasterArgs {
   const float* dL_drgb;
   const float* rgb;
   const float* den;
-  const uint32_t* slot;   // Gaussian-major slot of each list position
+  const uint2* rect;      // tile rectangle of every (view, Gaussian)
+  const uint32_t* goff;   // first Gaussian-major pair slot of every (view, Gaussian)
   float3* part;           // per-pair partial 2D gradients, 3 float3 per slot
   float* tilepart;
   // work items (see make_items) and the split-tile accumulator
@@ -163,9 +163,8 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
   c.tx = local % cam->tiles_x;
   c.ty = local / cam->tiles_x;
   c.n = a.n;
-  const int64_t hb = cam->hist_base + static_cast<int64_t>(local) * a.nblk;
   const uint64_t cap = static_cast<uint64_t>(a.capacity);
-  uint64_t s = a.hist[hb], e = a.hist[hb + a.nblk];
+  uint64_t s = a.tile_start[lo], e = a.tile_start[lo + 1];
   s = s < cap ? s : cap;
   e = e < cap ? e : cap;
   if (e < s) e = s;
@@ -473,7 +472,12 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
         v9[j] = s_acc[j][k];
         s_acc[j][k] = 0.f;
       }
-      const uint32_t sl = a.slot[b + k];
+      // slot = the Gaussian's first slot + this tile's row-major index in
+      // its tile rectangle (the order in which binning enumerated its pairs)
+      const int64_t g = static_cast<int64_t>(c.v) * c.n + s_id[k];
+      const uint2 rc = a.rect[g];
+      const uint32_t rx0 = rc.x & 0xffffu, rw = (rc.x >> 16) - rx0, ry0 = rc.y & 0xffffu;
+      const uint32_t sl = a.goff[g] + (static_cast<uint32_t>(c.ty) - ry0) * rw + (static_cast<uint32_t>(c.tx) - rx0);
       if (sl < a.capacity) {
         float3* dst = a.part + 3 * static_cast<int64_t>(sl);
         dst[0] = make_float3(v9[0], v9[1], v9[2]);
@@ -503,14 +507,14 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   const PairView pv = pair_view(pairs, capacity);
   a.cams = at<DevCamera>(ws, L.off_cams);
   a.rec = at<SplatRec>(ws, L.off_rec);
-  a.hist = at<uint32_t>(ws, L.off_hist);
+  a.tile_start = at<uint32_t>(ws, L.off_tstart);
   a.ids = pv.ids;
-  a.slot = pv.slot;
+  a.rect = at<uint2>(ws, L.off_rect);
+  a.goff = at<uint32_t>(ws, L.off_goff);
   a.part = pv.part;
   a.n = L.n;
   a.capacity = capacity;
   a.nv = L.nv;
-  a.nblk = L.nblk;
   a.tau = P->tau;
   a.globals = globals;
   a.items = at<uint32_t>(ws, L.off_items);

@@ -10,7 +10,7 @@
 namespace wsr {
 
 constexpr int kWave = 64;
-constexpr int kBinChunk = 8192;       // Gaussians per binning block
+constexpr int kBinChunk = 2048;       // Gaussians per binning block
 constexpr int kTileChunk = 14336;     // tiles per binning LDS histogram (56 KB + static < 64 KB)
 constexpr int kScanItems = 4096;      // elements per scan block (256 threads x 16)
 constexpr int kRasterBatch = 256;     // splats staged in LDS per batch
@@ -28,7 +28,7 @@ struct DevCamera {
   int32_t tile_base;   // first global tile index of this view
   int32_t pad0;
   int64_t pix_base;    // first pixel of this view in the concatenated images
-  int64_t hist_base;   // first entry of this view in the (tile, block) count matrix
+  int64_t hist_base;   // first entry of this view in the (block, tile) count matrix
 };
 
 // Splat record written by the projection (48 bytes, three float4):
@@ -40,22 +40,20 @@ struct __align__(16) SplatRec {
 };
 
 // The caller's pair buffer (capacity entries of kPairBytes bytes): per
-// (tile, Gaussian) pair a 36-byte partial 2D gradient (written by the raster
-// backward at the pair's Gaussian-major slot), the Gaussian id at each
-// position of the per-tile lists, and the Gaussian-major slot of each
-// position.
-constexpr int64_t kPairBytes = 44;
+// (tile, Gaussian) pair a 36-byte partial 2D gradient, written by the raster
+// backward at the pair's Gaussian-major slot (the Gaussian's pair offset plus
+// the tile's row-major index inside the Gaussian's tile rectangle), and the
+// Gaussian id at each position of the per-tile lists.
+constexpr int64_t kPairBytes = 40;
 struct PairView {
   float3* part;        // [capacity][3] float3: (mu_x, mu_y, A) (B, C, r) (g, b, a)
   uint32_t* ids;       // [capacity]
-  uint32_t* slot;      // [capacity]
 };
 __host__ __device__ inline PairView pair_view(const void* pairs, int64_t capacity) {
   char* b = static_cast<char*>(const_cast<void*>(pairs));
   PairView v;
   v.part = reinterpret_cast<float3*>(b);
   v.ids = reinterpret_cast<uint32_t*>(b + 36 * capacity);
-  v.slot = reinterpret_cast<uint32_t*>(b + 40 * capacity);
   return v;
 }
 
@@ -78,7 +76,7 @@ struct Layout {
   int64_t hist_len = 0;      // entries of the count matrix (without the trailing total)
   int64_t scan_parts = 0;
   size_t off_cams = 0, off_flags = 0, off_rec = 0, off_rect = 0, off_hist = 0, off_scan = 0,
-         off_goff = 0, off_grad2d = 0, off_tilepart = 0, off_gpart = 0, off_items = 0, off_acc = 0;
+         off_goff = 0, off_grad2d = 0, off_tstart = 0, off_tilepart = 0, off_gpart = 0, off_items = 0, off_acc = 0;
   int64_t gpart_blocks = 0;
   size_t bytes = 0;
 };
