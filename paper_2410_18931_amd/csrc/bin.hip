@@ -154,7 +154,18 @@ __global__ __launch_bounds__(256) void column_scan(const DevCamera* cams, int32_
   const int64_t tiles_v = static_cast<int64_t>(cam.tiles_x) * cam.tiles_y;
   uint32_t* col = hist + cam.hist_base + (t - cam.tile_base);
   uint32_t run = 0;
-  for (int b = 0; b < nblk; ++b) {
+  int b = 0;
+  for (; b + 8 <= nblk; b += 8) {  // eight independent loads in flight
+    uint32_t c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = col[(b + k) * tiles_v];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      col[(b + k) * tiles_v] = run;
+      run += c[k];
+    }
+  }
+  for (; b < nblk; ++b) {
     const uint32_t c = col[b * tiles_v];
     col[b * tiles_v] = run;
     run += c;

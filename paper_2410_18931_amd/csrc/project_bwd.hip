@@ -269,34 +269,65 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
 
 // Sum of each (view, Gaussian)'s per-tile partial 2D gradients: its pairs
 // occupy a contiguous range of Gaussian-major slots.  A light kernel of its
-// own (high occupancy, several independent loads in flight per thread), so
-// the register-heavy chain below reads one 9-float gradient per slot.
+// own, so the register-heavy chain below reads one 9-float gradient per
+// slot.  A lane sums the range of its own Gaussian when it is short; a long
+// range (a splat covering many tiles) is summed by the whole wave, lanes
+// striding through it, so the largest splats do not form a serial tail.
+constexpr uint32_t kHeavySlots = 32;
+
+__device__ __forceinline__ void add3(float* g, int o, const float3 v) {
+  g[o] += v.x;
+  g[o + 1] += v.y;
+  g[o + 2] += v.z;
+}
+
 __global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, const float3* part, uint32_t capacity,
                                                          int64_t slots, float* grad2d, float* out_grad2d) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int lane = threadIdx.x % kWave;
+  uint32_t s0 = 0, s1 = 0;
+  if (k < slots) {
+    s0 = goff[k];
+    s1 = goff[k + 1];
+    s0 = s0 < capacity ? s0 : capacity;
+    s1 = s1 < capacity ? s1 : capacity;
+    if (s1 < s0) s1 = s0;
+  }
+  const bool heavy = s1 - s0 > kHeavySlots;
+  float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (!heavy) {
+    uint32_t j = s0;
+    for (; j + 2 <= s1; j += 2) {
+      const float3* p = part + 3 * static_cast<int64_t>(j);
+      const float3 x0 = p[0], x1 = p[1], x2 = p[2], y0 = p[3], y1 = p[4], y2 = p[5];
+      add3(g, 0, x0); add3(g, 3, x1); add3(g, 6, x2);
+      add3(g, 0, y0); add3(g, 3, y1); add3(g, 6, y2);
+    }
+    if (j < s1) {
+      const float3* p = part + 3 * static_cast<int64_t>(j);
+      add3(g, 0, p[0]); add3(g, 3, p[1]); add3(g, 6, p[2]);
+    }
+  }
+  // the wave sums its heavy Gaussians one after another
+  uint64_t hmask = __ballot(heavy);
+  while (hmask) {
+    const int src = __ffsll(static_cast<long long>(hmask)) - 1;
+    hmask &= hmask - 1;
+    const uint32_t h0 = __shfl(s0, src, kWave), h1 = __shfl(s1, src, kWave);
+    float w[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (uint32_t j = h0 + lane; j < h1; j += kWave) {
+      const float3* p = part + 3 * static_cast<int64_t>(j);
+      add3(w, 0, p[0]); add3(w, 3, p[1]); add3(w, 6, p[2]);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      float x = w[q];
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+      if (lane == src) g[q] = x;
+    }
+  }
   if (k >= slots) return;
-  uint32_t s0 = goff[k], s1 = goff[k + 1];
-  s0 = s0 < capacity ? s0 : capacity;
-  s1 = s1 < capacity ? s1 : capacity;
-  float3 a0 = make_float3(0.f, 0.f, 0.f), a1 = a0, a2 = a0;
-  float3 b0 = a0, b1 = a0, b2 = a0;
-  uint32_t j = s0;
-  for (; j + 1 < s1; j += 2) {
-    const float3* p = part + 3 * static_cast<int64_t>(j);
-    const float3 x0 = p[0], x1 = p[1], x2 = p[2], y0 = p[3], y1 = p[4], y2 = p[5];
-    a0.x += x0.x; a0.y += x0.y; a0.z += x0.z; a1.x += x1.x; a1.y += x1.y; a1.z += x1.z;
-    a2.x += x2.x; a2.y += x2.y; a2.z += x2.z;
-    b0.x += y0.x; b0.y += y0.y; b0.z += y0.z; b1.x += y1.x; b1.y += y1.y; b1.z += y1.z;
-    b2.x += y2.x; b2.y += y2.y; b2.z += y2.z;
-  }
-  if (j < s1) {
-    const float3* p = part + 3 * static_cast<int64_t>(j);
-    const float3 x0 = p[0], x1 = p[1], x2 = p[2];
-    a0.x += x0.x; a0.y += x0.y; a0.z += x0.z; a1.x += x1.x; a1.y += x1.y; a1.z += x1.z;
-    a2.x += x2.x; a2.y += x2.y; a2.z += x2.z;
-  }
-  const float g[9] = {a0.x + b0.x, a0.y + b0.y, a0.z + b0.z, a1.x + b1.x, a1.y + b1.y,
-                      a1.z + b1.z, a2.x + b2.x, a2.y + b2.y, a2.z + b2.z};
   float* d = grad2d + 9 * k;
 #pragma unroll
   for (int q = 0; q < 9; ++q) d[q] = g[q];
@@ -308,28 +339,34 @@ __global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, c
 
 // Final reduction of the global parameters: dL/dsigma, dL/dbeta from the
 // per-block partials, dL/dw_B and dL/dc_B from the per-tile partials.
-__global__ __launch_bounds__(256) void reduce_globals(const double* gpart, int64_t nblocks,
-                                                      const float* tilepart, int64_t ntiles, float* out) {
-  __shared__ double sh[256][6];
+__global__ __launch_bounds__(1024) void reduce_globals(const double* gpart, int64_t nblocks,
+                                                       const float* tilepart, int64_t ntiles, float* out) {
+  __shared__ double sh[16][6];
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t b = threadIdx.x; b < nblocks; b += 256) {
+  for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
     acc[0] += gpart[2 * b];
     acc[1] += gpart[2 * b + 1];
   }
-  for (int64_t t = threadIdx.x; t < ntiles; t += 256) {
+  for (int64_t t = threadIdx.x; t < ntiles; t += 1024) {
     acc[3] += tilepart[4 * t];
     acc[4] += tilepart[4 * t + 1];
     acc[5] += tilepart[4 * t + 2];
     acc[2] += tilepart[4 * t + 3];
   }
-  for (int k = 0; k < 6; ++k) sh[threadIdx.x][k] = acc[k];
-  __syncthreads();
-  for (int step = 128; step >= 1; step >>= 1) {
-    if (threadIdx.x < step)
-      for (int k = 0; k < 6; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + step][k];
-    __syncthreads();
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double x = acc[k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+    if (lane == 0) sh[wv][k] = x;
   }
-  if (threadIdx.x < 6) out[threadIdx.x] = static_cast<float>(sh[0][threadIdx.x]);
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += sh[w][threadIdx.x];
+    out[threadIdx.x] = static_cast<float>(t);
+  }
 }
 
 __global__ void fill_zero_kernel(uint32_t* p, int64_t words) {
@@ -402,7 +439,7 @@ hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const fl
     e = launch_fill_zero(gpart, 2 * sizeof(double), st);
   }
   if (e != hipSuccess) return e;
-  reduce_globals<<<1, 256, 0, st>>>(gpart, static_cast<int64_t>(blocks), at<float>(ws, L.off_tilepart),
+  reduce_globals<<<1, 1024, 0, st>>>(gpart, static_cast<int64_t>(blocks), at<float>(ws, L.off_tilepart),
                                     L.total_tiles, g->globals);
   return hipGetLastError();
 }

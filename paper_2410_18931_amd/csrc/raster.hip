@@ -19,13 +19,15 @@
 namespace wsr {
 namespace {
 
+// Every wave owns an 8x8 pixel block of the tile (one pixel per lane): tile 8
+// is one wave, tile 16 four, tile 32 sixteen.  Up to 256 records are staged
+// per batch.
 template <int T>
 struct TileGeom {
-  static constexpr int kThreads = T == 8 ? 64 : 256;
-  static constexpr int kWaves = kThreads / kWave;
-  static constexpr int kSub = T == 32 ? 16 : 8;        // wave block edge
-  static constexpr int kPpl = (kSub / 8) * (kSub / 8); // pixels per lane
-  static constexpr int kBatch = kThreads;              // records per LDS batch
+  static constexpr int kSub = 8;                       // wave block edge
+  static constexpr int kWaves = (T / 8) * (T / 8);
+  static constexpr int kThreads = kWaves * kWave;
+  static constexpr int kBatch = kThreads < 256 ? kThreads : 256;
 };
 
 // The support predicate and the Gaussian falloff.  Forward and backward
@@ -139,7 +141,7 @@ struct TileCtx {
   uint32_t k, nk;                 // item index within the tile, items of the tile
   int wave, lane;
   int bx0, by0;                   // first pixel of this wave's block
-  int px[TileGeom<T>::kPpl], py[TileGeom<T>::kPpl];
+  int px, py;                     // this lane's pixel
 };
 
 template <int T>
@@ -174,14 +176,10 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
   c.end = static_cast<uint32_t>(ee < e ? ee : e);
   c.wave = threadIdx.x / kWave;
   c.lane = threadIdx.x % kWave;
-  c.bx0 = c.tx * T + (G::kWaves == 4 ? (c.wave & 1) * G::kSub : 0);
-  c.by0 = c.ty * T + (G::kWaves == 4 ? (c.wave >> 1) * G::kSub : 0);
-  const int lx = c.lane & 7, ly = c.lane >> 3;
-#pragma unroll
-  for (int k = 0; k < G::kPpl; ++k) {
-    c.px[k] = c.bx0 + lx + 8 * (k & 1);
-    c.py[k] = c.by0 + ly + 8 * (k >> 1);
-  }
+  c.bx0 = c.tx * T + (c.wave % (T / 8)) * G::kSub;
+  c.by0 = c.ty * T + (c.wave / (T / 8)) * G::kSub;
+  c.px = c.bx0 + (c.lane & 7);
+  c.py = c.by0 + (c.lane >> 3);
   return true;
 }
 
@@ -193,7 +191,7 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
   using G = TileGeom<T>;
   __syncthreads();  // previous batch fully consumed
   const uint32_t j = b + threadIdx.x;
-  if (j < c.end) {
+  if (threadIdx.x < G::kBatch && j < c.end) {
     const uint32_t id = a.ids[j];
     s_id[threadIdx.x] = id;
     s_rec[threadIdx.x] = a.rec[static_cast<int64_t>(c.v) * c.n + id];
@@ -229,66 +227,54 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   const DevCamera* cam;
   if (!tile_setup<T>(a, c, cam)) return;
 
-  float nr[G::kPpl], ng[G::kPpl], nb[G::kPpl], dd[G::kPpl];
-  int cntp[G::kPpl];
-  float pcx[G::kPpl], pcy[G::kPpl];
-#pragma unroll
-  for (int k = 0; k < G::kPpl; ++k) {
-    nr[k] = ng[k] = nb[k] = dd[k] = 0.f;
-    cntp[k] = 0;
-    pcx[k] = static_cast<float>(c.px[k]) + 0.5f;
-    pcy[k] = static_cast<float>(c.py[k]) + 0.5f;
-  }
+  float nr = 0.f, ng = 0.f, nb = 0.f, dd = 0.f;
+  int cntp = 0;
+  const float pcx = static_cast<float>(c.px) + 0.5f;
+  const float pcy = static_cast<float>(c.py) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
     const int m = stage_and_cull<T>(a, c, b, s_rec, s_id, s_list);
     const uint16_t* list = s_list + c.wave * G::kBatch;
     for (int i = 0; i < m; ++i) {
       const SplatRec r = s_rec[list[i]];
-#pragma unroll
-      for (int k = 0; k < G::kPpl; ++k) {
-        float dx, dy;
-        const float q = pair_q(r, pcx[k], pcy[k], &dx, &dy);
-        if (q <= tau) {
-          const float al = r.r1.w * falloff(q);
-          nr[k] = fmaf(al, r.r2.x, nr[k]);
-          ng[k] = fmaf(al, r.r2.y, ng[k]);
-          nb[k] = fmaf(al, r.r2.z, nb[k]);
-          dd[k] += al;
-          if (COUNT) ++cntp[k];
-        }
+      float dx, dy;
+      const float q = pair_q(r, pcx, pcy, &dx, &dy);
+      if (q <= tau) {
+        const float al = r.r1.w * falloff(q);
+        nr = fmaf(al, r.r2.x, nr);
+        ng = fmaf(al, r.r2.y, ng);
+        nb = fmaf(al, r.r2.z, nb);
+        dd += al;
+        if (COUNT) ++cntp;
       }
     }
   }
+  if (c.px >= cam->width || c.py >= cam->height) return;
+  const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
+  if (COUNT) atomicAdd(a.out_count + pix, cntp);
+  if (c.nk > 1) {
+    // split tile: partial sums, normalised by raster_fwd_finalize
+    float* ac = a.acc + 4 * pix;
+    unsafeAtomicAdd(ac, nr);
+    unsafeAtomicAdd(ac + 1, ng);
+    unsafeAtomicAdd(ac + 2, nb);
+    unsafeAtomicAdd(ac + 3, dd);
+    return;
+  }
   const float wbg = a.globals[2];
   const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
-#pragma unroll
-  for (int k = 0; k < G::kPpl; ++k) {
-    if (c.px[k] >= cam->width || c.py[k] >= cam->height) continue;
-    const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py[k]) * cam->width + c.px[k];
-    if (COUNT) atomicAdd(a.out_count + pix, cntp[k]);
-    if (c.nk > 1) {
-      // split tile: partial sums, normalised by raster_fwd_finalize
-      float* ac = a.acc + 4 * pix;
-      unsafeAtomicAdd(ac, nr[k]);
-      unsafeAtomicAdd(ac + 1, ng[k]);
-      unsafeAtomicAdd(ac + 2, nb[k]);
-      unsafeAtomicAdd(ac + 3, dd[k]);
-      continue;
-    }
-    const float D = wbg + dd[k];
-    const float Nr = fmaf(bgr, wbg, nr[k]), Ng = fmaf(bgg, wbg, ng[k]), Nb = fmaf(bgb, wbg, nb[k]);
-    float Cr = bgr, Cg = bgg, Cb = bgb;
-    if (D != 0.f) {
-      Cr = Nr / D;
-      Cg = Ng / D;
-      Cb = Nb / D;
-    }
-    a.out_rgb[3 * pix] = Cr;
-    a.out_rgb[3 * pix + 1] = Cg;
-    a.out_rgb[3 * pix + 2] = Cb;
-    a.out_den[pix] = D;
+  const float D = wbg + dd;
+  const float Nr = fmaf(bgr, wbg, nr), Ng = fmaf(bgg, wbg, ng), Nb = fmaf(bgb, wbg, nb);
+  float Cr = bgr, Cg = bgg, Cb = bgb;
+  if (D != 0.f) {
+    Cr = Nr / D;
+    Cg = Ng / D;
+    Cb = Nb / D;
   }
+  a.out_rgb[3 * pix] = Cr;
+  a.out_rgb[3 * pix + 1] = Cg;
+  a.out_rgb[3 * pix + 2] = Cb;
+  a.out_den[pix] = D;
 }
 
 // Normalisation of the tiles whose list was split over several work items:
@@ -354,34 +340,29 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
   const float wbg = a.globals[2];
   const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
   float bacc[4] = {0.f, 0.f, 0.f, 0.f};  // dL/dc_B (rgb), dL/dw_B
-  // per-pixel factors of this lane's pixel(s); other lanes fetch them with
-  // v_readlane (wave-uniform lane index, no memory round trip)
-  float4 pdv[G::kPpl];
-#pragma unroll
-  for (int k = 0; k < G::kPpl; ++k) {
-    float4 pd = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (c.px[k] < cam->width && c.py[k] < cam->height) {
-      const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py[k]) * cam->width + c.px[k];
-      const float D = a.den[pix];
-      const float g0 = a.dL_drgb[3 * pix], g1 = a.dL_drgb[3 * pix + 1], g2 = a.dL_drgb[3 * pix + 2];
-      if (D != 0.f) {
-        const float iD = 1.f / D;
-        pd.x = g0 * iD;
-        pd.y = g1 * iD;
-        pd.z = g2 * iD;
-        pd.w = pd.x * a.rgb[3 * pix] + pd.y * a.rgb[3 * pix + 1] + pd.z * a.rgb[3 * pix + 2];
-        bacc[0] += wbg * pd.x;
-        bacc[1] += wbg * pd.y;
-        bacc[2] += wbg * pd.z;
-        bacc[3] += pd.x * bgr + pd.y * bgg + pd.z * bgb - pd.w;
-      } else {
-        // C is the background colour where the denominator vanishes
-        bacc[0] += g0;
-        bacc[1] += g1;
-        bacc[2] += g2;
-      }
+  // per-pixel factors of this lane's pixel; other lanes of the wave fetch
+  // them with v_readlane (wave-uniform lane index, no memory round trip)
+  float4 pd = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (c.px < cam->width && c.py < cam->height) {
+    const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
+    const float D = a.den[pix];
+    const float g0 = a.dL_drgb[3 * pix], g1 = a.dL_drgb[3 * pix + 1], g2 = a.dL_drgb[3 * pix + 2];
+    if (D != 0.f) {
+      const float iD = 1.f / D;
+      pd.x = g0 * iD;
+      pd.y = g1 * iD;
+      pd.z = g2 * iD;
+      pd.w = pd.x * a.rgb[3 * pix] + pd.y * a.rgb[3 * pix + 1] + pd.z * a.rgb[3 * pix + 2];
+      bacc[0] += wbg * pd.x;
+      bacc[1] += wbg * pd.y;
+      bacc[2] += wbg * pd.z;
+      bacc[3] += pd.x * bgr + pd.y * bgg + pd.z * bgb - pd.w;
+    } else {
+      // C is the background colour where the denominator vanishes
+      bacc[0] += g0;
+      bacc[1] += g1;
+      bacc[2] += g2;
     }
-    pdv[k] = pd;
   }
   for (int k = threadIdx.x; k < 9 * G::kBatch; k += G::kThreads) (&s_acc[0][0])[k] = 0.f;
 
@@ -409,21 +390,19 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
       for (int row = 0; row < G::kSub; ++row) {
         const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
         const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
-        const int lrow = (row & 7) * 8;
-        const int krow = (row >> 3) * 2;
+        const int lrow = row * 8;
         float S0 = 0.f, S1 = 0.f, S2 = 0.f;
 #pragma unroll
         for (int col = 0; col < G::kSub; ++col) {
           const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
           const float q = quad_form(A, B2dy, Cdy2, dx);
           if (valid && q <= tau) {
-            // pixel (row, col) of the block lives in lane (row%8)*8 + col%8, slot (row/8)*2 + col/8
-            const float4 pv = (G::kPpl == 1 || krow == 0) ? pdv[col >> 3] : pdv[(G::kPpl == 1 ? 0 : 2) + (col >> 3)];
-            const int src = lrow + (col & 7);
-            const float pdx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.x), src));
-            const float pdy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.y), src));
-            const float pdz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.z), src));
-            const float pdw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.w), src));
+            // pixel (row, col) of the block lives in lane row * 8 + col
+            const int src = lrow + col;
+            const float pdx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pd.x), src));
+            const float pdy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pd.y), src));
+            const float pdz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pd.z), src));
+            const float pdw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pd.w), src));
             const float Gq = falloff(q);
             const float al = amp * Gq;
             const float dLda = fmaf(pdx, cr, fmaf(pdy, cg, fmaf(pdz, cb, -pdw)));
