@@ -313,3 +313,56 @@ def test_capacity_overflow_is_reported_then_recovered():
     ctx.check()
     rgb, den = ctx.render_fwd(g)
     compare_image(to_views(ctx, rgb)[0], oracle.render(sc, cams[0], st, eta=AMB_ETA), label="after regrow")
+
+
+# ---------------------------------------------------------------- graphs and autotuning
+
+def _small_multiview():
+    sc, _, st = ws.make_scene("c3", n=30000)
+    rng = np.random.default_rng(11)
+    cams = []
+    for _ in range(3):
+        w = int(rng.integers(96, 193))
+        u = rng.standard_normal(3)
+        cams.append(ws.look_at_camera(u / np.linalg.norm(u) * rng.uniform(4, 6), w, int(round(9 * w / 16))))
+    return sc, cams, st
+
+
+def test_graph_replays_match_eager():
+    from paper_2410_18931_amd.graph import GraphStep
+    sc, cams, st = _small_multiview()
+    log("case: graph replay vs eager, views " + str([(c["width"], c["height"]) for c in cams]))
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    ctx_e = WSRContext(sc["means"].shape[1], cams, st)
+    rgb_e, den_e = ctx_e.forward(dev, g)
+    dL = torch.randn_like(rgb_e)
+    ge = ctx_e.render_bwd(dev, g, dL, rgb_e, den_e)
+    ctx_g = WSRContext(sc["means"].shape[1], cams, st)
+    step = GraphStep(ctx_g, dev, g, dL)
+    for rep in range(3):
+        step.replay()
+        torch.cuda.synchronize()
+        step.check()
+        assert (step.rgb - rgb_e).abs().max().item() <= 1e-5, rep
+        assert (step.den - den_e).abs().max().item() <= 1e-4 * den_e.abs().max().item(), rep
+        for k in ("means", "log_scales", "quats", "sh", "lc_v"):
+            d = (step.grads[k] - ge[k]).abs().max().item()
+            assert d <= 1e-4 * ge[k].abs().max().item(), (rep, k, d)
+        # eager work on the same device between replays
+        ctx_e.forward(dev, g)
+        torch.cuda.synchronize()
+
+
+def test_autotune_picks_a_tile_and_caches(tmp_path):
+    from paper_2410_18931_amd.autotune import autotune
+    sc, cams, st = _small_multiview()
+    log("case: autotune")
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    cache = str(tmp_path / "tune.json")
+    r1 = autotune(dev, cams, st, g, reps=3, cache=cache)
+    assert r1["tile"] in (8, 16, 32) and not r1["cached"]
+    assert set(r1["ms"]) == {"8", "16", "32"}
+    r2 = autotune(dev, cams, st, g, reps=3, cache=cache)
+    assert r2["cached"] and r2["tile"] == r1["tile"]
