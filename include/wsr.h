@@ -105,7 +105,16 @@ typedef struct {
     float dilation;            /* 0.3 */
     float near_z;              /* 0.2 */
     float opacity_offset;      /* 0.5; SH opacity mode only */
+    int32_t flags;             /* WSR_FLAG_* */
+    int32_t reserved_;
 } wsr_params;
+
+/* wsr_render_fwd writes the raw sums instead of the image: out_rgb receives
+ * sum_i c_i a_i and out_den sum_i a_i, without the background term.  Eq. 7
+ * is a sum over Gaussians, so renders of disjoint subsets of a scene add up:
+ * C = (c_B w_B + sum_shards N) / (w_B + sum_shards D).  This is how the path
+ * shards Gaussians across devices. */
+#define WSR_FLAG_UNNORMALISED 1
 
 /* Learnable global parameters, a DEVICE array of 6 floats:
  * [0] sigma, [1] beta (EXP only), [2] w_B, [3..5] c_B (RGB). */

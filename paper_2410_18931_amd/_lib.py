@@ -37,7 +37,11 @@ class WsrCamera(C.Structure):
 
 class WsrParams(C.Structure):
     _fields_ = [("weight_kind", C.c_int32), ("tile", C.c_int32), ("tau", C.c_float),
-                ("dilation", C.c_float), ("near_z", C.c_float), ("opacity_offset", C.c_float)]
+                ("dilation", C.c_float), ("near_z", C.c_float), ("opacity_offset", C.c_float),
+                ("flags", C.c_int32), ("reserved_", C.c_int32)]
+
+
+FLAG_UNNORMALISED = 1
 
 
 class WsrGrads(C.Structure):
@@ -112,6 +116,6 @@ def make_cameras(cams) -> "C.Array":
     return arr
 
 
-def make_params(settings) -> WsrParams:
+def make_params(settings, flags: int = 0) -> WsrParams:
     return WsrParams(WEIGHT_KINDS[settings.weight_kind], int(settings.tile), float(settings.tau),
-                     float(settings.dilation), float(settings.near), float(settings.opacity_offset))
+                     float(settings.dilation), float(settings.near), float(settings.opacity_offset), int(flags), 0)

@@ -104,6 +104,7 @@ struct RasterArgs {
   int64_t capacity;
   int32_t nv;
   float tau;
+  int32_t unnormalised;   // write the raw sums (no background, no division)
   const float* globals;
   // forward outputs
   float* out_rgb;
@@ -217,6 +218,32 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
   return m;
 }
 
+// Eq. 7 for one pixel from its sums (or the raw sums in unnormalised mode).
+__device__ __forceinline__ void write_pixel(const RasterArgs& a, int64_t pix, float nr, float ng, float nb,
+                                            float dd) {
+  if (a.unnormalised) {
+    a.out_rgb[3 * pix] = nr;
+    a.out_rgb[3 * pix + 1] = ng;
+    a.out_rgb[3 * pix + 2] = nb;
+    a.out_den[pix] = dd;
+    return;
+  }
+  const float wbg = a.globals[2];
+  const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
+  const float D = wbg + dd;
+  const float Nr = fmaf(bgr, wbg, nr), Ng = fmaf(bgg, wbg, ng), Nb = fmaf(bgb, wbg, nb);
+  float Cr = bgr, Cg = bgg, Cb = bgb;
+  if (D != 0.f) {
+    Cr = Nr / D;
+    Cg = Ng / D;
+    Cb = Nb / D;
+  }
+  a.out_rgb[3 * pix] = Cr;
+  a.out_rgb[3 * pix + 1] = Cg;
+  a.out_rgb[3 * pix + 2] = Cb;
+  a.out_den[pix] = D;
+}
+
 template <int T, bool COUNT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
@@ -261,20 +288,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
     unsafeAtomicAdd(ac + 3, dd);
     return;
   }
-  const float wbg = a.globals[2];
-  const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
-  const float D = wbg + dd;
-  const float Nr = fmaf(bgr, wbg, nr), Ng = fmaf(bgg, wbg, ng), Nb = fmaf(bgb, wbg, nb);
-  float Cr = bgr, Cg = bgg, Cb = bgb;
-  if (D != 0.f) {
-    Cr = Nr / D;
-    Cg = Ng / D;
-    Cb = Nb / D;
-  }
-  a.out_rgb[3 * pix] = Cr;
-  a.out_rgb[3 * pix + 1] = Cg;
-  a.out_rgb[3 * pix + 2] = Cb;
-  a.out_den[pix] = D;
+  write_pixel(a, pix, nr, ng, nb, dd);
 }
 
 // Normalisation of the tiles whose list was split over several work items:
@@ -288,8 +302,6 @@ __global__ __launch_bounds__(256) void raster_fwd_finalize(RasterArgs a) {
   const DevCamera& cam = a.cams[v];
   const int local = tile - cam.tile_base;
   const int tx = local % cam.tiles_x, ty = local / cam.tiles_x;
-  const float wbg = a.globals[2];
-  const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
   for (int q = threadIdx.x; q < T * T; q += 256) {
     const int px = tx * T + q % T, py = ty * T + q / T;
     if (px >= cam.width || py >= cam.height) continue;
@@ -297,18 +309,7 @@ __global__ __launch_bounds__(256) void raster_fwd_finalize(RasterArgs a) {
     float4* ac = reinterpret_cast<float4*>(a.acc) + pix;
     const float4 s = *ac;
     *ac = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float D = wbg + s.w;
-    const float Nr = fmaf(bgr, wbg, s.x), Ng = fmaf(bgg, wbg, s.y), Nb = fmaf(bgb, wbg, s.z);
-    float Cr = bgr, Cg = bgg, Cb = bgb;
-    if (D != 0.f) {
-      Cr = Nr / D;
-      Cg = Ng / D;
-      Cb = Nb / D;
-    }
-    a.out_rgb[3 * pix] = Cr;
-    a.out_rgb[3 * pix + 1] = Cg;
-    a.out_rgb[3 * pix + 2] = Cb;
-    a.out_den[pix] = D;
+    write_pixel(a, pix, s.x, s.y, s.z, s.w);
   }
 }
 
@@ -495,6 +496,7 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   a.capacity = capacity;
   a.nv = L.nv;
   a.tau = P->tau;
+  a.unnormalised = (P->flags & WSR_FLAG_UNNORMALISED) ? 1 : 0;
   a.globals = globals;
   a.items = at<uint32_t>(ws, L.off_items);
   a.total_tiles = L.total_tiles;

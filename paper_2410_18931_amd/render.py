@@ -145,14 +145,15 @@ class WSRContext:
     def check(self) -> None:
         _lib.check("wsr_check", self.lib.wsr_check(_ptr(self.ws), self.ws_bytes, _stream()))
 
-    def render_fwd(self, globals_: torch.Tensor, count: bool = False, out=None):
+    def render_fwd(self, globals_: torch.Tensor, count: bool = False, out=None, unnormalised: bool = False):
         if out is None:
             rgb = torch.empty((self.total_pixels, 3), dtype=torch.float32, device=self.device)
             den = torch.empty((self.total_pixels,), dtype=torch.float32, device=self.device)
         else:
             rgb, den = out
         cnt = torch.empty((self.total_pixels,), dtype=torch.int32, device=self.device) if count else None
-        st = self.lib.wsr_render_fwd(self.cams_c, self.nv, C.byref(self.params), self.n, _ptr(globals_),
+        params = _lib.make_params(self.settings, _lib.FLAG_UNNORMALISED) if unnormalised else self.params
+        st = self.lib.wsr_render_fwd(self.cams_c, self.nv, C.byref(params), self.n, _ptr(globals_),
                                      _ptr(self.ws), self.ws_bytes, _ptr(self.pairs), self.capacity,
                                      _ptr(rgb), _ptr(den), _ptr(cnt), _stream())
         _lib.check("wsr_render_fwd", st)
