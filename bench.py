@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes as C
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +36,38 @@ FWD_FLOPS_PER_PAIR = 20
 BWD_FLOPS_PER_PAIR = 48
 
 
+# HBM traffic of the dominant kernel, from `rocprofv3 --pmc FETCH_SIZE` and
+# `--pmc WRITE_SIZE` runs of this benchmark (KiB per dispatch), each scaled by
+# what the same counter reads for a plain device copy of known size
+# (`--calibrate-copy`).  Valid only for the kernel source it was measured on.
+TRAFFIC = {}
+
+
+def _source_sha(name: str) -> str:
+    path = os.path.join(ROOT, "paper_2410_18931_amd", "csrc", name)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_bytes(kernel: str):
+    t = TRAFFIC.get(kernel)
+    if not t or t["source_sha"] != _source_sha(t["source"]):
+        return None
+    return t["fetch_kib"] * 1024 / t["fetch_factor"] + t["write_kib"] * 1024 / t["write_factor"]
+
+
+def calibrate_copy(mb: int, reps: int = 5) -> None:
+    """A plain device copy of `mb` MiB, for scaling the HBM byte counters."""
+    import torch
+    n = mb * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,6 +79,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=24, help="image rows the CPU baseline renders")
     ap.add_argument("--graph", action="store_true", help="time replays of the whole step captured as one HIP graph")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this size (for scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -91,10 +126,14 @@ def cpu_baseline(scene, cams, settings, rows: int) -> dict:
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: the weighted-sum path here is a single-GPU build "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: this weighted-sum path is a single-GPU build; sharding "
+              "Gaussians over GPUs (one all-reduce of the unnormalised sums) is designed, not implemented",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -218,7 +257,8 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": {"kernel": f"{dominant} (raster_{'fwd' if dominant == 'raster_fwd' else 'bwd'}_kernel)",
                      "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": traffic_bytes(dominant),
                      "flops_per_pair": FWD_FLOPS_PER_PAIR if dominant == "raster_fwd" else BWD_FLOPS_PER_PAIR,
                      "launch_ms": round(stage_ms[dominant], 4)},
         "stage_hbm_gbs": {k: round(ab[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in names},
