@@ -40,7 +40,11 @@ BWD_FLOPS_PER_PAIR = 48
 # `--pmc WRITE_SIZE` runs of this benchmark (KiB per dispatch), each scaled by
 # what the same counter reads for a plain device copy of known size
 # (`--calibrate-copy`).  Valid only for the kernel source it was measured on.
-TRAFFIC = {}
+TRAFFIC = {
+    "raster_bwd": {"source": "raster.hip", "source_sha": "3ef59bc352188e86",
+                   "fetch_kib": 1323096.0, "write_kib": 490067.1,
+                   "fetch_factor": 262157.6 / 524288.0, "write_factor": 524288.0 / 524288.0},
+}
 
 
 def _source_sha(name: str) -> str:
@@ -77,7 +81,7 @@ def parse():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--config", default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=24, help="image rows the CPU baseline renders")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU baseline sample")
     ap.add_argument("--graph", action="store_true", help="time replays of the whole step captured as one HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this size (for scaling HBM byte counters)")
@@ -93,35 +97,39 @@ def algorithmic_bytes(n: int, pixels: int, storage: str, binned: int, nv: int = 
     return {
         "project": attr + n * nv * 56,                       # attributes in, 2D record + rect out
         "bin": n * nv * 16 + binned * 4,                     # rects read twice, ids written
-        "raster_fwd": pixels * 16,                           # colour + denominator out
-        "raster_bwd": pixels * 28,                           # dL/dC, C, D in
+        "raster_fwd": n * nv * 48 + pixels * 16,             # 2D records in, colour + denominator out
+        "raster_bwd": n * nv * (48 + 36) + pixels * 28,      # 2D records, dL/dC, C, D in; 2D gradients out
         "project_bwd": attr + n * nv * 36 + grads,           # attributes + 2D grads in, grads out
         "step": 2 * attr + grads + pixels * 44,
     }
 
 
-def cpu_baseline(scene, cams, settings, rows: int) -> dict:
-    """The FP64 reference checker as it stands, on a bounded sample: `rows`
-    image rows in 6 evenly spaced strips, forward + backward, extrapolated to
-    a full frame by the pixel ratio."""
+def cpu_baseline(scene, cams, settings, seconds: float) -> dict:
+    """The FP64 reference checker as it stands, on a bounded sample of the
+    same frame: full-width strips of 4 rows, visited in a seeded random order,
+    forward + backward, until `seconds` have passed (at least one strip);
+    frames/s = sampled fraction of the frame / time."""
     import oracle
     cam = cams[0]
     H, W = int(cam["height"]), int(cam["width"])
-    nstrips = 6
-    h = max(1, rows // nstrips)
-    ys = np.linspace(0, H - h, nstrips).astype(int)
-    rng = np.random.default_rng(0)
+    h = 4
+    order = np.random.default_rng(0).permutation(np.arange(0, H - h + 1, h))
+    rng = np.random.default_rng(1)
+    done = 0
     t0 = time.perf_counter()
-    for y in ys:
+    for y in order:
         crop = (0, int(y), W, int(y) + h)
         oracle.render(scene, cam, settings, crop=crop)
         oracle.render_bwd(scene, cam, settings, rng.standard_normal((h, W, 3)), crop=crop)
+        done += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
     dt = time.perf_counter() - t0
-    frac = nstrips * h / H
+    frac = done * h / H
     return {"value": frac / dt, "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 C checker (strict all-pairs mode), forward+backward on {nstrips} full-width strips of "
-                      f"{h} rows ({nstrips * h} of {H} rows) of the same frame, {dt:.1f} s; frames/s = "
-                      f"sampled fraction / time"}
+            "sample": f"FP64 C checker (strict all-pairs mode), forward+backward on {done} full-width strips of "
+                      f"{h} rows ({done * h} of {H} rows, seeded random positions) of the same frame, "
+                      f"{dt:.1f} s; frames/s = sampled fraction / time"}
 
 
 def main():
@@ -260,12 +268,12 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": traffic_bytes(dominant),
                      "flops_per_pair": FWD_FLOPS_PER_PAIR if dominant == "raster_fwd" else BWD_FLOPS_PER_PAIR,
-                     "launch_ms": round(stage_ms[dominant], 4)},
+                     "launch_ms": round(stage_ms[dominant], 4), "algorithmic_bytes": ab[dominant]},
         "stage_hbm_gbs": {k: round(ab[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in names},
     }
     if not args.no_cpu_baseline:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(scene, cams, st, args.cpu_rows)
+        out["cpu_baseline"] = cpu_baseline(scene, cams, st, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

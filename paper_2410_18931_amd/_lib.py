@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libwsr.so")
+# WSR_LIB may point at another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("WSR_LIB", os.path.join(_PKG, "libwsr.so"))
 
 WSR_OK, WSR_ERR_INVALID, WSR_ERR_WORKSPACE, WSR_ERR_CAPACITY, WSR_ERR_HIP = range(5)
 WEIGHT_KINDS = {"dir": 0, "exp": 1, "lc": 2}

@@ -16,6 +16,11 @@
 // the backward recomputes every pair.
 #include "wsr_internal.h"
 
+// Records staged per backward batch, as a multiple of the forward's (build-time tunable).
+#ifndef WSR_BWD_BATCH_MULT
+#define WSR_BWD_BATCH_MULT 1
+#endif
+
 namespace wsr {
 namespace {
 
@@ -28,6 +33,9 @@ struct TileGeom {
   static constexpr int kWaves = (T / 8) * (T / 8);
   static constexpr int kThreads = kWaves * kWave;
   static constexpr int kBatch = kThreads < 256 ? kThreads : 256;
+  // the backward fills 64-lane chunks from each wave's culled list, so it
+  // stages larger batches to keep the chunks full
+  static constexpr int kBatchBwd = WSR_BWD_BATCH_MULT * kBatch;
 };
 
 // The support predicate and the Gaussian falloff.  Forward and backward
@@ -186,20 +194,22 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
 
 // Stage one batch of records into LDS and build this wave's culled list.
 // Returns the list length.
-template <int T>
+template <int T, int BATCH>
 __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
                                               SplatRec* s_rec, uint32_t* s_id, uint16_t* s_list) {
   using G = TileGeom<T>;
   __syncthreads();  // previous batch fully consumed
-  const uint32_t j = b + threadIdx.x;
-  if (threadIdx.x < G::kBatch && j < c.end) {
-    const uint32_t id = a.ids[j];
-    s_id[threadIdx.x] = id;
-    s_rec[threadIdx.x] = a.rec[static_cast<int64_t>(c.v) * c.n + id];
+  for (int q = threadIdx.x; q < BATCH; q += G::kThreads) {
+    const uint32_t j = b + q;
+    if (j < c.end) {
+      const uint32_t id = a.ids[j];
+      s_id[q] = id;
+      s_rec[q] = a.rec[static_cast<int64_t>(c.v) * c.n + id];
+    }
   }
   __syncthreads();
-  const int cnt = static_cast<int>(min(static_cast<uint32_t>(G::kBatch), c.end - b));
-  uint16_t* list = s_list + c.wave * G::kBatch;
+  const int cnt = static_cast<int>(min(static_cast<uint32_t>(BATCH), c.end - b));
+  uint16_t* list = s_list + c.wave * BATCH;
   int m = 0;
   const float bx = c.bx0 + 0.5f, by = c.by0 + 0.5f;
   for (int k0 = 0; k0 < cnt; k0 += kWave) {
@@ -260,10 +270,12 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   const float pcy = static_cast<float>(c.py) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T>(a, c, b, s_rec, s_id, s_list);
+    const int m = stage_and_cull<T, G::kBatch>(a, c, b, s_rec, s_id, s_list);
     const uint16_t* list = s_list + c.wave * G::kBatch;
-    for (int i = 0; i < m; ++i) {
-      const SplatRec r = s_rec[list[i]];
+    // four splats per step: one 8-byte read fetches their list entries and
+    // all four records are requested before any arithmetic, so LDS latency
+    // is paid once per four splats
+    auto accumulate = [&](const SplatRec& r) {
       float dx, dy;
       const float q = pair_q(r, pcx, pcy, &dx, &dy);
       if (q <= tau) {
@@ -274,7 +286,20 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
         dd += al;
         if (COUNT) ++cntp;
       }
+    };
+    int i = 0;
+    for (; i + 4 <= m; i += 4) {
+      const uint2 k4 = *reinterpret_cast<const uint2*>(list + i);
+      const SplatRec r0 = s_rec[k4.x & 0xffffu];
+      const SplatRec r1 = s_rec[k4.x >> 16];
+      const SplatRec r2 = s_rec[k4.y & 0xffffu];
+      const SplatRec r3 = s_rec[k4.y >> 16];
+      accumulate(r0);
+      accumulate(r1);
+      accumulate(r2);
+      accumulate(r3);
     }
+    for (; i < m; ++i) accumulate(s_rec[list[i]]);
   }
   if (c.px >= cam->width || c.py >= cam->height) return;
   const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
@@ -323,16 +348,18 @@ __device__ __forceinline__ float wave_sum(float x) {
 // lane owns one splat of the wave's culled list and walks the wave's pixel
 // block, so a splat's nine gradient sums stay in one lane's registers (no
 // cross-lane reduction).  The waves of a tile merge their per-splat partials
-// with LDS float atomics; each (tile, splat) then issues one global atomic per
-// value.  Per-pixel factors gbar = dL/dC / D and s = gbar . C are staged in LDS
-// and read as wave-uniform broadcasts.
+// with LDS float atomics; each (tile, splat) pair then stores its nine sums
+// with plain stores at the pair's Gaussian-major slot.  Per-pixel factors
+// gbar = dL/dC / D and s = gbar . C stay in the registers of the pixel's lane
+// and reach the other lanes through v_readlane (a wave-uniform lane index).
 template <int T>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
-  __shared__ SplatRec s_rec[G::kBatch];
-  __shared__ uint32_t s_id[G::kBatch];
-  __shared__ uint16_t s_list[G::kWaves * G::kBatch];
-  __shared__ float s_acc[9][G::kBatch];
+  constexpr int kB = G::kBatchBwd;
+  __shared__ SplatRec s_rec[kB];
+  __shared__ uint32_t s_id[kB];
+  __shared__ uint16_t s_list[G::kWaves * kB];
+  __shared__ float s_acc[9][kB];
   __shared__ float s_bg[G::kWaves][4];
   TileCtx<T> c;
   const DevCamera* cam;
@@ -365,12 +392,12 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
       bacc[2] += g2;
     }
   }
-  for (int k = threadIdx.x; k < 9 * G::kBatch; k += G::kThreads) (&s_acc[0][0])[k] = 0.f;
+  for (int k = threadIdx.x; k < 9 * kB; k += G::kThreads) (&s_acc[0][0])[k] = 0.f;
 
   const float tau = a.tau;
-  for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T>(a, c, b, s_rec, s_id, s_list);
-    const uint16_t* list = s_list + c.wave * G::kBatch;
+  for (uint32_t b = c.start; b < c.end; b += kB) {
+    const int m = stage_and_cull<T, kB>(a, c, b, s_rec, s_id, s_list);
+    const uint16_t* list = s_list + c.wave * kB;
     for (int c0 = 0; c0 < m; c0 += kWave) {
       const int j = c0 + c.lane;
       const bool valid = j < m;
@@ -444,7 +471,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
     // one plain store per (tile, splat) pair, at the pair's Gaussian-major
     // slot (every pair of the batch is written, zeros included, so the
     // projection backward can sum each Gaussian's slot range blindly)
-    const int cnt = static_cast<int>(min(static_cast<uint32_t>(G::kBatch), c.end - b));
+    const int cnt = static_cast<int>(min(static_cast<uint32_t>(kB), c.end - b));
     for (int k = threadIdx.x; k < cnt; k += G::kThreads) {
       float v9[9];
 #pragma unroll
