@@ -65,7 +65,7 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   size_t off = 0;
   L->off_cams = off;     off = align256(off + sizeof(DevCamera) * WSR_MAX_VIEWS);
   L->off_flags = off;    off = align256(off + sizeof(DevFlags));
-  L->off_rec = off;      off = align256(off + sizeof(SplatRec) * slots);
+  L->off_rec = off;      off = align256(off + sizeof(DevSplat) * slots);
   L->off_rect = off;     off = align256(off + sizeof(uint2) * slots);
   L->off_hist = off;     off = align256(off + sizeof(uint32_t) * (hist + 1));
   L->off_scan = off;     off = align256(off + sizeof(uint32_t) * L->scan_parts);
@@ -76,6 +76,7 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   L->off_gpart = off;    off = align256(off + sizeof(double) * 2 * L->gpart_blocks);
   L->off_items = off;    off = align256(off + sizeof(uint32_t) * (tiles + 1));
   L->off_acc = off;      off = align256(off + sizeof(float) * 4 * pixels);
+  L->off_pd = off;       off = align256(off + sizeof(float) * 4 * tiles * tile * tile);
   L->bytes = off;
   return true;
 }

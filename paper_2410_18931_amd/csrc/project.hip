@@ -27,7 +27,7 @@ struct ProjArgs {
   const float* lc_v;
   const float* globals;
   const DevCamera* cams;
-  SplatRec* rec;
+  DevSplat* rec;
   uint2* rect;
   float* out_proj;
   int64_t n;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
       r.r1 = make_float4(static_cast<float>(g.C), static_cast<float>(ox), static_cast<float>(oy), u * w);
       const uint32_t ext = half_bits_up(static_cast<float>(ex)) | (half_bits_up(static_cast<float>(ey)) << 16);
       r.r2 = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(ext));
-      a.rec[slot] = r;
+      a.rec[slot].s = r;
     }
     a.rect[slot] = rect;
     if (a.out_proj) {
@@ -197,7 +197,7 @@ hipError_t launch_project(const wsr_scene* sc, const wsr_params* P, const float*
   a.lc_v = sc->lc_v;
   a.globals = globals;
   a.cams = at<DevCamera>(ws, L.off_cams);
-  a.rec = at<SplatRec>(ws, L.off_rec);
+  a.rec = at<DevSplat>(ws, L.off_rec);
   a.rect = at<uint2>(ws, L.off_rect);
   a.out_proj = out_proj;
   a.n = L.n;

@@ -16,11 +16,6 @@
 // the backward recomputes every pair.
 #include "wsr_internal.h"
 
-// Records staged per backward batch, as a multiple of the forward's (build-time tunable).
-#ifndef WSR_BWD_BATCH_MULT
-#define WSR_BWD_BATCH_MULT 1
-#endif
-
 namespace wsr {
 namespace {
 
@@ -33,9 +28,7 @@ struct TileGeom {
   static constexpr int kWaves = (T / 8) * (T / 8);
   static constexpr int kThreads = kWaves * kWave;
   static constexpr int kBatch = kThreads < 256 ? kThreads : 256;
-  // the backward fills 64-lane chunks from each wave's culled list, so it
-  // stages larger batches to keep the chunks full
-  static constexpr int kBatchBwd = WSR_BWD_BATCH_MULT * kBatch;
+  static_assert(kBatch <= 256, "culled lists hold 8-bit record indices");
 };
 
 // The support predicate and the Gaussian falloff.  Forward and backward
@@ -105,7 +98,7 @@ __device__ __forceinline__ bool block_hits(const SplatRec& r, float bx, float by
 
 struct RasterArgs {
   const DevCamera* cams;
-  const SplatRec* rec;
+  const DevSplat* rec;
   const uint32_t* tile_start;  // start of every tile's id list
   const uint32_t* ids;
   int64_t n;
@@ -122,8 +115,6 @@ struct RasterArgs {
   const float* dL_drgb;
   const float* rgb;
   const float* den;
-  const uint2* rect;      // tile rectangle of every (view, Gaussian)
-  const uint32_t* goff;   // first Gaussian-major pair slot of every (view, Gaussian)
   float3* part;           // per-pair partial 2D gradients, 3 float3 per slot
   float* tilepart;
   // work items (see make_items) and the split-tile accumulator
@@ -193,23 +184,30 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
 }
 
 // Stage one batch of records into LDS and build this wave's culled list.
-// Returns the list length.
-template <int T, int BATCH>
+// Returns the list length.  With SLOTS, also the Gaussian-major slot of each
+// staged (tile, splat) pair: the Gaussian's first slot plus this tile's
+// row-major index in its tile rectangle (the order in which binning
+// enumerated its pairs).
+template <int T, int BATCH, bool SLOTS>
 __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
-                                              SplatRec* s_rec, uint32_t* s_id, uint16_t* s_list) {
+                                              SplatRec* s_rec, uint32_t* s_slot, uint8_t* s_list) {
   using G = TileGeom<T>;
   __syncthreads();  // previous batch fully consumed
   for (int q = threadIdx.x; q < BATCH; q += G::kThreads) {
     const uint32_t j = b + q;
     if (j < c.end) {
-      const uint32_t id = a.ids[j];
-      s_id[q] = id;
-      s_rec[q] = a.rec[static_cast<int64_t>(c.v) * c.n + id];
+      const DevSplat* d = a.rec + static_cast<int64_t>(c.v) * c.n + a.ids[j];
+      s_rec[q] = d->s;
+      if (SLOTS) {
+        const uint4 sl = d->slot;
+        const uint32_t rx0 = sl.y & 0xffffu, rw = (sl.y >> 16) - rx0, ry0 = sl.z & 0xffffu;
+        s_slot[q] = sl.x + (static_cast<uint32_t>(c.ty) - ry0) * rw + (static_cast<uint32_t>(c.tx) - rx0);
+      }
     }
   }
   __syncthreads();
   const int cnt = static_cast<int>(min(static_cast<uint32_t>(BATCH), c.end - b));
-  uint16_t* list = s_list + c.wave * BATCH;
+  uint8_t* list = s_list + c.wave * BATCH;
   int m = 0;
   const float bx = c.bx0 + 0.5f, by = c.by0 + 0.5f;
   for (int k0 = 0; k0 < cnt; k0 += kWave) {
@@ -218,7 +216,7 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
     const uint64_t mask = __ballot(hit);
     if (hit) {
       const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
-      list[pos] = static_cast<uint16_t>(k);
+      list[pos] = static_cast<uint8_t>(k);
     }
     m += __popcll(mask);
   }
@@ -258,8 +256,7 @@ template <int T, bool COUNT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
   __shared__ SplatRec s_rec[G::kBatch];
-  __shared__ uint32_t s_id[G::kBatch];
-  __shared__ uint16_t s_list[G::kWaves * G::kBatch];
+  __shared__ __align__(16) uint8_t s_list[G::kWaves * G::kBatch];
   TileCtx<T> c;
   const DevCamera* cam;
   if (!tile_setup<T>(a, c, cam)) return;
@@ -270,30 +267,28 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   const float pcy = static_cast<float>(c.py) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T, G::kBatch>(a, c, b, s_rec, s_id, s_list);
-    const uint16_t* list = s_list + c.wave * G::kBatch;
-    // four splats per step: one 8-byte read fetches their list entries and
+    const int m = stage_and_cull<T, G::kBatch, false>(a, c, b, s_rec, nullptr, s_list);
+    const uint8_t* list = s_list + c.wave * G::kBatch;
+    // four splats per step: one 4-byte read fetches their list entries and
     // all four records are requested before any arithmetic, so LDS latency
     // is paid once per four splats
     auto accumulate = [&](const SplatRec& r) {
       float dx, dy;
       const float q = pair_q(r, pcx, pcy, &dx, &dy);
-      if (q <= tau) {
-        const float al = r.r1.w * falloff(q);
-        nr = fmaf(al, r.r2.x, nr);
-        ng = fmaf(al, r.r2.y, ng);
-        nb = fmaf(al, r.r2.z, nb);
-        dd += al;
-        if (COUNT) ++cntp;
-      }
+      const float al = q <= tau ? r.r1.w * falloff(q) : 0.f;
+      nr = fmaf(al, r.r2.x, nr);
+      ng = fmaf(al, r.r2.y, ng);
+      nb = fmaf(al, r.r2.z, nb);
+      dd += al;
+      if (COUNT) cntp += q <= tau ? 1 : 0;
     };
     int i = 0;
     for (; i + 4 <= m; i += 4) {
-      const uint2 k4 = *reinterpret_cast<const uint2*>(list + i);
-      const SplatRec r0 = s_rec[k4.x & 0xffffu];
-      const SplatRec r1 = s_rec[k4.x >> 16];
-      const SplatRec r2 = s_rec[k4.y & 0xffffu];
-      const SplatRec r3 = s_rec[k4.y >> 16];
+      const uint32_t k4 = *reinterpret_cast<const uint32_t*>(list + i);
+      const SplatRec r0 = s_rec[k4 & 0xffu];
+      const SplatRec r1 = s_rec[(k4 >> 8) & 0xffu];
+      const SplatRec r2 = s_rec[(k4 >> 16) & 0xffu];
+      const SplatRec r3 = s_rec[k4 >> 24];
       accumulate(r0);
       accumulate(r1);
       accumulate(r2);
@@ -344,35 +339,125 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
-// Backward: the same staging and per-wave culling as the forward, but each
-// lane owns one splat of the wave's culled list and walks the wave's pixel
-// block, so a splat's nine gradient sums stay in one lane's registers (no
-// cross-lane reduction).  The waves of a tile merge their per-splat partials
-// with LDS float atomics; each (tile, splat) pair then stores its nine sums
-// with plain stores at the pair's Gaussian-major slot.  Per-pixel factors
-// gbar = dL/dC / D and s = gbar . C stay in the registers of the pixel's lane
-// and reach the other lanes through v_readlane (a wave-uniform lane index).
-template <int T>
-__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(RasterArgs a) {
-  using G = TileGeom<T>;
-  constexpr int kB = G::kBatchBwd;
-  __shared__ SplatRec s_rec[kB];
-  __shared__ uint32_t s_id[kB];
-  __shared__ uint16_t s_list[G::kWaves * kB];
-  __shared__ float s_acc[9][kB];
-  __shared__ float s_bg[G::kWaves][4];
-  TileCtx<T> c;
-  const DevCamera* cam;
-  if (!tile_setup<T>(a, c, cam)) return;
+// One chunk of the backward for one wave: up to 64 / K splats of the wave's
+// culled list, each walked by K lanes that take 8 / K pixel rows of the
+// wave's block apiece.  K = 1 for full chunks; a list's last, partly filled
+// chunk uses K = 2, 4 or 8 so that a short remainder still keeps most lanes
+// busy.
+//
+// Per splat the lanes sum over their pixels, with G = exp(-q/2) and
+// e = G dL/da: per row S0 = sum e, S1 = sum e dx and S2 = sum e dx^2 (three
+// FMAs a pixel), folded with dy once per row into the moments Mx = sum e dx,
+// My = sum e dy, Mxx = sum e dx^2, Mxy = sum e dx dy, Myy = sum e dy^2; and
+// sum G gbar.  The splat's amplitude multiplies them once at the end.  The K
+// lanes of a splat add their sums with lane shuffles and one of them merges
+// the result into the tile's LDS accumulator.
+//
+// The per-pixel factors (gbar, s) of the wave's block come from the prepass
+// (raster_bwd_prep).  With K = 1 every lane walks the same pixel at the same
+// time, so they are read with scalar loads at a wave-uniform address and
+// enter the FMAs as scalar operands; with K > 1 the lanes walk different
+// rows and read them with vector loads (the wave's 1 KB stays in L1).
+template <int T, int K, int B>
+__device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
+                                          const SplatRec* s_rec, const float4* __restrict__ pd_wave,
+                                          float (*s_acc)[B], float tau) {
+  constexpr int kRows = 8 / K;
+  const int jj = c.lane / K, sub = c.lane % K;
+  const int j = c0 + jj;
+  const bool valid = j < m;
+  const int kr = valid ? list[j] : 0;
+  const SplatRec r = s_rec[kr];
+  const float amp = r.r1.w, cr = r.r2.x, cg = r.r2.y, cb = r.r2.z;
+  float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+  float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
+  const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
+  // first pixel centre of the block relative to the splat's integer origin
+  // (exact), so dx = (ex0 + col) - fx matches the forward's
+  const float ex0 = (static_cast<float>(c.bx0) + 0.5f) - r.r1.y;
+  const float ey0 = (static_cast<float>(c.by0) + 0.5f) - r.r1.z;
+#pragma unroll 1
+  for (int rr = 0; rr < kRows; ++rr) {
+    const int row = sub * kRows + rr;
+    const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
+    const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
+    float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+#pragma unroll
+    for (int col = 0; col < 8; ++col) {
+      const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
+      const float q = quad_form(A, B2dy, Cdy2, dx);
+      {
+        // with K = 1 the address is wave-uniform: a scalar load into SGPRs
+        const float4 pd = pd_wave[row * 8 + col];
+        const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
+        const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
+        const float e = Gq * dLda;
+        S0 += e;
+        S1 = fmaf(e, dx, S1);
+        S2 = fmaf(e, dx * dx, S2);
+        g_r = fmaf(Gq, pd.x, g_r);
+        g_g = fmaf(Gq, pd.y, g_g);
+        g_b = fmaf(Gq, pd.z, g_b);
+      }
+    }
+    g_amp += S0;
+    Mx += S1;
+    My = fmaf(dy, S0, My);
+    Mxx += S2;
+    Mxy = fmaf(dy, S1, Mxy);
+    Myy = fmaf(dy * dy, S0, Myy);
+  }
+#pragma unroll
+  for (int d = 1; d < K; d <<= 1) {
+    Mx += __shfl_xor(Mx, d, kWave);
+    My += __shfl_xor(My, d, kWave);
+    Mxx += __shfl_xor(Mxx, d, kWave);
+    Mxy += __shfl_xor(Mxy, d, kWave);
+    Myy += __shfl_xor(Myy, d, kWave);
+    g_r += __shfl_xor(g_r, d, kWave);
+    g_g += __shfl_xor(g_g, d, kWave);
+    g_b += __shfl_xor(g_b, d, kWave);
+    g_amp += __shfl_xor(g_amp, d, kWave);
+  }
+  if (valid && sub == 0) {
+    // the sums above leave out the splat's constant amplitude (a = amp G):
+    // dq = -amp e / 2, and with q = A dx^2 + B2 dx dy + C dy^2, dx = px - mu_x,
+    // dL/dmu_x = -sum dq (2A dx + B2 dy) = amp (A Mx + (B2/2) My), and so on;
+    // dL/dc = amp sum G gbar, dL/damp = sum G dL/da
+    atomicAdd(&s_acc[0][kr], amp * (A * Mx + 0.5f * B2 * My));
+    atomicAdd(&s_acc[1][kr], amp * (0.5f * B2 * Mx + Cc * My));
+    atomicAdd(&s_acc[2][kr], -0.5f * amp * Mxx);
+    atomicAdd(&s_acc[3][kr], -amp * Mxy);
+    atomicAdd(&s_acc[4][kr], -0.5f * amp * Myy);
+    atomicAdd(&s_acc[5][kr], amp * g_r);
+    atomicAdd(&s_acc[6][kr], amp * g_g);
+    atomicAdd(&s_acc[7][kr], amp * g_b);
+    atomicAdd(&s_acc[8][kr], g_amp);
+  }
+}
 
+// Backward prepass, one workgroup per tile: the per-pixel factors
+// gbar = dL/dC / D and s = gbar . C (zero outside the image), stored padded to
+// whole tiles in the order the raster backward walks them
+// ([tile][wave block][row * 8 + col], i.e. thread order), and the tile's
+// partial sums of the background gradients dL/dc_B and dL/dw_B.
+template <int T>
+__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterArgs a, float4* pdg) {
+  using G = TileGeom<T>;
+  __shared__ float s_bg[G::kWaves][4];
+  const int tile = static_cast<int>(blockIdx.x);
+  const int v = find_view(a.cams, a.nv, tile);
+  const DevCamera& cam = a.cams[v];
+  const int local = tile - cam.tile_base;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int px = (local % cam.tiles_x) * T + (wave % (T / 8)) * 8 + (lane & 7);
+  const int py = (local / cam.tiles_x) * T + (wave / (T / 8)) * 8 + (lane >> 3);
   const float wbg = a.globals[2];
   const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
   float bacc[4] = {0.f, 0.f, 0.f, 0.f};  // dL/dc_B (rgb), dL/dw_B
-  // per-pixel factors of this lane's pixel; other lanes of the wave fetch
-  // them with v_readlane (wave-uniform lane index, no memory round trip)
   float4 pd = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (c.px < cam->width && c.py < cam->height) {
-    const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
+  if (px < cam.width && py < cam.height) {
+    const int64_t pix = cam.pix_base + static_cast<int64_t>(py) * cam.width + px;
     const float D = a.den[pix];
     const float g0 = a.dL_drgb[3 * pix], g1 = a.dL_drgb[3 * pix + 1], g2 = a.dL_drgb[3 * pix + 2];
     if (D != 0.f) {
@@ -381,91 +466,72 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
       pd.y = g1 * iD;
       pd.z = g2 * iD;
       pd.w = pd.x * a.rgb[3 * pix] + pd.y * a.rgb[3 * pix + 1] + pd.z * a.rgb[3 * pix + 2];
-      bacc[0] += wbg * pd.x;
-      bacc[1] += wbg * pd.y;
-      bacc[2] += wbg * pd.z;
-      bacc[3] += pd.x * bgr + pd.y * bgg + pd.z * bgb - pd.w;
+      bacc[0] = wbg * pd.x;
+      bacc[1] = wbg * pd.y;
+      bacc[2] = wbg * pd.z;
+      bacc[3] = pd.x * bgr + pd.y * bgg + pd.z * bgb - pd.w;
     } else {
       // C is the background colour where the denominator vanishes
-      bacc[0] += g0;
-      bacc[1] += g1;
-      bacc[2] += g2;
+      bacc[0] = g0;
+      bacc[1] = g1;
+      bacc[2] = g2;
     }
   }
+  pdg[static_cast<int64_t>(tile) * G::kThreads + threadIdx.x] = pd;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float sj = wave_sum(bacc[j]);
+    if (lane == 0) s_bg[wave][j] = sj;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    float sj = 0.f;
+#pragma unroll
+    for (int w = 0; w < G::kWaves; ++w) sj += s_bg[w][threadIdx.x];
+    a.tilepart[tile * 4 + threadIdx.x] = sj;
+  }
+}
+
+// Backward: the same staging and per-wave culling as the forward, but lanes
+// own splats of the wave's culled list and walk the wave's pixel block (see
+// bwd_chunk), so a splat's nine gradient sums stay in registers.  The waves
+// of a tile merge their per-splat partials with LDS float atomics; each
+// (tile, splat) pair then stores its nine sums with plain stores at the
+// pair's Gaussian-major slot.
+// (The occupancy hint of 5 waves per SIMD caps the register budget of the
+// unrolled pixel rows; without it the compiler takes 110 VGPRs, 4 waves.)
+template <int T>
+__global__ __launch_bounds__(TileGeom<T>::kThreads) __attribute__((amdgpu_waves_per_eu(5)))
+void raster_bwd_kernel(RasterArgs a, const float4* __restrict__ pdg) {
+  using G = TileGeom<T>;
+  constexpr int kB = G::kBatch;
+  __shared__ SplatRec s_rec[kB];
+  __shared__ uint32_t s_slot[kB];
+  __shared__ __align__(16) uint8_t s_list[G::kWaves * kB];
+  __shared__ float s_acc[9][kB];
+  TileCtx<T> c;
+  const DevCamera* cam;
+  if (!tile_setup<T>(a, c, cam)) return;
+
+  // this wave's 64 per-pixel factors (wave-uniform base address)
+  const int wave_u = __builtin_amdgcn_readfirstlane(c.wave);
+  const float4* __restrict__ pd_wave = pdg + (c.tile * G::kWaves + wave_u) * kWave;
   for (int k = threadIdx.x; k < 9 * kB; k += G::kThreads) (&s_acc[0][0])[k] = 0.f;
 
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += kB) {
-    const int m = stage_and_cull<T, kB>(a, c, b, s_rec, s_id, s_list);
-    const uint16_t* list = s_list + c.wave * kB;
+    const int m = stage_and_cull<T, kB, true>(a, c, b, s_rec, s_slot, s_list);
+    const uint8_t* list = s_list + c.wave * kB;
     for (int c0 = 0; c0 < m; c0 += kWave) {
-      const int j = c0 + c.lane;
-      const bool valid = j < m;
-      const int kr = valid ? list[j] : 0;
-      const SplatRec r = s_rec[kr];
-      const float amp = r.r1.w, cr = r.r2.x, cg = r.r2.y, cb = r.r2.z;
-      // Moments of e = a * dL/da over the block's pixels (dq = -e / 2):
-      // Mx = sum e dx, My = sum e dy, Mxx = sum e dx^2, Mxy = sum e dx dy,
-      // Myy = sum e dy^2.  Each row keeps S0 = sum e, S1 = sum e dx and
-      // S2 = sum e dx^2 and folds dy in once, so a pixel costs three FMAs.
-      float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
-      float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
-      const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
-      // first pixel centre of the block relative to the splat's integer
-      // origin (exact), so dx = (ex0 + col) - fx matches the forward's
-      const float ex0 = (static_cast<float>(c.bx0) + 0.5f) - r.r1.y;
-      const float ey0 = (static_cast<float>(c.by0) + 0.5f) - r.r1.z;
-      for (int row = 0; row < G::kSub; ++row) {
-        const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
-        const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
-        const int lrow = row * 8;
-        float S0 = 0.f, S1 = 0.f, S2 = 0.f;
-#pragma unroll
-        for (int col = 0; col < G::kSub; ++col) {
-          const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
-          const float q = quad_form(A, B2dy, Cdy2, dx);
-          if (valid && q <= tau) {
-            // pixel (row, col) of the block lives in lane row * 8 + col
-            const int src = lrow + col;
-            const float pdx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pd.x), src));
-            const float pdy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pd.y), src));
-            const float pdz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pd.z), src));
-            const float pdw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pd.w), src));
-            const float Gq = falloff(q);
-            const float al = amp * Gq;
-            const float dLda = fmaf(pdx, cr, fmaf(pdy, cg, fmaf(pdz, cb, -pdw)));
-            const float e = al * dLda;
-            S0 += e;
-            S1 = fmaf(e, dx, S1);
-            S2 = fmaf(e, dx * dx, S2);
-            g_r = fmaf(al, pdx, g_r);
-            g_g = fmaf(al, pdy, g_g);
-            g_b = fmaf(al, pdz, g_b);
-            g_amp = fmaf(dLda, Gq, g_amp);
-          }
-        }
-        Mx += S1;
-        My = fmaf(dy, S0, My);
-        Mxx += S2;
-        Mxy = fmaf(dy, S1, Mxy);
-        Myy = fmaf(dy * dy, S0, Myy);
-      }
-      // dq = -e/2; q = A dx^2 + B2 dx dy + C dy^2 with dx = px - mu_x, so
-      // dL/dmu_x = -sum dq (2A dx + B2 dy) = A Mx + (B2/2) My, and so on
-      const float g_mx = A * Mx + 0.5f * B2 * My;
-      const float g_my = 0.5f * B2 * Mx + Cc * My;
-      const float gA = -0.5f * Mxx, gB = -Mxy, gC = -0.5f * Myy;
-      if (valid) {
-        atomicAdd(&s_acc[0][kr], g_mx);
-        atomicAdd(&s_acc[1][kr], g_my);
-        atomicAdd(&s_acc[2][kr], gA);
-        atomicAdd(&s_acc[3][kr], gB);
-        atomicAdd(&s_acc[4][kr], gC);
-        atomicAdd(&s_acc[5][kr], g_r);
-        atomicAdd(&s_acc[6][kr], g_g);
-        atomicAdd(&s_acc[7][kr], g_b);
-        atomicAdd(&s_acc[8][kr], g_amp);
-      }
+      const int rem = m - c0;
+      if (rem > 32)
+        bwd_chunk<T, 1, kB>(c, c0, m, list, s_rec, pd_wave, s_acc, tau);
+      else if (rem > 16)
+        bwd_chunk<T, 2, kB>(c, c0, m, list, s_rec, pd_wave, s_acc, tau);
+      else if (rem > 8)
+        bwd_chunk<T, 4, kB>(c, c0, m, list, s_rec, pd_wave, s_acc, tau);
+      else
+        bwd_chunk<T, 8, kB>(c, c0, m, list, s_rec, pd_wave, s_acc, tau);
     }
     __syncthreads();
     // one plain store per (tile, splat) pair, at the pair's Gaussian-major
@@ -479,12 +545,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
         v9[j] = s_acc[j][k];
         s_acc[j][k] = 0.f;
       }
-      // slot = the Gaussian's first slot + this tile's row-major index in
-      // its tile rectangle (the order in which binning enumerated its pairs)
-      const int64_t g = static_cast<int64_t>(c.v) * c.n + s_id[k];
-      const uint2 rc = a.rect[g];
-      const uint32_t rx0 = rc.x & 0xffffu, rw = (rc.x >> 16) - rx0, ry0 = rc.y & 0xffffu;
-      const uint32_t sl = a.goff[g] + (static_cast<uint32_t>(c.ty) - ry0) * rw + (static_cast<uint32_t>(c.tx) - rx0);
+      const uint32_t sl = s_slot[k];
       if (sl < a.capacity) {
         float3* dst = a.part + 3 * static_cast<int64_t>(sl);
         dst[0] = make_float3(v9[0], v9[1], v9[2]);
@@ -493,19 +554,6 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
       }
     }
   }
-  // per-tile background partial sums
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const float s = wave_sum(bacc[j]);
-    if (c.lane == 0) s_bg[c.wave][j] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < 4 && c.k == 0) {
-    float s = 0.f;
-#pragma unroll
-    for (int w = 0; w < G::kWaves; ++w) s += s_bg[w][threadIdx.x];
-    a.tilepart[c.tile * 4 + threadIdx.x] = s;
-  }
 }
 
 RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capacity,
@@ -513,11 +561,9 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   RasterArgs a = {};
   const PairView pv = pair_view(pairs, capacity);
   a.cams = at<DevCamera>(ws, L.off_cams);
-  a.rec = at<SplatRec>(ws, L.off_rec);
+  a.rec = at<DevSplat>(ws, L.off_rec);
   a.tile_start = at<uint32_t>(ws, L.off_tstart);
   a.ids = pv.ids;
-  a.rect = at<uint2>(ws, L.off_rect);
-  a.goff = at<uint32_t>(ws, L.off_goff);
   a.part = pv.part;
   a.n = L.n;
   a.capacity = capacity;
@@ -542,8 +588,9 @@ hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, bool count, h
 }
 
 template <int T>
-hipError_t bwd_t(const RasterArgs& a, int64_t grid, hipStream_t st) {
-  raster_bwd_kernel<T><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a);
+hipError_t bwd_t(const RasterArgs& a, float4* pd, int64_t grid, int64_t tiles, hipStream_t st) {
+  raster_bwd_prep<T><<<dim3(static_cast<unsigned>(tiles)), TileGeom<T>::kThreads, 0, st>>>(a, pd);
+  raster_bwd_kernel<T><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a, pd);
   return hipGetLastError();
 }
 
@@ -580,10 +627,11 @@ hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t cap
   a.den = den;
   a.tilepart = at<float>(ws, L.off_tilepart);
   const int64_t grid = max_raster_items(L, capacity);
+  float4* pd = at<float4>(ws, L.off_pd);
   switch (L.tile) {
-    case 8: return bwd_t<8>(a, grid, st);
-    case 32: return bwd_t<32>(a, grid, st);
-    default: return bwd_t<16>(a, grid, st);
+    case 8: return bwd_t<8>(a, pd, grid, L.total_tiles, st);
+    case 32: return bwd_t<32>(a, pd, grid, L.total_tiles, st);
+    default: return bwd_t<16>(a, pd, grid, L.total_tiles, st);
   }
 }
 

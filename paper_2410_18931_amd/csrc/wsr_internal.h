@@ -39,6 +39,16 @@ struct __align__(16) SplatRec {
   float4 r0, r1, r2;
 };
 
+// The record as stored in HBM: 64 bytes, so that no record straddles a cache
+// line, with the pair-slot data the raster backward needs appended:
+//   slot = (goff, rect.x, rect.y, 0): the Gaussian's first Gaussian-major
+//   pair slot (written by binning) and its tile rectangle (x0 | x1 << 16,
+//   y0 | y1 << 16).
+struct __align__(64) DevSplat {
+  SplatRec s;
+  uint4 slot;
+};
+
 // The caller's pair buffer (capacity entries of kPairBytes bytes): per
 // (tile, Gaussian) pair a 36-byte partial 2D gradient, written by the raster
 // backward at the pair's Gaussian-major slot (the Gaussian's pair offset plus
@@ -76,7 +86,8 @@ struct Layout {
   int64_t hist_len = 0;      // entries of the count matrix (without the trailing total)
   int64_t scan_parts = 0;
   size_t off_cams = 0, off_flags = 0, off_rec = 0, off_rect = 0, off_hist = 0, off_scan = 0,
-         off_goff = 0, off_grad2d = 0, off_tstart = 0, off_tilepart = 0, off_gpart = 0, off_items = 0, off_acc = 0;
+         off_goff = 0, off_grad2d = 0, off_tstart = 0, off_tilepart = 0, off_gpart = 0, off_items = 0, off_acc = 0,
+         off_pd = 0;
   int64_t gpart_blocks = 0;
   size_t bytes = 0;
 };
