@@ -178,9 +178,9 @@ int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params
  * grads (they are overwritten, not accumulated).  out_grad2d (nullable,
  * DEVICE [n_views][n][9]) receives the per-(view, Gaussian) gradient with
  * respect to (mu_x, mu_y, A, B, C, r, g, b, a) where (A, B, C) is the conic
- * (q = A dx^2 + 2B dx dy + C dy^2) and a = u w the amplitude.  No global
- * atomics; the only run-to-run variation is the float summation order of the
- * per-splat partials merged across the waves of a tile (last-bit effects). */
+ * (q = A dx^2 + 2B dx dy + C dy^2) and a = u w the amplitude.  No atomics:
+ * every sum is formed in a fixed order, so for given inputs (dL_drgb, rgb,
+ * den and the binning) the result does not vary from run to run. */
 int32_t wsr_render_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views,
                        const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
                        void* pairs, int64_t capacity, const float* dL_drgb, const float* rgb,

@@ -184,13 +184,15 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
 }
 
 // Stage one batch of records into LDS and build this wave's culled list.
-// Returns the list length.  With SLOTS, also the Gaussian-major slot of each
-// staged (tile, splat) pair: the Gaussian's first slot plus this tile's
-// row-major index in its tile rectangle (the order in which binning
-// enumerated its pairs).
+// Returns the list length.  With SLOTS (the backward), also the
+// Gaussian-major slot of each staged (tile, splat) pair -- the Gaussian's
+// first slot plus this tile's row-major index in its tile rectangle, the
+// order in which binning enumerated its pairs -- and, per staged record, its
+// position in this wave's list (0xffff if culled).
 template <int T, int BATCH, bool SLOTS>
 __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
-                                              SplatRec* s_rec, uint32_t* s_slot, uint8_t* s_list) {
+                                              SplatRec* s_rec, uint32_t* s_slot, uint8_t* s_list,
+                                              uint16_t* s_pos) {
   using G = TileGeom<T>;
   __syncthreads();  // previous batch fully consumed
   for (int q = threadIdx.x; q < BATCH; q += G::kThreads) {
@@ -214,10 +216,9 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
     const int k = k0 + c.lane;
     const bool hit = k < cnt && block_hits(s_rec[k], bx, by, static_cast<float>(G::kSub - 1), a.tau);
     const uint64_t mask = __ballot(hit);
-    if (hit) {
-      const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
-      list[pos] = static_cast<uint8_t>(k);
-    }
+    const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
+    if (hit) list[pos] = static_cast<uint8_t>(k);
+    if (SLOTS && k < BATCH) s_pos[c.wave * BATCH + k] = hit ? static_cast<uint16_t>(pos) : 0xffffu;
     m += __popcll(mask);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   const float pcy = static_cast<float>(c.py) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T, G::kBatch, false>(a, c, b, s_rec, nullptr, s_list);
+    const int m = stage_and_cull<T, G::kBatch, false>(a, c, b, s_rec, nullptr, s_list, nullptr);
     const uint8_t* list = s_list + c.wave * G::kBatch;
     // four splats per step: one 4-byte read fetches their list entries and
     // all four records are requested before any arithmetic, so LDS latency
@@ -339,32 +340,23 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
-// One chunk of the backward for one wave: up to 64 / K splats of the wave's
-// culled list, each walked by K lanes that take 8 / K pixel rows of the
-// wave's block apiece.  K = 1 for full chunks; a list's last, partly filled
-// chunk uses K = 2, 4 or 8 so that a short remainder still keeps most lanes
-// busy.
-//
-// Per splat the lanes sum over their pixels, with G = exp(-q/2) and
+// One chunk of the backward for one wave: up to 64 splats of the wave's
+// culled list, one per lane, each walked over the wave's 8x8 pixel block.
+// Per splat the lane sums over the pixels, with G = exp(-q/2) and
 // e = G dL/da: per row S0 = sum e, S1 = sum e dx and S2 = sum e dx^2 (three
 // FMAs a pixel), folded with dy once per row into the moments Mx = sum e dx,
 // My = sum e dy, Mxx = sum e dx^2, Mxy = sum e dx dy, Myy = sum e dy^2; and
-// sum G gbar.  The splat's amplitude multiplies them once at the end.  The K
-// lanes of a splat add their sums with lane shuffles and one of them merges
-// the result into the tile's LDS accumulator.
+// sum G gbar.  The splat's amplitude multiplies them once at the end.  The
+// lane's nine partial 2D gradient sums are written to out[j][lane].
 //
-// The per-pixel factors (gbar, s) of the wave's block come from the prepass
-// (raster_bwd_prep).  With K = 1 every lane walks the same pixel at the same
-// time, so they are read with scalar loads at a wave-uniform address and
-// enter the FMAs as scalar operands; with K > 1 the lanes walk different
-// rows and read them with vector loads (the wave's 1 KB stays in L1).
-template <int T, int K, int B>
+// All lanes walk the same pixel at the same time, so the per-pixel factors
+// (gbar, s) from the prepass (raster_bwd_prep) are read with scalar loads at
+// a wave-uniform address and enter the FMAs as scalar operands.
+template <int T>
 __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
                                           const SplatRec* s_rec, const float4* __restrict__ pd_wave,
-                                          float (*s_acc)[B], float tau) {
-  constexpr int kRows = 8 / K;
-  const int jj = c.lane / K, sub = c.lane % K;
-  const int j = c0 + jj;
+                                          float (*out)[kWave], float tau) {
+  const int j = c0 + c.lane;
   const bool valid = j < m;
   const int kr = valid ? list[j] : 0;
   const SplatRec r = s_rec[kr];
@@ -377,8 +369,7 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
   const float ex0 = (static_cast<float>(c.bx0) + 0.5f) - r.r1.y;
   const float ey0 = (static_cast<float>(c.by0) + 0.5f) - r.r1.z;
 #pragma unroll 1
-  for (int rr = 0; rr < kRows; ++rr) {
-    const int row = sub * kRows + rr;
+  for (int row = 0; row < 8; ++row) {
     const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
     const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
     float S0 = 0.f, S1 = 0.f, S2 = 0.f;
@@ -386,19 +377,16 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
     for (int col = 0; col < 8; ++col) {
       const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
       const float q = quad_form(A, B2dy, Cdy2, dx);
-      {
-        // with K = 1 the address is wave-uniform: a scalar load into SGPRs
-        const float4 pd = pd_wave[row * 8 + col];
-        const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
-        const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
-        const float e = Gq * dLda;
-        S0 += e;
-        S1 = fmaf(e, dx, S1);
-        S2 = fmaf(e, dx * dx, S2);
-        g_r = fmaf(Gq, pd.x, g_r);
-        g_g = fmaf(Gq, pd.y, g_g);
-        g_b = fmaf(Gq, pd.z, g_b);
-      }
+      const float4 pd = pd_wave[row * 8 + col];  // wave-uniform: SGPRs
+      const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
+      const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
+      const float e = Gq * dLda;
+      S0 += e;
+      S1 = fmaf(e, dx, S1);
+      S2 = fmaf(e, dx * dx, S2);
+      g_r = fmaf(Gq, pd.x, g_r);
+      g_g = fmaf(Gq, pd.y, g_g);
+      g_b = fmaf(Gq, pd.z, g_b);
     }
     g_amp += S0;
     Mx += S1;
@@ -407,33 +395,20 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
     Mxy = fmaf(dy, S1, Mxy);
     Myy = fmaf(dy * dy, S0, Myy);
   }
-#pragma unroll
-  for (int d = 1; d < K; d <<= 1) {
-    Mx += __shfl_xor(Mx, d, kWave);
-    My += __shfl_xor(My, d, kWave);
-    Mxx += __shfl_xor(Mxx, d, kWave);
-    Mxy += __shfl_xor(Mxy, d, kWave);
-    Myy += __shfl_xor(Myy, d, kWave);
-    g_r += __shfl_xor(g_r, d, kWave);
-    g_g += __shfl_xor(g_g, d, kWave);
-    g_b += __shfl_xor(g_b, d, kWave);
-    g_amp += __shfl_xor(g_amp, d, kWave);
-  }
-  if (valid && sub == 0) {
-    // the sums above leave out the splat's constant amplitude (a = amp G):
-    // dq = -amp e / 2, and with q = A dx^2 + B2 dx dy + C dy^2, dx = px - mu_x,
-    // dL/dmu_x = -sum dq (2A dx + B2 dy) = amp (A Mx + (B2/2) My), and so on;
-    // dL/dc = amp sum G gbar, dL/damp = sum G dL/da
-    atomicAdd(&s_acc[0][kr], amp * (A * Mx + 0.5f * B2 * My));
-    atomicAdd(&s_acc[1][kr], amp * (0.5f * B2 * Mx + Cc * My));
-    atomicAdd(&s_acc[2][kr], -0.5f * amp * Mxx);
-    atomicAdd(&s_acc[3][kr], -amp * Mxy);
-    atomicAdd(&s_acc[4][kr], -0.5f * amp * Myy);
-    atomicAdd(&s_acc[5][kr], amp * g_r);
-    atomicAdd(&s_acc[6][kr], amp * g_g);
-    atomicAdd(&s_acc[7][kr], amp * g_b);
-    atomicAdd(&s_acc[8][kr], g_amp);
-  }
+  // the sums above leave out the splat's constant amplitude (a = amp G):
+  // dq = -amp e / 2, and with q = A dx^2 + B2 dx dy + C dy^2, dx = px - mu_x,
+  // dL/dmu_x = -sum dq (2A dx + B2 dy) = amp (A Mx + (B2/2) My), and so on;
+  // dL/dc = amp sum G gbar, dL/damp = sum G dL/da
+  const int l = c.lane;
+  out[0][l] = amp * (A * Mx + 0.5f * B2 * My);
+  out[1][l] = amp * (0.5f * B2 * Mx + Cc * My);
+  out[2][l] = -0.5f * amp * Mxx;
+  out[3][l] = -amp * Mxy;
+  out[4][l] = -0.5f * amp * Myy;
+  out[5][l] = amp * g_r;
+  out[6][l] = amp * g_g;
+  out[7][l] = amp * g_b;
+  out[8][l] = g_amp;
 }
 
 // Backward prepass, one workgroup per tile: the per-pixel factors
@@ -494,21 +469,27 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterA
 
 // Backward: the same staging and per-wave culling as the forward, but lanes
 // own splats of the wave's culled list and walk the wave's pixel block (see
-// bwd_chunk), so a splat's nine gradient sums stay in registers.  The waves
-// of a tile merge their per-splat partials with LDS float atomics; each
-// (tile, splat) pair then stores its nine sums with plain stores at the
-// pair's Gaussian-major slot.
-// (The occupancy hint of 5 waves per SIMD caps the register budget of the
-// unrolled pixel rows; without it the compiler takes 110 VGPRs, 4 waves.)
+// bwd_chunk), so a splat's nine gradient sums stay in registers.
+//
+// The waves of a tile merge their sums without atomics.  Thread k owns
+// staged record k.  The waves process their chunks in lockstep rounds (one
+// chunk each per round); after a round every wave's sums sit in LDS, and each
+// owner adds the entries of its record -- found through the per-wave list
+// positions recorded by the culling -- into registers, waves in a fixed
+// order.  At the end of the batch the owner stores the record's sums, zeros
+// included, with plain stores at the pair's Gaussian-major slot.  The
+// summation order is fixed, so the result does not vary from run to run.
 template <int T>
-__global__ __launch_bounds__(TileGeom<T>::kThreads) __attribute__((amdgpu_waves_per_eu(5)))
-void raster_bwd_kernel(RasterArgs a, const float4* __restrict__ pdg) {
+__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(RasterArgs a,
+                                                                           const float4* __restrict__ pdg) {
   using G = TileGeom<T>;
   constexpr int kB = G::kBatch;
   __shared__ SplatRec s_rec[kB];
   __shared__ uint32_t s_slot[kB];
   __shared__ __align__(16) uint8_t s_list[G::kWaves * kB];
-  __shared__ float s_acc[9][kB];
+  __shared__ uint16_t s_pos[G::kWaves * kB];
+  __shared__ float s_part[G::kWaves][9][kWave];
+  __shared__ int s_m[G::kWaves];
   TileCtx<T> c;
   const DevCamera* cam;
   if (!tile_setup<T>(a, c, cam)) return;
@@ -516,41 +497,42 @@ void raster_bwd_kernel(RasterArgs a, const float4* __restrict__ pdg) {
   // this wave's 64 per-pixel factors (wave-uniform base address)
   const int wave_u = __builtin_amdgcn_readfirstlane(c.wave);
   const float4* __restrict__ pd_wave = pdg + (c.tile * G::kWaves + wave_u) * kWave;
-  for (int k = threadIdx.x; k < 9 * kB; k += G::kThreads) (&s_acc[0][0])[k] = 0.f;
-
   const float tau = a.tau;
+  const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
   for (uint32_t b = c.start; b < c.end; b += kB) {
-    const int m = stage_and_cull<T, kB, true>(a, c, b, s_rec, s_slot, s_list);
-    const uint8_t* list = s_list + c.wave * kB;
-    for (int c0 = 0; c0 < m; c0 += kWave) {
-      const int rem = m - c0;
-      if (rem > 32)
-        bwd_chunk<T, 1, kB>(c, c0, m, list, s_rec, pd_wave, s_acc, tau);
-      else if (rem > 16)
-        bwd_chunk<T, 2, kB>(c, c0, m, list, s_rec, pd_wave, s_acc, tau);
-      else if (rem > 8)
-        bwd_chunk<T, 4, kB>(c, c0, m, list, s_rec, pd_wave, s_acc, tau);
-      else
-        bwd_chunk<T, 8, kB>(c, c0, m, list, s_rec, pd_wave, s_acc, tau);
-    }
-    __syncthreads();
-    // one plain store per (tile, splat) pair, at the pair's Gaussian-major
-    // slot (every pair of the batch is written, zeros included, so the
-    // projection backward can sum each Gaussian's slot range blindly)
+    const int m = stage_and_cull<T, kB, true>(a, c, b, s_rec, s_slot, s_list, s_pos);
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kB), c.end - b));
-    for (int k = threadIdx.x; k < cnt; k += G::kThreads) {
-      float v9[9];
+    if (c.lane == 0) s_m[c.wave] = m;
+    __syncthreads();
+    int rounds = 0;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) {
-        v9[j] = s_acc[j][k];
-        s_acc[j][k] = 0.f;
+    for (int w = 0; w < G::kWaves; ++w) rounds = max(rounds, (s_m[w] + kWave - 1) / kWave);
+    const uint8_t* list = s_list + c.wave * kB;
+    float acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0.f;
+    for (int r = 0; r < rounds; ++r) {
+      if (r * kWave < m) bwd_chunk<T>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
+      __syncthreads();
+      if (own < cnt) {
+#pragma unroll
+        for (int w = 0; w < G::kWaves; ++w) {
+          const int p = s_pos[w * kB + own];  // 0xffff: culled by wave w
+          if ((p >> 6) == r) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) acc[q] += s_part[w][q][p & (kWave - 1)];
+          }
+        }
       }
-      const uint32_t sl = s_slot[k];
+      __syncthreads();
+    }
+    if (own < cnt) {
+      const uint32_t sl = s_slot[own];
       if (sl < a.capacity) {
         float3* dst = a.part + 3 * static_cast<int64_t>(sl);
-        dst[0] = make_float3(v9[0], v9[1], v9[2]);
-        dst[1] = make_float3(v9[3], v9[4], v9[5]);
-        dst[2] = make_float3(v9[6], v9[7], v9[8]);
+        dst[0] = make_float3(acc[0], acc[1], acc[2]);
+        dst[1] = make_float3(acc[3], acc[4], acc[5]);
+        dst[2] = make_float3(acc[6], acc[7], acc[8]);
       }
     }
   }
