@@ -83,6 +83,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU baseline sample")
     ap.add_argument("--graph", action="store_true", help="time replays of the whole step captured as one HIP graph")
+    ap.add_argument("--mode", default="render", choices=["render", "train"],
+                    help="render: forward + backward of the renderer (the headline metric); train: whole "
+                         "training steps (forward, l1 + 0.2 D-SSIM loss, backward, Adam)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this size (for scaling HBM byte counters)")
     return ap.parse_args()
@@ -132,6 +135,73 @@ def cpu_baseline(scene, cams, settings, seconds: float) -> dict:
                       f"{dt:.1f} s; frames/s = sampled fraction / time"}
 
 
+def bench_train(args) -> None:
+    """Whole training steps on the workload: forward, loss, backward and Adam
+    over every attribute and the global parameters, with the id list sized
+    once up front (no per-step host synchronisation)."""
+    import torch
+
+    import wsr_synth as ws
+    from paper_2410_18931_amd import WSRContext, globals_tensor, scene_to_device
+    from paper_2410_18931_amd.train import Loss, TrainStep, adam_
+
+    scene, cams, st = ws.make_scene(args.config)
+    st = st.copy(tile=args.tile)
+    n = scene["means"].shape[1]
+    g = globals_tensor(st)
+    ctx = WSRContext(n, cams, st)
+    # target images: the same scene with its degree-0 colour shifted, so the
+    # loss and every gradient are non-trivial
+    tgt = {k: v.copy() for k, v in scene.items()}
+    tgt["sh"][0, :, :3] += 0.1
+    targets = ctx.forward(scene_to_device(tgt), g)[0].clone()
+    ctx._alloc_pairs(int(ctx.last_pairs * 1.3) + 1024)
+    dev = scene_to_device(scene)
+    trainer = TrainStep(ctx, dev, g.clone(), targets, grow=False)
+    for _ in range(args.warmup):
+        trainer.step()
+    torch.cuda.synchronize()
+    ctx.check()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        loss = trainer.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.check()
+    ms = e0.elapsed_time(e1) / args.steps
+    # the loss and the optimiser on their own (same tensors, same sizes)
+    lossf = Loss(cams)
+    rgb, _ = ctx.render_fwd(trainer.globals_)
+    dL = torch.empty_like(rgb)
+    e0.record()
+    for _ in range(args.steps):
+        lossf(rgb, targets, dL)
+    e1.record()
+    torch.cuda.synchronize()
+    loss_ms = e0.elapsed_time(e1) / args.steps
+    e0.record()
+    for k in range(args.steps):
+        for p_, g_, key, m_, v_ in trainer._groups:
+            adam_(p_, g_, m_, v_, 1000 + k, 0.0)
+    e1.record()
+    torch.cuda.synchronize()
+    adam_ms = e0.elapsed_time(e1) / args.steps
+    out = {
+        "metric": "training steps/s (forward, l1 + 0.2 D-SSIM loss, backward, Adam over all attributes) "
+                  "at 1M splats 1080p",
+        "value": round(1e3 / ms, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.config}: {n:,} Gaussians, {ctx.nv} view(s), {ctx.total_pixels:,} px, "
+                               f"tile {args.tile}, f32, training", "gaussians": n, "views": ctx.nv,
+                   "pixels": ctx.total_pixels, "tile": args.tile},
+        "stages_ms": {"loss": round(loss_ms, 4), "adam": round(adam_ms, 4)},
+        "final_loss": float(loss.item()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -143,6 +213,9 @@ def main():
               "Gaussians over GPUs (one all-reduce of the unnormalised sums) is designed, not implemented",
               file=sys.stderr)
         sys.exit(2)
+    if args.mode == "train":
+        bench_train(args)
+        return
 
     import torch
 

@@ -211,6 +211,40 @@ int32_t wsr_pair_count(const void* ws, int64_t ws_bytes, int64_t* out_total, voi
  * this workspace overflowed its id list, else WSR_OK. */
 int32_t wsr_check(const void* ws, int64_t ws_bytes, void* stream);
 
+/* ---- Training step around the renderer (Sec. 5, implementation details) ----
+ *
+ * The paper trains with the rendering loss of 3D Gaussian Splatting: an l1
+ * term plus a D-SSIM term weighted 0.2.  Per view v with P_v = 3 H W entries
+ *   L_v = (1 - lambda) mean|x - y| + lambda (1 - mean SSIM(x, y)),
+ * and L = mean over views.  SSIM is computed per colour channel under an
+ * 11 x 11 Gaussian window (sigma 1.5) with zero padding, C1 = 0.01^2 and
+ * C2 = 0.03^2 (Wang et al. 2004, dynamic range 1).
+ *
+ * Size in bytes of the workspace wsr_loss needs for these cameras (only width
+ * and height are read), or -1 for invalid input. */
+int64_t wsr_loss_workspace_bytes(const wsr_camera* cams, int32_t n_views);
+
+/* Loss and its gradient.  img, target: DEVICE float [P][3], views
+ * concatenated in camera order (the layout wsr_render_fwd writes).  Writes
+ * the DEVICE scalar *loss and DEVICE dL_dimg [P][3] (overwritten).  The
+ * workspace (DEVICE, caller-owned, 256-byte aligned) holds the derivative maps
+ * and per-tile loss shares; the shares are summed in FP64 in a fixed order,
+ * so the result does not vary from run to run.  Asynchronous on `stream`.
+ * Returns WSR_ERR_INVALID for null pointers, n_views outside
+ * [1, WSR_MAX_VIEWS], an empty or oversized view or lambda outside [0, 1];
+ * WSR_ERR_WORKSPACE if ws_bytes is too small. */
+int32_t wsr_loss(const wsr_camera* cams, int32_t n_views, const float* img, const float* target, float lambda,
+                 void* ws, int64_t ws_bytes, float* loss, float* dL_dimg, void* stream);
+
+/* One Adam update (Kingma and Ba 2015, with bias correction) of n DEVICE
+ * floats in place: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  step counts
+ * from 1.  param, m and v are read and written, grad is read.  Asynchronous
+ * on `stream`.  Returns WSR_ERR_INVALID for null pointers with n > 0,
+ * n < 0, step < 1 or beta outside [0, 1). */
+int32_t wsr_adam(float* param, const float* grad, float* m, float* v, int64_t n, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,7 @@ ABI_VERSION = 2
 
 EXPORTED = ("wsr_abi_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_pair_bytes", "wsr_project", "wsr_bin",
             "wsr_render_fwd", "wsr_render_bwd", "wsr_raster_bwd", "wsr_project_bwd", "wsr_pair_count",
-            "wsr_check")
+            "wsr_check", "wsr_loss_workspace_bytes", "wsr_loss", "wsr_adam")
 
 
 class WsrScene(C.Structure):
@@ -91,6 +91,13 @@ def load():
     lib.wsr_pair_count.argtypes = [P, I64, C.POINTER(C.c_int64), P]
     lib.wsr_check.restype = I32
     lib.wsr_check.argtypes = [P, I64, P]
+    F = C.c_float
+    lib.wsr_loss_workspace_bytes.restype = I64
+    lib.wsr_loss_workspace_bytes.argtypes = [P, I32]
+    lib.wsr_loss.restype = I32
+    lib.wsr_loss.argtypes = [P, I32, P, P, F, P, I64, P, P, P]
+    lib.wsr_adam.restype = I32
+    lib.wsr_adam.argtypes = [P, P, P, P, I64, I32, F, F, F, F, P]
     if lib.wsr_abi_version() != ABI_VERSION:
         raise RuntimeError("libwsr.so ABI version mismatch; rebuild the library")
     _lib = lib

@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(os.path.dirname(PKG), "_build")
 LIB = os.path.join(PKG, "libwsr.so")
-SOURCES = ["api.hip", "project.hip", "bin.hip", "raster.hip", "project_bwd.hip"]
+SOURCES = ["api.hip", "project.hip", "bin.hip", "raster.hip", "project_bwd.hip", "train.hip"]
 ARCH = os.environ.get("WSR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -241,4 +241,36 @@ int32_t wsr_check(const void* ws, int64_t ws_bytes, void* stream) {
   return f.overflow ? WSR_ERR_CAPACITY : WSR_OK;
 }
 
+static bool loss_cams_ok(const wsr_camera* cams, int32_t n_views) {
+  if (!cams || n_views < 1 || n_views > WSR_MAX_VIEWS) return false;
+  for (int v = 0; v < n_views; ++v)
+    if (cams[v].width < 1 || cams[v].height < 1 || cams[v].width > 32767 || cams[v].height > 32767) return false;
+  return true;
+}
+
+int64_t wsr_loss_workspace_bytes(const wsr_camera* cams, int32_t n_views) {
+  if (!loss_cams_ok(cams, n_views)) return -1;
+  return loss_workspace_bytes(cams, n_views);
+}
+
+int32_t wsr_loss(const wsr_camera* cams, int32_t n_views, const float* img, const float* target, float lambda,
+                 void* ws, int64_t ws_bytes, float* loss, float* dL_dimg, void* stream) {
+  if (!loss_cams_ok(cams, n_views) || !img || !target || !ws || !loss || !dL_dimg) return WSR_ERR_INVALID;
+  if (!(lambda >= 0.f && lambda <= 1.f)) return WSR_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return WSR_ERR_INVALID;
+  if (ws_bytes < loss_workspace_bytes(cams, n_views)) return WSR_ERR_WORKSPACE;
+  const hipError_t e = launch_loss(cams, n_views, img, target, lambda, ws, loss, dL_dimg,
+                                   static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? WSR_OK : WSR_ERR_HIP;
+}
+
+int32_t wsr_adam(float* param, const float* grad, float* m, float* v, int64_t n, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void* stream) {
+  if (n < 0 || step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f)) return WSR_ERR_INVALID;
+  if (n > 0 && (!param || !grad || !m || !v)) return WSR_ERR_INVALID;
+  const hipError_t e = launch_adam(param, grad, m, v, n, step, lr, beta1, beta2, eps,
+                                   static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? WSR_OK : WSR_ERR_HIP;
+}
+
 }  // extern "C"

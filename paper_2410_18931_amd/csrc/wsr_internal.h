@@ -159,6 +159,11 @@ hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const fl
                               const Layout& L, void* ws, const void* pairs, int64_t capacity,
                               const wsr_grads* g, float* out_grad2d, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+int64_t loss_workspace_bytes(const wsr_camera* cams, int32_t nv);
+hipError_t launch_loss(const wsr_camera* cams, int32_t nv, const float* img, const float* target, float lambda,
+                       void* ws, float* loss, float* dL, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int32_t step, float lr, float b1,
+                       float b2, float eps, hipStream_t st);
 // Upper bound of the raster work items for an id list of `capacity` entries.
 inline int64_t max_raster_items(const Layout& L, int64_t capacity) {
   return L.total_tiles + (capacity + kItemSplats - 1) / kItemSplats;

@@ -96,3 +96,25 @@ def test_lc_requires_weights_and_logit_mode_requires_logits():
     p = _lib.make_params(st)
     no_logit = _lib.WsrScene(8, 0, 0, 0, 0, dummy, dummy, dummy, dummy, None, dummy)
     assert lib.wsr_project(C.byref(no_logit), cc, 1, C.byref(p), dummy, dummy, 1 << 30, None, None) == 1
+
+
+def test_loss_and_adam_reject_bad_arguments_before_launch():
+    lib = _lib.load()
+    _, cams, _ = ws.make_scene("c1", n=8)
+    cc = _lib.make_cameras(cams)
+    dummy = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    INV, WSP = _lib.WSR_ERR_INVALID, _lib.WSR_ERR_WORKSPACE
+    need = lib.wsr_loss_workspace_bytes(cc, 1)
+    # 9 float maps per pixel plus one FP64 share per (16x16 tile, channel)
+    assert need >= 9 * 4 * 128 * 128 + 8 * 3 * 64
+    assert lib.wsr_loss_workspace_bytes(cc, 0) == -1
+    assert lib.wsr_loss_workspace_bytes(None, 1) == -1
+    F = C.c_float
+    assert lib.wsr_loss(cc, 1, dummy, dummy, F(0.2), dummy, need - 1, dummy, dummy, None) == WSP
+    assert lib.wsr_loss(cc, 1, dummy, dummy, F(1.5), dummy, need, dummy, dummy, None) == INV
+    assert lib.wsr_loss(cc, 1, None, dummy, F(0.2), dummy, need, dummy, dummy, None) == INV
+    assert lib.wsr_loss(cc, 1, dummy, dummy, F(0.2), C.c_void_p(0x1004), need, dummy, dummy, None) == INV
+    assert lib.wsr_adam(dummy, dummy, dummy, dummy, 10, 0, F(0.1), F(0.9), F(0.999), F(1e-15), None) == INV
+    assert lib.wsr_adam(dummy, dummy, dummy, dummy, 10, 1, F(0.1), F(1.0), F(0.999), F(1e-15), None) == INV
+    assert lib.wsr_adam(None, dummy, dummy, dummy, 10, 1, F(0.1), F(0.9), F(0.999), F(1e-15), None) == INV
+    assert lib.wsr_adam(None, None, None, None, 0, 1, F(0.1), F(0.9), F(0.999), F(1e-15), None) == _lib.WSR_OK
