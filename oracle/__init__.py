@@ -68,6 +68,9 @@ def _load():
                                    C.c_int32, C.c_double, P, P, P, P, P, P, P]
         lib.ora_render_bwd.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                        P, P, P, P, P, P, P, P, P]
+        D = C.c_double
+        lib.ora_render_sorted.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, D, D, D, D,
+                                          P, P, P]
         lib.ora_sh_basis.argtypes = [P, C.c_int64, C.c_int32, P]
         lib.ora_quat_to_rot.argtypes = [P, C.c_int64, P]
         lib.ora_num_threads.restype = C.c_int32
@@ -151,6 +154,24 @@ def render(scene, cam, settings, crop=None, mode: str = "strict", eta: float = 1
                        {"strict": 0, "aabb": 1}[mode], float(eta), _ptr(Cimg), _ptr(num),
                        _ptr(den), _ptr(amb), _ptr(ambc), _ptr(absden), _ptr(cnt))
     return {"C": Cimg, "num": num, "den": den, "amb": amb, "amb_c": ambc, "abs_den": absden, "count": cnt}
+
+
+def render_sorted(scene, cam, settings, crop=None, alpha_max: float = 0.99, alpha_min: float = 0.0,
+                  t_min: float = 0.0, eta: float = 1e-6) -> dict:
+    """Sorted alpha blending (Eq. 6) of the same splats, front to back by
+    camera depth, alpha = min(alpha_max, u exp(-q/2)) with u the opacity (no
+    depth weight), layers below alpha_min skipped, composition stopped once
+    the transmittance falls below t_min, background c_B behind.  Returns the
+    colour, the final transmittance and the per-pixel sum of alpha over
+    layers within ``eta`` of the support cutoff."""
+    pk = _Packed(scene, cam, settings)
+    x0, y0, x1, y1 = _window(cam, crop)
+    h, w = max(y1 - y0, 0), max(x1 - x0, 0)
+    out = {"C": np.zeros((h, w, 3)), "T": np.zeros((h, w)), "amb": np.zeros((h, w))}
+    _load().ora_render_sorted(C.byref(pk.scene), C.byref(pk.cam), C.byref(pk.params), x0, y0, x1, y1,
+                              float(alpha_max), float(alpha_min), float(t_min), float(eta), _ptr(out["C"]),
+                              _ptr(out["T"]), _ptr(out["amb"]))
+    return out
 
 
 def render_bwd(scene, cam, settings, dL_dC, crop=None) -> dict:

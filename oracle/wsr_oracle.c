@@ -854,6 +854,92 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
     free_visible(&v);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Sorted alpha blending (Eq. 6): the compositing the method removes the      */
+/* sort from.  Not part of Eq. 7; a baseline rendered from the same splats.   */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double depth;
+    int64_t index;     /* scene index: ties in depth keep index order */
+    double alpha;
+    const proj_t *g;
+} layer_t;
+
+static int layer_cmp(const void *a, const void *b)
+{
+    const layer_t *x = (const layer_t *)a, *y = (const layer_t *)b;
+    if (x->depth < y->depth) return -1;
+    if (x->depth > y->depth) return 1;
+    return (x->index > y->index) - (x->index < y->index);
+}
+
+/*
+ * Per pixel of the window: the Gaussians with q <= tau, front to back
+ * (ascending camera depth t_z, ties by scene index), each with opacity
+ * alpha_i = min(alpha_max, u_i exp(-q/2)) where u_i is the Gaussian's
+ * opacity (no depth weight: Eq. 6 has none); layers with alpha_i < alpha_min
+ * are skipped.  With T_i = prod_{j<i} (1 - alpha_j):
+ *     C = sum_i c_i alpha_i T_i + T c_B,   T = the transmittance after the last layer,
+ * and composition stops after the layer that takes T below t_min (t_min = 0:
+ * never).  Outputs: out_C [h][w][3], out_T [h][w] the final transmittance,
+ * out_amb [h][w] the sum of alpha over layers whose support decision is within
+ * eta * M of the cutoff (as in ora_render).  Any output may be NULL.
+ */
+void ora_render_sorted(const ora_scene *S, const ora_camera *cam, const ora_params *P,
+                       int64_t x0, int64_t y0, int64_t x1, int64_t y1, double alpha_max,
+                       double alpha_min, double t_min, double eta,
+                       double *out_C, double *out_T, double *out_amb)
+{
+    const int64_t w = x1 - x0, h = y1 - y0;
+    if (w <= 0 || h <= 0) return;
+    vis_t v;
+    collect_visible(S, cam, P, x0, y0, x1, y1, &v);
+    const double tau = P->tau;
+    #pragma omp parallel
+    {
+        layer_t *lay = (layer_t *)malloc(sizeof(layer_t) * (v.m > 0 ? v.m : 1));
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t yy = 0; yy < h; ++yy)
+            for (int64_t xx = 0; xx < w; ++xx) {
+                int64_t k = 0;
+                double amb = 0.0;
+                for (int64_t j = 0; j < v.m; ++j) {
+                    const proj_t *g = &v.g[j];
+                    const double q = pair_q(g, x0 + xx, y0 + yy);
+                    const double dx = (double)(x0 + xx) + 0.5 - g->mu[0];
+                    const double dy = (double)(y0 + yy) + 0.5 - g->mu[1];
+                    const double M = g->conic[0] * dx * dx + 2.0 * fabs(g->conic[1] * dx * dy) +
+                                     g->conic[2] * dy * dy;
+                    double a = g->u * exp(-0.5 * q);
+                    if (a > alpha_max) a = alpha_max;
+                    if (fabs(q - tau) <= eta * M) amb += fabs(a);
+                    if (q > tau || a < alpha_min) continue;
+                    lay[k].depth = g->depth;
+                    lay[k].index = v.idx[j];
+                    lay[k].alpha = a;
+                    lay[k].g = g;
+                    ++k;
+                }
+                qsort(lay, (size_t)k, sizeof(layer_t), layer_cmp);
+                double T = 1.0, c3[3] = {0.0, 0.0, 0.0};
+                for (int64_t i = 0; i < k; ++i) {
+                    const double a = lay[i].alpha;
+                    for (int c = 0; c < 3; ++c) c3[c] += lay[i].g->rgb[c] * a * T;
+                    T *= 1.0 - a;
+                    if (T < t_min) break;
+                }
+                const int64_t o = yy * w + xx;
+                for (int c = 0; c < 3; ++c)
+                    if (out_C) out_C[3 * o + c] = c3[c] + T * P->bg[c];
+                if (out_T) out_T[o] = T;
+                if (out_amb) out_amb[o] = amb;
+            }
+        free(lay);
+    }
+    free_visible(&v);
+}
+
 int32_t ora_num_threads(void)
 {
 #ifdef _OPENMP
