@@ -83,9 +83,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU baseline sample")
     ap.add_argument("--graph", action="store_true", help="time replays of the whole step captured as one HIP graph")
-    ap.add_argument("--mode", default="render", choices=["render", "train"],
+    ap.add_argument("--mode", default="render", choices=["render", "train", "sorted"],
                     help="render: forward + backward of the renderer (the headline metric); train: whole "
-                         "training steps (forward, l1 + 0.2 D-SSIM loss, backward, Adam)")
+                         "training steps (forward, l1 + 0.2 D-SSIM loss, backward, Adam); sorted: forward "
+                         "only, weighted sum against sorted alpha blending of the same splats")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this size (for scaling HBM byte counters)")
     return ap.parse_args()
@@ -202,6 +203,82 @@ def bench_train(args) -> None:
     print(json.dumps(out), flush=True)
 
 
+def bench_sorted(args) -> None:
+    """Forward only: the weighted sum (projection, binning, Eq. 7) against
+    sorted alpha blending of the same splats (projection with the DIR
+    weight, binning, per-tile depth sort, Eq. 6 front to back), exactly and
+    with the usual 3DGS skip / early-stop settings."""
+    import torch
+
+    import wsr_synth as ws
+    from paper_2410_18931_amd import WSRContext, globals_tensor, scene_to_device
+
+    scene, cams, st = ws.make_scene(args.config)
+    st = st.copy(tile=args.tile)
+    n = scene["means"].shape[1]
+    dev = scene_to_device(scene)
+    g = globals_tensor(st)
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    wsr = WSRContext(n, cams, st)
+    wsr.forward(dev, g)
+    wsr._alloc_pairs(int(wsr.last_pairs * 1.1) + 1024)
+    rgb = torch.empty((wsr.total_pixels, 3), device="cuda")
+    den = torch.empty((wsr.total_pixels,), device="cuda")
+
+    def wsr_fwd():
+        wsr.project(dev, g)
+        wsr.bin(grow=False)
+        wsr.render_fwd(g, out=(rgb, den))
+
+    ms_wsr = timed(wsr_fwd, args.steps)
+    wsr.check()
+    sd = WSRContext(n, cams, st.copy(weight_kind="dir"))
+    sd.forward(dev, g)
+    sd._alloc_pairs(int(sd.last_pairs * 1.1) + 1024)
+    T = torch.empty((sd.total_pixels,), device="cuda")
+    out = {}
+    for name, blend in (("exact", {}), ("3dgs", {"alpha_min": 1.0 / 255.0, "t_min": 1e-4})):
+        def sorted_fwd(blend=blend):
+            sd.project(dev, g)
+            sd.bin(grow=False)
+            sd.render_sorted(g, out=(rgb, T), **blend)
+        out[name] = timed(sorted_fwd, args.steps)
+        sd.check()
+    # the depth sort on its own (sorting sorted lists costs the same: bitonic)
+    import ctypes as C
+    from paper_2410_18931_amd import _lib
+    sp = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ms_sort = timed(lambda: _lib.check("wsr_sort_tiles", sd.lib.wsr_sort_tiles(
+        sd.cams_c, sd.nv, C.byref(sd.params), n, C.c_void_p(sd.ws.data_ptr()), sd.ws_bytes,
+        C.c_void_p(sd.pairs.data_ptr()), sd.capacity, sp)), args.steps)
+    res = {
+        "metric": "forward frames/s at 1M splats 1080p: weighted sum (Eq. 7) against sorted alpha blending "
+                  "(Eq. 6, per-tile depth sort) of the same splats",
+        "value": round(1e3 / ms_wsr, 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_wsr, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.config}: {n:,} Gaussians, {wsr.nv} view(s), tile {args.tile}, forward only",
+                   "gaussians": n, "pixels": wsr.total_pixels, "tile": args.tile},
+        "sorted_exact_ms": round(out["exact"], 4), "sorted_3dgs_ms": round(out["3dgs"], 4),
+        "sort_ms": round(ms_sort, 4),
+        "speedup_vs_sorted_exact": round(out["exact"] / ms_wsr, 3),
+        "speedup_vs_sorted_3dgs": round(out["3dgs"] / ms_wsr, 3),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -215,6 +292,9 @@ def main():
         sys.exit(2)
     if args.mode == "train":
         bench_train(args)
+        return
+    if args.mode == "sorted":
+        bench_sorted(args)
         return
 
     import torch

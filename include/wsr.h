@@ -54,7 +54,8 @@ typedef enum {
     WSR_ERR_INVALID = 1,     /* bad argument; nothing enqueued */
     WSR_ERR_WORKSPACE = 2,   /* workspace smaller than wsr_workspace_bytes */
     WSR_ERR_CAPACITY = 3,    /* per-tile list overflow (device flag) */
-    WSR_ERR_HIP = 4          /* a HIP runtime call failed */
+    WSR_ERR_HIP = 4,         /* a HIP runtime call failed */
+    WSR_ERR_TILE_LIST = 5    /* a tile list longer than wsr_sort_tiles takes (device flag) */
 } wsr_status;
 
 /* Depth weight w(d) of Sec. 4.2: Eq. 8 (DIR, w = 1), Eq. 9 (EXP,
@@ -208,8 +209,44 @@ int32_t wsr_project_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t 
 int32_t wsr_pair_count(const void* ws, int64_t ws_bytes, int64_t* out_total, void* stream);
 
 /* Synchronises `stream`; returns WSR_ERR_CAPACITY if the last wsr_bin on
- * this workspace overflowed its id list, else WSR_OK. */
+ * this workspace overflowed its id list, WSR_ERR_TILE_LIST if a wsr_sort_tiles
+ * since then met a list longer than WSR_SORT_MAX, else WSR_OK. */
 int32_t wsr_check(const void* ws, int64_t ws_bytes, void* stream);
+
+/* ---- Sorted alpha blending (Eq. 6): the baseline the method removes the
+ * sort from (Sec. 1, Sec. 4.1) -----------------------------------------
+ *
+ * Renders the same splats front to back: project with weight_kind
+ * WSR_WEIGHT_DIR (so a splat's amplitude is its opacity u), bin, sort each
+ * tile's list by camera depth, then composite
+ *     C = sum_i c_i alpha_i T_i + T c_B,  alpha_i = min(alpha_max, u_i exp(-q_i / 2)),
+ *     T_i = prod_{j<i} (1 - alpha_j),
+ * skipping layers with alpha_i < alpha_min and stopping a pixel once its
+ * transmittance falls below t_min (0 and 0 give Eq. 6 exactly; 1/255 and
+ * 1e-4 are the usual 3D Gaussian Splatting settings).  Forward only. */
+#define WSR_SORT_MAX 8192
+
+typedef struct {
+    float alpha_max;   /* opacity clamp, (0, 1] */
+    float alpha_min;   /* layers below this are skipped, >= 0 */
+    float t_min;       /* a pixel stops below this transmittance, >= 0 */
+    int32_t reserved_;
+} wsr_blend;
+
+/* Sorts every tile's id list (as left by wsr_bin on the same workspace and
+ * pair buffer) by (camera depth, Gaussian id), in place, one workgroup per
+ * tile in LDS.  A list longer than WSR_SORT_MAX is left unsorted and raises
+ * a flag that wsr_check reports as WSR_ERR_TILE_LIST.  Asynchronous. */
+int32_t wsr_sort_tiles(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
+                       void* ws, int64_t ws_bytes, void* pairs, int64_t capacity, void* stream);
+
+/* Front-to-back composition of the sorted lists.  params->weight_kind must
+ * be WSR_WEIGHT_DIR (else WSR_ERR_INVALID).  globals as for wsr_project
+ * (c_B = globals[3..5]).  out_rgb: DEVICE concatenated [H][W][3]; out_T:
+ * DEVICE concatenated [H][W], the final transmittance.  Asynchronous. */
+int32_t wsr_render_sorted(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
+                          const float* globals, const wsr_blend* blend, void* ws, int64_t ws_bytes,
+                          const void* pairs, int64_t capacity, float* out_rgb, float* out_T, void* stream);
 
 /* ---- Training step around the renderer (Sec. 5, implementation details) ----
  *

@@ -21,7 +21,8 @@ ABI_VERSION = 2
 
 EXPORTED = ("wsr_abi_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_pair_bytes", "wsr_project", "wsr_bin",
             "wsr_render_fwd", "wsr_render_bwd", "wsr_raster_bwd", "wsr_project_bwd", "wsr_pair_count",
-            "wsr_check", "wsr_loss_workspace_bytes", "wsr_loss", "wsr_adam")
+            "wsr_check", "wsr_loss_workspace_bytes", "wsr_loss", "wsr_adam", "wsr_sort_tiles",
+            "wsr_render_sorted")
 
 
 class WsrScene(C.Structure):
@@ -43,6 +44,13 @@ class WsrParams(C.Structure):
 
 
 FLAG_UNNORMALISED = 1
+WSR_ERR_TILE_LIST = 5
+SORT_MAX = 8192
+
+
+class WsrBlend(C.Structure):
+    _fields_ = [("alpha_max", C.c_float), ("alpha_min", C.c_float), ("t_min", C.c_float),
+                ("reserved_", C.c_int32)]
 
 
 class WsrGrads(C.Structure):
@@ -98,6 +106,10 @@ def load():
     lib.wsr_loss.argtypes = [P, I32, P, P, F, P, I64, P, P, P]
     lib.wsr_adam.restype = I32
     lib.wsr_adam.argtypes = [P, P, P, P, I64, I32, F, F, F, F, P]
+    lib.wsr_sort_tiles.restype = I32
+    lib.wsr_sort_tiles.argtypes = [P, I32, P, I64, P, I64, P, I64, P]
+    lib.wsr_render_sorted.restype = I32
+    lib.wsr_render_sorted.argtypes = [P, I32, P, I64, P, P, P, I64, P, I64, P, P, P]
     if lib.wsr_abi_version() != ABI_VERSION:
         raise RuntimeError("libwsr.so ABI version mismatch; rebuild the library")
     _lib = lib

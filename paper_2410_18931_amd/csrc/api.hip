@@ -117,6 +117,7 @@ const char* wsr_status_string(int32_t status) {
     case WSR_ERR_WORKSPACE: return "workspace too small";
     case WSR_ERR_CAPACITY: return "per-tile id list overflow";
     case WSR_ERR_HIP: return "HIP runtime error";
+    case WSR_ERR_TILE_LIST: return "tile list longer than the per-tile sort takes";
     default: return "unknown status";
   }
 }
@@ -238,7 +239,37 @@ int32_t wsr_check(const void* ws, int64_t ws_bytes, void* stream) {
   hipError_t e = hipMemcpyAsync(&f, at<DevFlags>(ws, L.off_flags), sizeof(f), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return WSR_ERR_HIP;
-  return f.overflow ? WSR_ERR_CAPACITY : WSR_OK;
+  if (f.overflow) return WSR_ERR_CAPACITY;
+  return f.sort_overflow ? WSR_ERR_TILE_LIST : WSR_OK;
+}
+
+int32_t wsr_sort_tiles(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
+                       void* ws, int64_t ws_bytes, void* pairs, int64_t capacity, void* stream) {
+  static_assert(kSortMax == WSR_SORT_MAX, "sort limit");
+  if (!params_ok(params) || !ws || !pairs_ok(pairs, capacity)) return WSR_ERR_INVALID;
+  Layout L;
+  if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
+  if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
+  const hipError_t e = launch_sort_tiles(L, ws, pairs, capacity, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? WSR_OK : WSR_ERR_HIP;
+}
+
+int32_t wsr_render_sorted(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
+                          const float* globals, const wsr_blend* blend, void* ws, int64_t ws_bytes,
+                          const void* pairs, int64_t capacity, float* out_rgb, float* out_T, void* stream) {
+  if (!params_ok(params) || params->weight_kind != WSR_WEIGHT_DIR || !globals || !blend || !ws || !out_rgb ||
+      !out_T || !pairs_ok(pairs, capacity))
+    return WSR_ERR_INVALID;
+  if (!(blend->alpha_max > 0.f && blend->alpha_max <= 1.f) || !(blend->alpha_min >= 0.f) ||
+      !(blend->t_min >= 0.f))
+    return WSR_ERR_INVALID;
+  Layout L;
+  if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
+  if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
+  const hipError_t e = launch_raster_sorted(L, ws, pairs, capacity, params, globals, blend->alpha_max,
+                                            blend->alpha_min, blend->t_min, out_rgb, out_T,
+                                            static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? WSR_OK : WSR_ERR_HIP;
 }
 
 static bool loss_cams_ok(const wsr_camera* cams, int32_t n_views) {

@@ -219,6 +219,7 @@ __global__ __launch_bounds__(1024) void scan_parts(uint32_t* parts, int64_t npar
     flags->total_pairs = carry;
     flags->wrapped = carry > 0xffffffffull ? 1u : 0u;
     flags->overflow = (carry > static_cast<uint64_t>(capacity) || carry > 0xffffffffull) ? 1u : 0u;
+    flags->sort_overflow = 0u;
   }
 }
 
@@ -266,15 +267,14 @@ __global__ __launch_bounds__(256) void gauss_counts(const uint2* rect, int64_t s
   goff[k] = (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
 }
 
-// Copies every (view, Gaussian)'s first pair slot and tile rectangle into
-// its record, where the raster backward reads them with the rest of the
-// record (one cache line per pair instead of three).
-__global__ __launch_bounds__(256) void record_slots(const uint2* rect, const uint32_t* goff, int64_t slots,
-                                                    DevSplat* rec) {
+// Copies every (view, Gaussian)'s first pair slot into its record (the
+// projection stored the tile rectangle there), where the raster backward
+// reads it with the rest of the record: one cache line per pair instead of
+// three.
+__global__ __launch_bounds__(256) void record_slots(const uint32_t* goff, int64_t slots, DevSplat* rec) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (k >= slots) return;
-  const uint2 r = rect[k];
-  rec[k].slot = make_uint4(goff[k], r.x, r.y, 0u);
+  rec[k].slot.x = goff[k];
 }
 
 // Raster work items: tile t's list is cut into max(1, ceil(L / kItemSplats))
@@ -341,7 +341,7 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_in_place(goff, glen, parts, nullptr, 0, st)) != hipSuccess) return e;
   if (L.n * L.nv > 0) {
-    record_slots<<<static_cast<unsigned>((L.n * L.nv + 255) / 256), 256, 0, st>>>(a.rect, goff, L.n * L.nv,
+    record_slots<<<static_cast<unsigned>((L.n * L.nv + 255) / 256), 256, 0, st>>>(goff, L.n * L.nv,
                                                                                   at<DevSplat>(ws, L.off_rec));
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

@@ -129,7 +129,12 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
       r.r1 = make_float4(static_cast<float>(g.C), static_cast<float>(ox), static_cast<float>(oy), u * w);
       const uint32_t ext = half_bits_up(static_cast<float>(ex)) | (half_bits_up(static_cast<float>(ey)) << 16);
       r.r2 = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(ext));
-      a.rec[slot].s = r;
+      DevSplat ds;
+      ds.s = r;
+      // first pair slot filled in by binning; the camera depth orders the
+      // splats for the sorted-blending baseline
+      ds.slot = make_uint4(0u, rect.x, rect.y, __float_as_uint(static_cast<float>(g.tz)));
+      a.rec[slot] = ds;
     }
     a.rect[slot] = rect;
     if (a.out_proj) {

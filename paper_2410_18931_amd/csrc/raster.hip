@@ -538,6 +538,130 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
   }
 }
 
+// ---- Sorted alpha blending (Eq. 6): the baseline the method removes the
+// sort from.  The splats are those of the weighted sum (projected with the
+// DIR weight, so a record's amplitude is the opacity u), ordered per tile by
+// camera depth and composited front to back.
+
+// One workgroup per tile: the tile's list, keyed by (depth bits, id), is
+// sorted in LDS by a bitonic network over the next power of two (padding
+// keys sort last) and written back in place.  Lists longer than kSortMax
+// raise a flag and stay unsorted.
+__global__ __launch_bounds__(1024) void sort_tiles_kernel(const DevCamera* cams, int32_t nv, const DevSplat* rec,
+                                                          int64_t n, const uint32_t* tile_start, uint32_t* ids,
+                                                          int64_t capacity, DevFlags* flags) {
+  __shared__ uint64_t keys[kSortMax];
+  const int tile = static_cast<int>(blockIdx.x);
+  const uint64_t cap = static_cast<uint64_t>(capacity);
+  uint64_t s = tile_start[tile], e = tile_start[tile + 1];
+  s = s < cap ? s : cap;
+  e = e < cap ? e : cap;
+  if (e <= s + 1) return;
+  const int len = static_cast<int>(e - s);
+  if (e - s > static_cast<uint64_t>(kSortMax)) {
+    if (threadIdx.x == 0) flags->sort_overflow = 1u;
+    return;
+  }
+  const int v = find_view(cams, nv, tile);
+  int npow = 2;
+  while (npow < len) npow <<= 1;
+  for (int k = threadIdx.x; k < npow; k += 1024) {
+    uint64_t key = ~0ull;
+    if (k < len) {
+      const uint32_t id = ids[s + k];
+      const uint32_t depth = rec[static_cast<int64_t>(v) * n + id].slot.w;
+      key = (static_cast<uint64_t>(depth) << 32) | id;
+    }
+    keys[k] = key;
+  }
+  __syncthreads();
+  for (int size = 2; size <= npow; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (npow >> 1); i += 1024) {
+        const int lo = (i / stride) * 2 * stride + (i % stride);
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t x = keys[lo], y = keys[hi];
+        if ((x > y) == up) {
+          keys[lo] = y;
+          keys[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int k = threadIdx.x; k < len; k += 1024) ids[s + k] = static_cast<uint32_t>(keys[k]);
+}
+
+// One workgroup per tile (no splitting: the composition is sequential), the
+// same staging and per-wave culling as the weighted sum (the culled list
+// keeps the depth order); per pixel alpha = min(alpha_max, u G), layers
+// below alpha_min skipped, C += c alpha T and T *= 1 - alpha, a pixel stops
+// once T < t_min and the tile once all its pixels have stopped.
+template <int T>
+__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_sorted_kernel(RasterArgs a, float alpha_max,
+                                                                              float alpha_min, float t_min,
+                                                                              float* out_T) {
+  using G = TileGeom<T>;
+  __shared__ SplatRec s_rec[G::kBatch];
+  __shared__ __align__(16) uint8_t s_list[G::kWaves * G::kBatch];
+  TileCtx<T> c;
+  const int tile = static_cast<int>(blockIdx.x);
+  c.v = find_view(a.cams, a.nv, tile);
+  const DevCamera* cam = &a.cams[c.v];
+  const int local = tile - cam->tile_base;
+  c.tile = tile;
+  c.tx = local % cam->tiles_x;
+  c.ty = local / cam->tiles_x;
+  c.n = a.n;
+  const uint64_t cap = static_cast<uint64_t>(a.capacity);
+  uint64_t s = a.tile_start[tile], e = a.tile_start[tile + 1];
+  s = s < cap ? s : cap;
+  e = e < cap ? e : cap;
+  if (e < s) e = s;
+  c.start = static_cast<uint32_t>(s);
+  c.end = static_cast<uint32_t>(e);
+  c.k = 0;
+  c.nk = 1;
+  c.wave = threadIdx.x / kWave;
+  c.lane = threadIdx.x % kWave;
+  c.bx0 = c.tx * T + (c.wave % (T / 8)) * G::kSub;
+  c.by0 = c.ty * T + (c.wave / (T / 8)) * G::kSub;
+  c.px = c.bx0 + (c.lane & 7);
+  c.py = c.by0 + (c.lane >> 3);
+  const bool inside = c.px < cam->width && c.py < cam->height;
+  bool live = inside;
+  float cr = 0.f, cg = 0.f, cb = 0.f, Tr = 1.f;
+  const float pcx = static_cast<float>(c.px) + 0.5f;
+  const float pcy = static_cast<float>(c.py) + 0.5f;
+  const float tau = a.tau;
+  for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
+    const int m = stage_and_cull<T, G::kBatch, false>(a, c, b, s_rec, nullptr, s_list, nullptr);
+    const uint8_t* list = s_list + c.wave * G::kBatch;
+    for (int i = 0; i < m && live; ++i) {
+      const SplatRec r = s_rec[list[i]];
+      float dx, dy;
+      const float q = pair_q(r, pcx, pcy, &dx, &dy);
+      const float al = fminf(alpha_max, r.r1.w * falloff(q));
+      if (q <= tau && al >= alpha_min) {
+        const float w = al * Tr;
+        cr = fmaf(w, r.r2.x, cr);
+        cg = fmaf(w, r.r2.y, cg);
+        cb = fmaf(w, r.r2.z, cb);
+        Tr *= 1.f - al;
+        if (Tr < t_min) live = false;
+      }
+    }
+    if (!__syncthreads_or(live ? 1 : 0)) break;
+  }
+  if (!inside) return;
+  const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
+  a.out_rgb[3 * pix] = fmaf(Tr, a.globals[3], cr);
+  a.out_rgb[3 * pix + 1] = fmaf(Tr, a.globals[4], cg);
+  a.out_rgb[3 * pix + 2] = fmaf(Tr, a.globals[5], cb);
+  out_T[pix] = Tr;
+}
+
 RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capacity,
                      const wsr_params* P, const float* globals) {
   RasterArgs a = {};
@@ -615,6 +739,39 @@ hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t cap
     case 32: return bwd_t<32>(a, pd, grid, L.total_tiles, st);
     default: return bwd_t<16>(a, pd, grid, L.total_tiles, st);
   }
+}
+
+}  // namespace wsr
+
+namespace wsr {
+
+hipError_t launch_sort_tiles(const Layout& L, void* ws, void* pairs, int64_t capacity, hipStream_t st) {
+  if (L.total_tiles == 0) return hipSuccess;
+  const PairView pv = pair_view(pairs, capacity);
+  sort_tiles_kernel<<<dim3(static_cast<unsigned>(L.total_tiles)), 1024, 0, st>>>(
+      at<DevCamera>(ws, L.off_cams), L.nv, at<DevSplat>(ws, L.off_rec), L.n, at<uint32_t>(ws, L.off_tstart),
+      pv.ids, capacity, at<DevFlags>(ws, L.off_flags));
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_sorted(const Layout& L, void* ws, const void* pairs, int64_t capacity,
+                                const wsr_params* P, const float* globals, float alpha_max, float alpha_min,
+                                float t_min, float* out_rgb, float* out_T, hipStream_t st) {
+  if (L.total_tiles == 0) return hipSuccess;
+  RasterArgs a = make_args(L, ws, pairs, capacity, P, globals);
+  a.out_rgb = out_rgb;
+  const dim3 grid(static_cast<unsigned>(L.total_tiles));
+  switch (L.tile) {
+    case 8:
+      raster_sorted_kernel<8><<<grid, TileGeom<8>::kThreads, 0, st>>>(a, alpha_max, alpha_min, t_min, out_T);
+      break;
+    case 32:
+      raster_sorted_kernel<32><<<grid, TileGeom<32>::kThreads, 0, st>>>(a, alpha_max, alpha_min, t_min, out_T);
+      break;
+    default:
+      raster_sorted_kernel<16><<<grid, TileGeom<16>::kThreads, 0, st>>>(a, alpha_max, alpha_min, t_min, out_T);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace wsr

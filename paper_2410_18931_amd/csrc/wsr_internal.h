@@ -41,9 +41,11 @@ struct __align__(16) SplatRec {
 
 // The record as stored in HBM: 64 bytes, so that no record straddles a cache
 // line, with the pair-slot data the raster backward needs appended:
-//   slot = (goff, rect.x, rect.y, 0): the Gaussian's first Gaussian-major
-//   pair slot (written by binning) and its tile rectangle (x0 | x1 << 16,
-//   y0 | y1 << 16).
+//   slot = (goff, rect.x, rect.y, depth): the Gaussian's first Gaussian-major
+//   pair slot (written by binning), its tile rectangle (x0 | x1 << 16,
+//   y0 | y1 << 16) and its camera depth t_z as float bits (the sort key of
+//   the sorted-blending baseline; positive, so the bits order like the
+//   values).
 struct __align__(64) DevSplat {
   SplatRec s;
   uint4 slot;
@@ -72,7 +74,13 @@ struct DevFlags {
   uint32_t overflow;        // id-list capacity exceeded
   uint32_t wrapped;         // 32-bit pair count wrapped
   uint64_t total_pairs;     // pairs produced by the last binning
+  uint32_t sort_overflow;   // a tile list longer than the per-tile sort takes
+  uint32_t pad_;
 };
+
+// Longest tile list the per-tile depth sort of the sorted-blending baseline
+// holds in LDS (64-bit keys, 64 KB).
+constexpr int kSortMax = 8192;
 
 struct Layout {
   int64_t n = 0;
@@ -159,6 +167,10 @@ hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const fl
                               const Layout& L, void* ws, const void* pairs, int64_t capacity,
                               const wsr_grads* g, float* out_grad2d, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_sort_tiles(const Layout& L, void* ws, void* pairs, int64_t capacity, hipStream_t st);
+hipError_t launch_raster_sorted(const Layout& L, void* ws, const void* pairs, int64_t capacity,
+                                const wsr_params* P, const float* globals, float alpha_max, float alpha_min,
+                                float t_min, float* out_rgb, float* out_T, hipStream_t st);
 int64_t loss_workspace_bytes(const wsr_camera* cams, int32_t nv);
 hipError_t launch_loss(const wsr_camera* cams, int32_t nv, const float* img, const float* target, float lambda,
                        void* ws, float* loss, float* dL, hipStream_t st);

@@ -159,6 +159,29 @@ class WSRContext:
         _lib.check("wsr_render_fwd", st)
         return (rgb, den, cnt) if count else (rgb, den)
 
+    def render_sorted(self, globals_: torch.Tensor, alpha_max: float = 0.99, alpha_min: float = 0.0,
+                      t_min: float = 0.0, out=None):
+        """Sorted alpha blending of the binned splats (Eq. 6, the baseline
+        without the method): sort every tile list by depth, then composite
+        front to back.  The context's settings must use the DIR weight.
+        Returns (rgb [P][3], final transmittance [P])."""
+        if self.settings.weight_kind != "dir":
+            raise ValueError("sorted blending needs weight_kind='dir' (the amplitude must be the opacity)")
+        if out is None:
+            rgb = torch.empty((self.total_pixels, 3), dtype=torch.float32, device=self.device)
+            T = torch.empty((self.total_pixels,), dtype=torch.float32, device=self.device)
+        else:
+            rgb, T = out
+        st = self.lib.wsr_sort_tiles(self.cams_c, self.nv, C.byref(self.params), self.n, _ptr(self.ws),
+                                     self.ws_bytes, _ptr(self.pairs), self.capacity, _stream())
+        _lib.check("wsr_sort_tiles", st)
+        blend = _lib.WsrBlend(float(alpha_max), float(alpha_min), float(t_min), 0)
+        st = self.lib.wsr_render_sorted(self.cams_c, self.nv, C.byref(self.params), self.n, _ptr(globals_),
+                                        C.byref(blend), _ptr(self.ws), self.ws_bytes, _ptr(self.pairs),
+                                        self.capacity, _ptr(rgb), _ptr(T), _stream())
+        _lib.check("wsr_render_sorted", st)
+        return rgb, T
+
     def alloc_grads(self, scene: dict) -> dict:
         dev = self.device
         K = scene["sh"].shape[0]

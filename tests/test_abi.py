@@ -118,3 +118,25 @@ def test_loss_and_adam_reject_bad_arguments_before_launch():
     assert lib.wsr_adam(dummy, dummy, dummy, dummy, 10, 1, F(0.1), F(1.0), F(0.999), F(1e-15), None) == INV
     assert lib.wsr_adam(None, dummy, dummy, dummy, 10, 1, F(0.1), F(0.9), F(0.999), F(1e-15), None) == INV
     assert lib.wsr_adam(None, None, None, None, 0, 1, F(0.1), F(0.9), F(0.999), F(1e-15), None) == _lib.WSR_OK
+
+
+def test_sorted_entry_points_reject_bad_arguments_before_launch():
+    lib = _lib.load()
+    _, cams, st = ws.make_scene("c1", n=8)
+    cc = _lib.make_cameras(cams)
+    dummy = C.c_void_p(0x1000)
+    INV = _lib.WSR_ERR_INVALID
+    p_exp = _lib.make_params(st)                      # EXP weight: not allowed for sorted blending
+    p_dir = _lib.make_params(st.copy(weight_kind="dir"))
+    ok = _lib.WsrBlend(0.99, 0.0, 0.0, 0)
+    assert lib.wsr_render_sorted(cc, 1, C.byref(p_exp), 8, dummy, C.byref(ok), dummy, 1 << 30, dummy, 10,
+                                 dummy, dummy, None) == INV
+    for bad in (_lib.WsrBlend(0.0, 0.0, 0.0, 0), _lib.WsrBlend(1.5, 0.0, 0.0, 0), _lib.WsrBlend(0.9, -1.0, 0.0, 0),
+                _lib.WsrBlend(0.9, 0.0, -1.0, 0)):
+        assert lib.wsr_render_sorted(cc, 1, C.byref(p_dir), 8, dummy, C.byref(bad), dummy, 1 << 30, dummy, 10,
+                                     dummy, dummy, None) == INV
+    assert lib.wsr_render_sorted(cc, 1, C.byref(p_dir), 8, dummy, C.byref(ok), dummy, 16, dummy, 10,
+                                 dummy, dummy, None) == _lib.WSR_ERR_WORKSPACE
+    assert lib.wsr_sort_tiles(cc, 1, C.byref(p_dir), 8, dummy, 1 << 30, C.c_void_p(0x1004), 10, None) == INV
+    assert lib.wsr_sort_tiles(cc, 1, C.byref(p_dir), 8, dummy, 16, dummy, 10, None) == _lib.WSR_ERR_WORKSPACE
+    assert "sort" in _lib.status_string(_lib.WSR_ERR_TILE_LIST)
