@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wsr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-PROJ_STRIDE = 24
+PROJ_STRIDE = 25
 WEIGHT_KINDS = {"dir": 0, "exp": 1, "lc": 2}
 OPACITY_MODES = {"logit": 0, "sh": 1}
 
@@ -50,7 +50,7 @@ class _Params(C.Structure):
     _fields_ = [("weight_kind", C.c_int32), ("pad_", C.c_int32), ("sigma", C.c_double),
                 ("beta", C.c_double), ("w_bg", C.c_double), ("bg", C.c_double * 3),
                 ("tau", C.c_double), ("dilation", C.c_double), ("near_z", C.c_double),
-                ("opacity_offset", C.c_double)]
+                ("opacity_offset", C.c_double), ("alpha_cut", C.c_double)]
 
 
 _lib = None
@@ -108,7 +108,8 @@ class _Packed:
                            int(cam["width"]), int(cam["height"]), (C.c_int32 * 2)(0, 0))
         self.params = _Params(WEIGHT_KINDS[settings.weight_kind], 0, settings.sigma, settings.beta,
                               settings.w_bg, (C.c_double * 3)(*settings.bg), settings.tau,
-                              settings.dilation, settings.near, settings.opacity_offset)
+                              settings.dilation, settings.near, settings.opacity_offset,
+                              getattr(settings, "alpha_cut", 0.0))
 
 
 def num_threads() -> int:
@@ -125,6 +126,7 @@ def project(scene, cam, settings) -> dict:
         "visible": out[:, 0] > 0.5, "mu": out[:, 1:3], "cov2d": out[:, 3:6],
         "conic": out[:, 6:9], "rgb": out[:, 9:12], "u": out[:, 12], "w": out[:, 13],
         "depth": out[:, 14], "t": out[:, 15:18], "dir": out[:, 18:21], "rgb_raw": out[:, 21:24],
+        "cut": out[:, 24],
     }
 
 

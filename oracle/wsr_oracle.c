@@ -67,14 +67,15 @@ typedef struct {
     double sigma, beta;
     double w_bg, bg[3];
     double tau, dilation, near_z, opacity_offset;
+    double alpha_cut;        /* opacity early-out (App. D): 0 = off */
 } ora_params;
 
 /* Per-Gaussian projected quantities exported for stage-wise checks.  Layout of
  * one row of ora_project's output (ORA_PROJ_STRIDE doubles):
  *  0 visible, 1-2 mu, 3-5 cov2d (a, b, c), 6-8 conic (A, B, C),
  *  9-11 rgb (clamped), 12 u, 13 w, 14 depth, 15-17 t (camera space),
- *  18-20 view direction, 21-23 rgb before the clamp                           */
-#define ORA_PROJ_STRIDE 24
+ *  18-20 view direction, 21-23 rgb before the clamp, 24 support cutoff      */
+#define ORA_PROJ_STRIDE 25
 
 typedef struct {
     int visible;
@@ -87,6 +88,7 @@ typedef struct {
     double raw[3];
     double rgb[3];
     double u, w, depth;
+    double cut;       /* pairs with q <= cut contribute (tau, or less with the early-out) */
     double Y[ORA_MAX_K];
 } proj_t;
 
@@ -281,6 +283,16 @@ static void project_one(const ora_scene *S, const ora_camera *cam, const ora_par
         const double lin = 1.0 - tz / P->sigma;
         o->w = (lin > 0.0 ? lin : 0.0) * S->lc_v[i];
     }
+    /* Opacity early-out, the heuristic App. D proposes as future work (off
+     * with alpha_cut = 0): a pair contributes only while its opacity
+     * u exp(-q/2) is at least alpha_cut, i.e. q <= 2 ln(u / alpha_cut); a
+     * Gaussian with u <= alpha_cut never does. */
+    o->cut = P->tau;
+    if (P->alpha_cut > 0.0) {
+        if (!(o->u > P->alpha_cut)) return;
+        const double c = 2.0 * log(o->u / P->alpha_cut);
+        if (c < o->cut) o->cut = c;
+    }
     o->visible = 1;
 }
 
@@ -305,6 +317,7 @@ void ora_project(const ora_scene *S, const ora_camera *cam, const ora_params *P,
             r[21 + c] = g.raw[c];
         }
         r[12] = g.u; r[13] = g.w;
+        r[24] = g.cut;
     }
 }
 
@@ -375,7 +388,7 @@ static void collect_visible(const ora_scene *S, const ora_camera *cam, const ora
     for (int64_t i = 0; i < n; ++i) {
         project_one(S, cam, P, i, &all[i]);
         if (!all[i].visible) continue;
-        support_box(&all[i], P->tau, boxes + 4 * i);
+        support_box(&all[i], all[i].cut, boxes + 4 * i);
         const int64_t *b = boxes + 4 * i;
         keep[i] = (b[1] >= x0 && b[0] < x1 && b[3] >= y0 && b[2] < y1);
     }
@@ -415,7 +428,8 @@ static void free_visible(vis_t *v)
  *          window list (the window list only drops Gaussians whose exact
  *          ellipse box misses the window);
  *   mode 1 ("aabb"): every Gaussian only visits the pixels of its own box.
- * Both visit exactly the pairs with q <= tau; they differ in summation order.
+ * Both visit exactly the pairs with q <= cut (cut = tau unless the opacity
+ * early-out lowers it, see project_one); they differ in summation order.
  * Outputs, each [h][w] row-major with h = y1-y0, w = x1-x0:
  *   out_C [h][w][3]   colour; den == 0 gives the background colour
  *   out_num [h][w][3] numerator including c_B w_B
@@ -455,7 +469,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                 for (int64_t j = 0; j < v.m; ++j) {
                     const proj_t *g = &v.g[j];
                     const double q = pair_q(g, x0 + xx, y0 + yy);
-                    if (q <= tau) {
+                    if (q <= g->cut) {
                         const double a = g->u * g->w * exp(-0.5 * q);
                         nr += a * g->rgb[0];
                         ng += a * g->rgb[1];
@@ -483,7 +497,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                 const int64_t hi = b[1] < x1 - 1 ? b[1] : x1 - 1;
                 for (int64_t px = lo; px <= hi; ++px) {
                     const double q = pair_q(g, px, py);
-                    if (q <= tau) {
+                    if (q <= g->cut) {
                         const double a = g->u * g->w * exp(-0.5 * q);
                         const int64_t o = yy * w + (px - x0);
                         num[3 * o] += a * g->rgb[0];
@@ -515,7 +529,8 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
     }
 
     if (out_amb || out_ambc) {
-        /* pairs whose support decision is within eta*tau of the cutoff */
+        /* pairs whose support decision is within eta*M of the cutoff (plus the
+         * float error of a computed early-out cutoff) */
         #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t yy = 0; yy < h; ++yy)
             for (int64_t xx = 0; xx < w; ++xx) {
@@ -528,7 +543,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                     const double dy = (double)(y0 + yy) + 0.5 - g->mu[1];
                     const double M = g->conic[0] * dx * dx + 2.0 * fabs(g->conic[1] * dx * dy) +
                                      g->conic[2] * dy * dy;
-                    if (fabs(q - tau) <= eta * M) {
+                    if (fabs(q - g->cut) <= eta * M + (g->cut < tau ? 10.0 * eta * (fabs(g->cut) + 1.0) : 0.0)) {
                         const double a = fabs(g->u * g->w * exp(-0.5 * q));
                         double md = 0.0;
                         for (int c = 0; c < 3; ++c) {
@@ -586,7 +601,6 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
 
     vis_t v;
     collect_visible(S, cam, P, x0, y0, x1, y1, &v);
-    const double tau = P->tau;
 
     /* pass 1: per-pixel sums, colour, and the two per-pixel factors of the
      * gradient: gbar_c = g_c / den and s = sum_c gbar_c C_c */
@@ -604,7 +618,7 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
                 for (int64_t j = 0; j < v.m; ++j) {
                     const proj_t *g = &v.g[j];
                     const double q = pair_q(g, x0 + xx, y0 + yy);
-                    if (q <= tau) {
+                    if (q <= g->cut) {
                         const double a = g->u * g->w * exp(-0.5 * q);
                         for (int c = 0; c < 3; ++c) N3[c] += a * g->rgb[c];
                         D += a;
@@ -654,7 +668,7 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
         for (int64_t py = ylo; py <= yhi; ++py)
             for (int64_t px = xlo; px <= xhi; ++px) {
                 const double q = pair_q(g, px, py);
-                if (!(q <= tau)) continue;
+                if (!(q <= g->cut)) continue;
                 const int64_t o = (py - y0) * w + (px - x0);
                 const double G = exp(-0.5 * q);
                 const double a = as * G;

@@ -81,6 +81,7 @@ class Settings:
     near: float = 0.2
     opacity_offset: float = 0.5
     tile: int = 16
+    alpha_cut: float = 0.0            # opacity early-out threshold (0: off)
 
     def copy(self, **kw) -> "Settings":
         d = dict(self.__dict__)
