@@ -83,6 +83,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU baseline sample")
     ap.add_argument("--graph", action="store_true", help="time replays of the whole step captured as one HIP graph")
+    ap.add_argument("--alpha-cut", type=float, default=0.0,
+                    help="opacity early-out threshold (0: off); the line then also reports the image error "
+                         "against the exact renderer")
     ap.add_argument("--mode", default="render", choices=["render", "train", "sorted"],
                     help="render: forward + backward of the renderer (the headline metric); train: whole "
                          "training steps (forward, l1 + 0.2 D-SSIM loss, backward, Adam); sorted: forward "
@@ -304,7 +307,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     scene, cams, st = ws.make_scene(args.config)
-    st = st.copy(tile=args.tile)
+    st = st.copy(tile=args.tile, alpha_cut=args.alpha_cut)
     n = scene["means"].shape[1]
     dev = scene_to_device(scene, storage=args.storage)
     g = globals_tensor(st)
@@ -407,6 +410,7 @@ def main():
                        f"one {cams[0]['width']}x{cams[0]['height']} view" if ctx.nv == 1 else
                        f"{ctx.nv} views of uneven size, {P:,} px in total") +
                        f", tile {args.tile}, {args.storage} attribute storage" +
+                       (f", opacity early-out at {args.alpha_cut:g}" if args.alpha_cut > 0 else "") +
                        (", whole step replayed as one HIP graph" if args.graph else ""),
                    "gaussians": n, "views": ctx.nv, "pixels": P, "tile": args.tile, "storage": args.storage,
                    "graph": bool(args.graph)},
@@ -424,6 +428,13 @@ def main():
                      "launch_ms": round(stage_ms[dominant], 4), "algorithmic_bytes": ab[dominant]},
         "stage_hbm_gbs": {k: round(ab[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in names},
     }
+    if args.alpha_cut > 0:
+        exact = WSRContext(n, cams, st.copy(alpha_cut=0.0))
+        rgb_exact, _ = exact.forward(dev, g)
+        rgb_cut, _ = ctx.forward(dev, g)
+        diff = (rgb_cut - rgb_exact).abs()
+        out["early_out"] = {"alpha_cut": args.alpha_cut, "binned_pairs_exact": exact.last_pairs,
+                            "image_err_vs_exact": {"max": diff.max().item(), "mean": diff.mean().item()}}
     if not args.no_cpu_baseline:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, cams, st, args.cpu_seconds)

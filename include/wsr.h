@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define WSR_ABI_VERSION 2
+#define WSR_ABI_VERSION 3
 #define WSR_MAX_VIEWS 256
 
 typedef enum {
@@ -98,7 +98,11 @@ typedef struct {
 
 /* Renderer settings.  tau is the support cutoff on q (a pair contributes iff
  * q <= tau); dilation is added to the diagonal of Sigma2D (px^2); near culls
- * Gaussians with camera-space z <= near; tile is 8, 16 or 32. */
+ * Gaussians with camera-space z <= near; tile is 8, 16 or 32.
+ * alpha_cut > 0 enables the opacity early-out that App. D proposes: a pair
+ * also needs u exp(-q/2) >= alpha_cut (so q <= 2 ln(u / alpha_cut)), and a
+ * Gaussian with u <= alpha_cut is culled.  It changes the image (opt-in);
+ * 0 turns it off.  The sorted-blending entry points require 0. */
 typedef struct {
     int32_t weight_kind;       /* wsr_weight_kind */
     int32_t tile;              /* 8 | 16 | 32 */
@@ -107,7 +111,7 @@ typedef struct {
     float near_z;              /* 0.2 */
     float opacity_offset;      /* 0.5; SH opacity mode only */
     int32_t flags;             /* WSR_FLAG_* */
-    int32_t reserved_;
+    float alpha_cut;           /* opacity early-out threshold, >= 0; 0 = off */
 } wsr_params;
 
 /* wsr_render_fwd writes the raw sums instead of the image: out_rgb receives

@@ -101,7 +101,8 @@ bool scene_ok(const wsr_scene* s, int32_t weight_kind) {
 bool params_ok(const wsr_params* p) {
   return p && p->weight_kind >= WSR_WEIGHT_DIR && p->weight_kind <= WSR_WEIGHT_LC &&
          (p->tile == 8 || p->tile == 16 || p->tile == 32) && std::isfinite(p->tau) && p->tau >= 0.f &&
-         std::isfinite(p->dilation) && std::isfinite(p->near_z);
+         std::isfinite(p->dilation) && std::isfinite(p->near_z) && std::isfinite(p->alpha_cut) &&
+         p->alpha_cut >= 0.f;
 }
 
 }  // namespace
@@ -246,7 +247,7 @@ int32_t wsr_check(const void* ws, int64_t ws_bytes, void* stream) {
 int32_t wsr_sort_tiles(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
                        void* ws, int64_t ws_bytes, void* pairs, int64_t capacity, void* stream) {
   static_assert(kSortMax == WSR_SORT_MAX, "sort limit");
-  if (!params_ok(params) || !ws || !pairs_ok(pairs, capacity)) return WSR_ERR_INVALID;
+  if (!params_ok(params) || params->alpha_cut != 0.f || !ws || !pairs_ok(pairs, capacity)) return WSR_ERR_INVALID;
   Layout L;
   if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
   if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
@@ -257,7 +258,8 @@ int32_t wsr_sort_tiles(const wsr_camera* cams, int32_t n_views, const wsr_params
 int32_t wsr_render_sorted(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
                           const float* globals, const wsr_blend* blend, void* ws, int64_t ws_bytes,
                           const void* pairs, int64_t capacity, float* out_rgb, float* out_T, void* stream) {
-  if (!params_ok(params) || params->weight_kind != WSR_WEIGHT_DIR || !globals || !blend || !ws || !out_rgb ||
+  if (!params_ok(params) || params->weight_kind != WSR_WEIGHT_DIR || params->alpha_cut != 0.f || !globals ||
+      !blend || !ws || !out_rgb ||
       !out_T || !pairs_ok(pairs, capacity))
     return WSR_ERR_INVALID;
   if (!(blend->alpha_max > 0.f && blend->alpha_max <= 1.f) || !(blend->alpha_min >= 0.f) ||

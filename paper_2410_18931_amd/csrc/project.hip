@@ -35,7 +35,7 @@ struct ProjArgs {
   int32_t opa_mode;
   int32_t weight_kind;
   int32_t tile;
-  float tau, dilation, near_z, opacity_offset;
+  float tau, dilation, near_z, opacity_offset, alpha_cut;
 };
 
 // float -> fp16 bits, rounded towards +inf (the support extents must never
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
     float rgb[3] = {0.f, 0.f, 0.f};
     float u = 0.f, w = 0.f;
     uint2 rect = make_uint2(0u, 0u);
+    bool alive = vis;
     if (vis) {
       // ---- a4: SH colour and opacity at the view direction ----
       double dir[3], len;
@@ -107,13 +108,21 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
         w = fmaxf(1.f - d / sigma, 0.f) * lcv;
       }
 
-      // ---- support box of q <= tau, widened so float rounding of q never
+      // ---- opacity early-out (App. D; off with alpha_cut = 0): a pair
+      // contributes only while u exp(-q/2) >= alpha_cut, i.e. while
+      // q <= 2 ln(u / alpha_cut); a Gaussian with u <= alpha_cut never does
+      double cut = a.tau;
+      if (a.alpha_cut > 0.f) {
+        alive = u > a.alpha_cut;
+        if (alive) cut = fmin(cut, 2.0 * log(static_cast<double>(u) / static_cast<double>(a.alpha_cut)));
+      }
+      // ---- support box of q <= cut, widened so float rounding of q never
       // reaches a pixel outside it ----
-      const double ex = sqrt(static_cast<double>(a.tau) * g.c00) * (1.0 + 1e-4) + 1e-3;
-      const double ey = sqrt(static_cast<double>(a.tau) * g.c11) * (1.0 + 1e-4) + 1e-3;
+      const double ex = sqrt(cut * g.c00) * (1.0 + 1e-4) + 1e-3;
+      const double ey = sqrt(cut * g.c11) * (1.0 + 1e-4) + 1e-3;
       const double plo_x = ceil(g.mux - ex - 0.5), phi_x = floor(g.mux + ex - 0.5);
       const double plo_y = ceil(g.muy - ey - 0.5), phi_y = floor(g.muy + ey - 0.5);
-      if (phi_x >= 0.0 && plo_x <= cam.width - 1.0 && phi_y >= 0.0 && plo_y <= cam.height - 1.0) {
+      if (alive && phi_x >= 0.0 && plo_x <= cam.width - 1.0 && phi_y >= 0.0 && plo_y <= cam.height - 1.0) {
         const int T = a.tile;
         const int x0 = static_cast<int>(fmax(plo_x, 0.0)) / T;
         const int x1 = static_cast<int>(fmin(phi_x, cam.width - 1.0)) / T + 1;
@@ -127,8 +136,11 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
       r.r0 = make_float4(static_cast<float>(g.mux - ox), static_cast<float>(g.muy - oy),
                          static_cast<float>(g.A), static_cast<float>(2.0 * g.B));
       r.r1 = make_float4(static_cast<float>(g.C), static_cast<float>(ox), static_cast<float>(oy), u * w);
+      // the fourth word: the support half-extents for culling, or with the
+      // early-out the splat's own cutoff (the raster then derives the
+      // extents from the conic)
       const uint32_t ext = half_bits_up(static_cast<float>(ex)) | (half_bits_up(static_cast<float>(ey)) << 16);
-      r.r2 = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(ext));
+      r.r2 = make_float4(rgb[0], rgb[1], rgb[2], a.alpha_cut > 0.f ? static_cast<float>(cut) : __uint_as_float(ext));
       DevSplat ds;
       ds.s = r;
       // first pair slot filled in by binning; the camera depth orders the
@@ -139,7 +151,7 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
     a.rect[slot] = rect;
     if (a.out_proj) {
       float4* o = reinterpret_cast<float4*>(a.out_proj + slot * 16);
-      o[0] = make_float4(vis ? 1.f : 0.f, vis ? static_cast<float>(g.mux) : 0.f,
+      o[0] = make_float4(alive ? 1.f : 0.f, vis ? static_cast<float>(g.mux) : 0.f,
                          vis ? static_cast<float>(g.muy) : 0.f, vis ? static_cast<float>(g.A) : 0.f);
       o[1] = make_float4(vis ? static_cast<float>(g.B) : 0.f, vis ? static_cast<float>(g.C) : 0.f, rgb[0], rgb[1]);
       o[2] = make_float4(rgb[2], u, w, static_cast<float>(g.tz));
@@ -211,6 +223,7 @@ hipError_t launch_project(const wsr_scene* sc, const wsr_params* P, const float*
   a.weight_kind = P->weight_kind;
   a.tile = P->tile;
   a.tau = P->tau;
+  a.alpha_cut = P->alpha_cut;
   a.dilation = P->dilation;
   a.near_z = P->near_z;
   a.opacity_offset = P->opacity_offset;

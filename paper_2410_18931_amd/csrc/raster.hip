@@ -67,8 +67,26 @@ __device__ __forceinline__ float2 rec_extent(const SplatRec& r) {
 // a margin far above the float error of q.  For needle-like splats
 // (eigenvalue ratio above ~100) float q loses digits to cancellation, so the
 // box decision is kept.
-__device__ __forceinline__ bool block_hits(const SplatRec& r, float bx, float by, float sub1, float tau) {
-  const float2 e = rec_extent(r);
+//
+// With CUT (the opacity early-out) the record's fourth word is the splat's
+// own cutoff instead of the half-extents, which are then derived from the
+// conic: the extents of q <= cut are sqrt(cut C / det) and sqrt(cut A / det),
+// with det = A C - B^2 formed by Kahan's algorithm (B^2 split exactly with an
+// FMA) so that it stays accurate for needle-like conics.
+template <bool CUT>
+__device__ __forceinline__ bool block_hits(const SplatRec& r, float bx, float by, float sub1, float tau_in) {
+  float2 e;
+  float tau = tau_in;
+  if (CUT) {
+    tau = r.r2.w;
+    const float A = r.r0.z, B = 0.5f * r.r0.w, C = r.r1.x;
+    const float bb = B * B;
+    const float det = fmaf(A, C, -bb) - fmaf(B, B, -bb);
+    const float s = det > 0.f ? tau / det : __builtin_inff();
+    e = make_float2(sqrtf(s * C) * 1.0001f, sqrtf(s * A) * 1.0001f);
+  } else {
+    e = rec_extent(r);
+  }
   const float ox = r.r1.y, oy = r.r1.z, fx = r.r0.x, fy = r.r0.y;
   const float mx = ox + fx, my = oy + fy;
   const float sx = 1e-3f * fabsf(mx) + 1e-2f, sy = 1e-3f * fabsf(my) + 1e-2f;  // rounding slack
@@ -189,7 +207,7 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
 // first slot plus this tile's row-major index in its tile rectangle, the
 // order in which binning enumerated its pairs -- and, per staged record, its
 // position in this wave's list (0xffff if culled).
-template <int T, int BATCH, bool SLOTS>
+template <int T, int BATCH, bool SLOTS, bool CUT>
 __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
                                               SplatRec* s_rec, uint32_t* s_slot, uint8_t* s_list,
                                               uint16_t* s_pos) {
@@ -214,7 +232,7 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
   const float bx = c.bx0 + 0.5f, by = c.by0 + 0.5f;
   for (int k0 = 0; k0 < cnt; k0 += kWave) {
     const int k = k0 + c.lane;
-    const bool hit = k < cnt && block_hits(s_rec[k], bx, by, static_cast<float>(G::kSub - 1), a.tau);
+    const bool hit = k < cnt && block_hits<CUT>(s_rec[k], bx, by, static_cast<float>(G::kSub - 1), a.tau);
     const uint64_t mask = __ballot(hit);
     const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
     if (hit) list[pos] = static_cast<uint8_t>(k);
@@ -253,7 +271,7 @@ __device__ __forceinline__ void write_pixel(const RasterArgs& a, int64_t pix, fl
   a.out_den[pix] = D;
 }
 
-template <int T, bool COUNT>
+template <int T, bool COUNT, bool CUT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
   __shared__ SplatRec s_rec[G::kBatch];
@@ -268,7 +286,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   const float pcy = static_cast<float>(c.py) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T, G::kBatch, false>(a, c, b, s_rec, nullptr, s_list, nullptr);
+    const int m = stage_and_cull<T, G::kBatch, false, CUT>(a, c, b, s_rec, nullptr, s_list, nullptr);
     const uint8_t* list = s_list + c.wave * G::kBatch;
     // four splats per step: one 4-byte read fetches their list entries and
     // all four records are requested before any arithmetic, so LDS latency
@@ -276,12 +294,13 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
     auto accumulate = [&](const SplatRec& r) {
       float dx, dy;
       const float q = pair_q(r, pcx, pcy, &dx, &dy);
-      const float al = q <= tau ? r.r1.w * falloff(q) : 0.f;
+      const float cut = CUT ? r.r2.w : tau;
+      const float al = q <= cut ? r.r1.w * falloff(q) : 0.f;
       nr = fmaf(al, r.r2.x, nr);
       ng = fmaf(al, r.r2.y, ng);
       nb = fmaf(al, r.r2.z, nb);
       dd += al;
-      if (COUNT) cntp += q <= tau ? 1 : 0;
+      if (COUNT) cntp += q <= cut ? 1 : 0;
     };
     int i = 0;
     for (; i + 4 <= m; i += 4) {
@@ -352,7 +371,7 @@ __device__ __forceinline__ float wave_sum(float x) {
 // All lanes walk the same pixel at the same time, so the per-pixel factors
 // (gbar, s) from the prepass (raster_bwd_prep) are read with scalar loads at
 // a wave-uniform address and enter the FMAs as scalar operands.
-template <int T>
+template <int T, bool CUT>
 __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
                                           const SplatRec* s_rec, const float4* __restrict__ pd_wave,
                                           float (*out)[kWave], float tau) {
@@ -364,6 +383,7 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
   float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
   float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
   const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
+  const float cut = CUT ? r.r2.w : tau;
   // first pixel centre of the block relative to the splat's integer origin
   // (exact), so dx = (ex0 + col) - fx matches the forward's
   const float ex0 = (static_cast<float>(c.bx0) + 0.5f) - r.r1.y;
@@ -378,7 +398,7 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
       const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
       const float q = quad_form(A, B2dy, Cdy2, dx);
       const float4 pd = pd_wave[row * 8 + col];  // wave-uniform: SGPRs
-      const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
+      const float Gq = (valid && q <= cut) ? falloff(q) : 0.f;
       const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
       const float e = Gq * dLda;
       S0 += e;
@@ -479,7 +499,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterA
 // order.  At the end of the batch the owner stores the record's sums, zeros
 // included, with plain stores at the pair's Gaussian-major slot.  The
 // summation order is fixed, so the result does not vary from run to run.
-template <int T>
+template <int T, bool CUT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(RasterArgs a,
                                                                            const float4* __restrict__ pdg) {
   using G = TileGeom<T>;
@@ -500,7 +520,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
   const float tau = a.tau;
   const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
   for (uint32_t b = c.start; b < c.end; b += kB) {
-    const int m = stage_and_cull<T, kB, true>(a, c, b, s_rec, s_slot, s_list, s_pos);
+    const int m = stage_and_cull<T, kB, true, CUT>(a, c, b, s_rec, s_slot, s_list, s_pos);
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kB), c.end - b));
     if (c.lane == 0) s_m[c.wave] = m;
     __syncthreads();
@@ -512,7 +532,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = 0.f;
     for (int r = 0; r < rounds; ++r) {
-      if (r * kWave < m) bwd_chunk<T>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
+      if (r * kWave < m) bwd_chunk<T, CUT>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
       __syncthreads();
       if (own < cnt) {
 #pragma unroll
@@ -636,7 +656,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_sorted_kernel(Ra
   const float pcy = static_cast<float>(c.py) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T, G::kBatch, false>(a, c, b, s_rec, nullptr, s_list, nullptr);
+    const int m = stage_and_cull<T, G::kBatch, false, false>(a, c, b, s_rec, nullptr, s_list, nullptr);
     const uint8_t* list = s_list + c.wave * G::kBatch;
     for (int i = 0; i < m && live; ++i) {
       const SplatRec r = s_rec[list[i]];
@@ -684,19 +704,30 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
 }
 
 template <int T>
-hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, bool count, hipStream_t st) {
-  if (count)
-    raster_fwd_kernel<T, true><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a);
-  else
-    raster_fwd_kernel<T, false><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a);
+hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, bool count, bool cut, hipStream_t st) {
+  const dim3 g(static_cast<unsigned>(grid));
+  if (cut) {
+    if (count)
+      raster_fwd_kernel<T, true, true><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
+    else
+      raster_fwd_kernel<T, false, true><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
+  } else {
+    if (count)
+      raster_fwd_kernel<T, true, false><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
+    else
+      raster_fwd_kernel<T, false, false><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
+  }
   raster_fwd_finalize<T><<<dim3(static_cast<unsigned>(tiles)), 256, 0, st>>>(a);
   return hipGetLastError();
 }
 
 template <int T>
-hipError_t bwd_t(const RasterArgs& a, float4* pd, int64_t grid, int64_t tiles, hipStream_t st) {
+hipError_t bwd_t(const RasterArgs& a, float4* pd, int64_t grid, int64_t tiles, bool cut, hipStream_t st) {
   raster_bwd_prep<T><<<dim3(static_cast<unsigned>(tiles)), TileGeom<T>::kThreads, 0, st>>>(a, pd);
-  raster_bwd_kernel<T><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a, pd);
+  if (cut)
+    raster_bwd_kernel<T, true><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a, pd);
+  else
+    raster_bwd_kernel<T, false><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a, pd);
   return hipGetLastError();
 }
 
@@ -717,9 +748,9 @@ hipError_t launch_raster_fwd(const Layout& L, void* ws, const void* pairs, int64
   }
   const int64_t grid = max_raster_items(L, capacity);
   switch (L.tile) {
-    case 8: return fwd_t<8>(a, grid, L.total_tiles, cnt, st);
-    case 32: return fwd_t<32>(a, grid, L.total_tiles, cnt, st);
-    default: return fwd_t<16>(a, grid, L.total_tiles, cnt, st);
+    case 8: return fwd_t<8>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, st);
+    case 32: return fwd_t<32>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, st);
+    default: return fwd_t<16>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, st);
   }
 }
 
@@ -735,9 +766,9 @@ hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t cap
   const int64_t grid = max_raster_items(L, capacity);
   float4* pd = at<float4>(ws, L.off_pd);
   switch (L.tile) {
-    case 8: return bwd_t<8>(a, pd, grid, L.total_tiles, st);
-    case 32: return bwd_t<32>(a, pd, grid, L.total_tiles, st);
-    default: return bwd_t<16>(a, pd, grid, L.total_tiles, st);
+    case 8: return bwd_t<8>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, st);
+    case 32: return bwd_t<32>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, st);
+    default: return bwd_t<16>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, st);
   }
 }
 
