@@ -50,7 +50,8 @@ class _Params(C.Structure):
     _fields_ = [("weight_kind", C.c_int32), ("pad_", C.c_int32), ("sigma", C.c_double),
                 ("beta", C.c_double), ("w_bg", C.c_double), ("bg", C.c_double * 3),
                 ("tau", C.c_double), ("dilation", C.c_double), ("near_z", C.c_double),
-                ("opacity_offset", C.c_double), ("alpha_cut", C.c_double)]
+                ("opacity_offset", C.c_double), ("alpha_cut", C.c_double), ("oit", C.c_int32),
+                ("pad2_", C.c_int32)]
 
 
 _lib = None
@@ -109,7 +110,7 @@ class _Packed:
         self.params = _Params(WEIGHT_KINDS[settings.weight_kind], 0, settings.sigma, settings.beta,
                               settings.w_bg, (C.c_double * 3)(*settings.bg), settings.tau,
                               settings.dilation, settings.near, settings.opacity_offset,
-                              getattr(settings, "alpha_cut", 0.0))
+                              getattr(settings, "alpha_cut", 0.0), int(bool(getattr(settings, "oit", False))), 0)
 
 
 def num_threads() -> int:

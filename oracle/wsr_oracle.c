@@ -68,6 +68,8 @@ typedef struct {
     double w_bg, bg[3];
     double tau, dilation, near_z, opacity_offset;
     double alpha_cut;        /* opacity early-out (App. D): 0 = off */
+    int32_t oit;             /* 1: weighted-blended OIT (Eq. 2) instead of Eq. 7 */
+    int32_t pad2_;
 } ora_params;
 
 /* Per-Gaussian projected quantities exported for stage-wise checks.  Layout of
@@ -457,6 +459,8 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
     double *num = (double *)calloc(w * h * 3, sizeof(double));
     double *den = (double *)calloc(w * h, sizeof(double));
     double *aden = (double *)calloc(w * h, sizeof(double));
+    double *cov = (double *)malloc(sizeof(double) * w * h);  /* OIT: prod (1 - alpha) */
+    for (int64_t o = 0; o < w * h; ++o) cov[o] = 1.0;
     int64_t *cnt = (int64_t *)calloc(w * h, sizeof(int64_t));
     const double tau = P->tau;
 
@@ -464,22 +468,25 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
         #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t yy = 0; yy < h; ++yy)
             for (int64_t xx = 0; xx < w; ++xx) {
-                double nr = 0, ng = 0, nb = 0, dd = 0, ad = 0;
+                double nr = 0, ng = 0, nb = 0, dd = 0, ad = 0, pc = 1.0;
                 int64_t c = 0;
                 for (int64_t j = 0; j < v.m; ++j) {
                     const proj_t *g = &v.g[j];
                     const double q = pair_q(g, x0 + xx, y0 + yy);
                     if (q <= g->cut) {
-                        const double a = g->u * g->w * exp(-0.5 * q);
+                        const double G = exp(-0.5 * q);
+                        const double a = g->u * g->w * G;
                         nr += a * g->rgb[0];
                         ng += a * g->rgb[1];
                         nb += a * g->rgb[2];
                         dd += a;
                         ad += fabs(a);
+                        pc *= 1.0 - clampd(g->u * G, 0.0, 1.0);
                         ++c;
                     }
                 }
                 const int64_t o = yy * w + xx;
+                cov[o] = pc;
                 num[3 * o] = nr; num[3 * o + 1] = ng; num[3 * o + 2] = nb;
                 den[o] = dd;
                 aden[o] = ad;
@@ -498,8 +505,10 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                 for (int64_t px = lo; px <= hi; ++px) {
                     const double q = pair_q(g, px, py);
                     if (q <= g->cut) {
-                        const double a = g->u * g->w * exp(-0.5 * q);
+                        const double G = exp(-0.5 * q);
+                        const double a = g->u * g->w * G;
                         const int64_t o = yy * w + (px - x0);
+                        cov[o] *= 1.0 - clampd(g->u * G, 0.0, 1.0);
                         num[3 * o] += a * g->rgb[0];
                         num[3 * o + 1] += a * g->rgb[1];
                         num[3 * o + 2] += a * g->rgb[2];
@@ -515,6 +524,21 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
     /* background term and normalisation */
     double *Cimg = (double *)malloc(sizeof(double) * w * h * 3);
     for (int64_t o = 0; o < w * h; ++o) {
+        if (P->oit) {
+            /* Eq. 2 with c_0 = c_B: coverage-weighted blend of the weighted
+             * average over the background (no w_B term) */
+            const double D = den[o];
+            for (int c = 0; c < 3; ++c) {
+                const double avg = (D != 0.0) ? num[3 * o + c] / D : 0.0;
+                Cimg[3 * o + c] = cov[o] * P->bg[c] + (1.0 - cov[o]) * avg;
+                if (out_num) out_num[3 * o + c] = num[3 * o + c];
+                if (out_C) out_C[3 * o + c] = Cimg[3 * o + c];
+            }
+            if (out_den) out_den[o] = D;
+            if (out_absden) out_absden[o] = aden[o];
+            if (out_cnt) out_cnt[o] = cnt[o];
+            continue;
+        }
         const double D = P->w_bg + den[o];
         double N3[3];
         for (int c = 0; c < 3; ++c) N3[c] = P->bg[c] * P->w_bg + num[3 * o + c];
@@ -562,6 +586,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
     free(num);
     free(den);
     free(aden);
+    free(cov);
     free(cnt);
     free_visible(&v);
 }
@@ -606,6 +631,9 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
      * gradient: gbar_c = g_c / den and s = sum_c gbar_c C_c */
     double *gbar = (double *)calloc(w * h * 3, sizeof(double));
     double *sfac = (double *)calloc(w * h, sizeof(double));
+    /* OIT (Eq. 2): k = P sum_c g_c (c_B,c - avg_c), so that the coverage term
+     * gives dL/dalpha_i = -k / (1 - alpha_i) */
+    double *kfac = (double *)calloc(w * h, sizeof(double));
     double bgw[4] = {0, 0, 0, 0}; /* dL/dbg_rgb, dL/dw_bg */
     #pragma omp parallel
     {
@@ -613,20 +641,36 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
         #pragma omp for schedule(dynamic, 1)
         for (int64_t yy = 0; yy < h; ++yy)
             for (int64_t xx = 0; xx < w; ++xx) {
-                double N3[3] = {P->bg[0] * P->w_bg, P->bg[1] * P->w_bg, P->bg[2] * P->w_bg};
-                double D = P->w_bg;
+                const double wb = P->oit ? 0.0 : P->w_bg;
+                double N3[3] = {P->bg[0] * wb, P->bg[1] * wb, P->bg[2] * wb};
+                double D = wb, pc = 1.0;
                 for (int64_t j = 0; j < v.m; ++j) {
                     const proj_t *g = &v.g[j];
                     const double q = pair_q(g, x0 + xx, y0 + yy);
                     if (q <= g->cut) {
-                        const double a = g->u * g->w * exp(-0.5 * q);
+                        const double G = exp(-0.5 * q);
+                        const double a = g->u * g->w * G;
                         for (int c = 0; c < 3; ++c) N3[c] += a * g->rgb[c];
                         D += a;
+                        pc *= 1.0 - clampd(g->u * G, 0.0, 1.0);
                     }
                 }
                 const int64_t o = yy * w + xx;
                 const double *gc = dL_dC + 3 * o;
-                if (D != 0.0) {
+                if (P->oit) {
+                    /* C = P c_B + (1 - P) N / D: dC/dN = (1 - P) / D,
+                     * dC/dD = -(1 - P) N / D^2, dC/dP = c_B - N / D */
+                    double avg[3], s = 0.0, kk = 0.0;
+                    for (int c = 0; c < 3; ++c) avg[c] = (D != 0.0) ? N3[c] / D : 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        gbar[3 * o + c] = (D != 0.0) ? gc[c] * (1.0 - pc) / D : 0.0;
+                        s += gbar[3 * o + c] * avg[c];
+                        kk += gc[c] * (P->bg[c] - avg[c]);
+                        loc[c] += gc[c] * pc;
+                    }
+                    sfac[o] = s;
+                    kfac[o] = pc * kk;
+                } else if (D != 0.0) {
                     double s = 0.0;
                     for (int c = 0; c < 3; ++c) {
                         gbar[3 * o + c] = gc[c] / D;
@@ -661,7 +705,7 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
         const proj_t *g = &v.g[j];
         const int64_t i = v.idx[j];
         const int64_t *b = v.box + 4 * j;
-        double dmu[2] = {0, 0}, dcon[3] = {0, 0, 0}, drgb[3] = {0, 0, 0}, das = 0.0;
+        double dmu[2] = {0, 0}, dcon[3] = {0, 0, 0}, drgb[3] = {0, 0, 0}, das = 0.0, du_cov = 0.0;
         const double as = g->u * g->w;
         const int64_t ylo = b[2] > y0 ? b[2] : y0, yhi = b[3] < y1 - 1 ? b[3] : y1 - 1;
         const int64_t xlo = b[0] > x0 ? b[0] : x0, xhi = b[1] < x1 - 1 ? b[1] : x1 - 1;
@@ -676,7 +720,16 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
                 const double dLda = gb[0] * g->rgb[0] + gb[1] * g->rgb[1] + gb[2] * g->rgb[2] - sfac[o];
                 for (int c = 0; c < 3; ++c) drgb[c] += a * gb[c];
                 das += dLda * G;
-                const double dq = -0.5 * a * dLda;
+                double dq = -0.5 * a * dLda;
+                if (P->oit) {
+                    /* alpha = u G, clamped to [0, 1] (no gradient where clamped) */
+                    const double al = g->u * G;
+                    if (al > 0.0 && al < 1.0) {
+                        const double dLdal = -kfac[o] / (1.0 - al);
+                        du_cov += G * dLdal;
+                        dq += -0.5 * g->u * G * dLdal;
+                    }
+                }
                 const double dx = (double)px + 0.5 - g->mu[0];
                 const double dy = (double)py + 0.5 - g->mu[1];
                 dmu[0] += -dq * (2.0 * g->conic[0] * dx + 2.0 * g->conic[1] * dy);
@@ -694,7 +747,7 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
         }
 
         /* ---- amplitude a_scale = u * w ---- */
-        const double du = das * g->w;
+        const double du = das * g->w + du_cov;
         const double dw = das * g->u;
         double ddir[3] = {0, 0, 0};
         double dY[ORA_MAX_K][3];
@@ -865,6 +918,7 @@ void ora_render_bwd(const ora_scene *S, const ora_camera *cam, const ora_params 
     free(gbeta);
     free(gbar);
     free(sfac);
+    free(kfac);
     free_visible(&v);
 }
 

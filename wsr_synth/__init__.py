@@ -82,6 +82,7 @@ class Settings:
     opacity_offset: float = 0.5
     tile: int = 16
     alpha_cut: float = 0.0            # opacity early-out threshold (0: off)
+    oit: bool = False                 # weighted-blended OIT (Eq. 2) instead of Eq. 7
 
     def copy(self, **kw) -> "Settings":
         d = dict(self.__dict__)
