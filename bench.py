@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU baseline sample")
     ap.add_argument("--graph", action="store_true", help="time replays of the whole step captured as one HIP graph")
+    ap.add_argument("--oit", action="store_true", help="weighted-blended OIT (Eq. 2) instead of Eq. 7")
     ap.add_argument("--alpha-cut", type=float, default=0.0,
                     help="opacity early-out threshold (0: off); the line then also reports the image error "
                          "against the exact renderer")
@@ -307,7 +308,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     scene, cams, st = ws.make_scene(args.config)
-    st = st.copy(tile=args.tile, alpha_cut=args.alpha_cut)
+    st = st.copy(tile=args.tile, alpha_cut=args.alpha_cut, oit=args.oit)
     n = scene["means"].shape[1]
     dev = scene_to_device(scene, storage=args.storage)
     g = globals_tensor(st)
@@ -411,6 +412,7 @@ def main():
                        f"{ctx.nv} views of uneven size, {P:,} px in total") +
                        f", tile {args.tile}, {args.storage} attribute storage" +
                        (f", opacity early-out at {args.alpha_cut:g}" if args.alpha_cut > 0 else "") +
+                       (", weighted-blended OIT (Eq. 2)" if args.oit else "") +
                        (", whole step replayed as one HIP graph" if args.graph else ""),
                    "gaussians": n, "views": ctx.nv, "pixels": P, "tile": args.tile, "storage": args.storage,
                    "graph": bool(args.graph)},

@@ -121,6 +121,16 @@ typedef struct {
  * shards Gaussians across devices. */
 #define WSR_FLAG_UNNORMALISED 1
 
+/* Weighted-blended order-independent transparency (Eq. 2, the operator the
+ * method starts from) instead of Eq. 7, forward and backward:
+ *     C = P c_B + (1 - P) (sum_i c_i a_i) / (sum_i a_i),  P = prod_i (1 - alpha_i),
+ * with a_i = u_i w(d_i) exp(-q/2) as in Eq. 7 and alpha_i = u_i exp(-q/2)
+ * clamped to [0, 1]; w_B is not used (its gradient is 0) and the weighted
+ * average is 0 where its denominator vanishes.  wsr_render_fwd's out_den then
+ * receives sum_i a_i.  Not combinable with WSR_FLAG_UNNORMALISED or
+ * alpha_cut > 0, nor with the sorted-blending entry points. */
+#define WSR_FLAG_OIT 2
+
 /* Learnable global parameters, a DEVICE array of 6 floats:
  * [0] sigma, [1] beta (EXP only), [2] w_B, [3..5] c_B (RGB). */
 #define WSR_GLOBALS 6

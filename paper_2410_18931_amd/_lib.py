@@ -44,6 +44,7 @@ class WsrParams(C.Structure):
 
 
 FLAG_UNNORMALISED = 1
+FLAG_OIT = 2
 WSR_ERR_TILE_LIST = 5
 SORT_MAX = 8192
 
@@ -137,6 +138,8 @@ def make_cameras(cams) -> "C.Array":
 
 
 def make_params(settings, flags: int = 0) -> WsrParams:
+    if getattr(settings, "oit", False):
+        flags |= FLAG_OIT
     return WsrParams(WEIGHT_KINDS[settings.weight_kind], int(settings.tile), float(settings.tau),
                      float(settings.dilation), float(settings.near), float(settings.opacity_offset), int(flags),
                      float(getattr(settings, "alpha_cut", 0.0)))

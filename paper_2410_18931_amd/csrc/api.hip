@@ -77,6 +77,10 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   L->off_items = off;    off = align256(off + sizeof(uint32_t) * (tiles + 1));
   L->off_acc = off;      off = align256(off + sizeof(float) * 4 * pixels);
   L->off_pd = off;       off = align256(off + sizeof(float) * 4 * tiles * tile * tile);
+  L->off_oit = off;      off = align256(off + sizeof(float) * 4 * pixels);
+  L->off_acclog = off;   off = align256(off + sizeof(float) * pixels);
+  L->off_du2d = off;     off = align256(off + sizeof(float) * (slots > 0 ? slots : 1));
+  L->off_pdk = off;      off = align256(off + sizeof(float) * tiles * tile * tile);
   L->bytes = off;
   return true;
 }
@@ -102,7 +106,8 @@ bool params_ok(const wsr_params* p) {
   return p && p->weight_kind >= WSR_WEIGHT_DIR && p->weight_kind <= WSR_WEIGHT_LC &&
          (p->tile == 8 || p->tile == 16 || p->tile == 32) && std::isfinite(p->tau) && p->tau >= 0.f &&
          std::isfinite(p->dilation) && std::isfinite(p->near_z) && std::isfinite(p->alpha_cut) &&
-         p->alpha_cut >= 0.f;
+         p->alpha_cut >= 0.f && (p->flags & ~(WSR_FLAG_UNNORMALISED | WSR_FLAG_OIT)) == 0 &&
+         (!(p->flags & WSR_FLAG_OIT) || ((p->flags & WSR_FLAG_UNNORMALISED) == 0 && p->alpha_cut == 0.f));
 }
 
 }  // namespace
@@ -155,7 +160,8 @@ int32_t wsr_bin(const wsr_camera* cams, int32_t n_views, const wsr_params* param
   Layout L;
   if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
   if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
-  return to_status(launch_bin(L, ws, pairs, capacity, static_cast<hipStream_t>(stream)));
+  return to_status(launch_bin(L, ws, pairs, capacity, (params->flags & WSR_FLAG_OIT) != 0,
+                              static_cast<hipStream_t>(stream)));
 }
 
 int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
@@ -247,7 +253,9 @@ int32_t wsr_check(const void* ws, int64_t ws_bytes, void* stream) {
 int32_t wsr_sort_tiles(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
                        void* ws, int64_t ws_bytes, void* pairs, int64_t capacity, void* stream) {
   static_assert(kSortMax == WSR_SORT_MAX, "sort limit");
-  if (!params_ok(params) || params->alpha_cut != 0.f || !ws || !pairs_ok(pairs, capacity)) return WSR_ERR_INVALID;
+  if (!params_ok(params) || params->alpha_cut != 0.f || (params->flags & WSR_FLAG_OIT) || !ws ||
+      !pairs_ok(pairs, capacity))
+    return WSR_ERR_INVALID;
   Layout L;
   if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
   if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
@@ -258,7 +266,8 @@ int32_t wsr_sort_tiles(const wsr_camera* cams, int32_t n_views, const wsr_params
 int32_t wsr_render_sorted(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
                           const float* globals, const wsr_blend* blend, void* ws, int64_t ws_bytes,
                           const void* pairs, int64_t capacity, float* out_rgb, float* out_T, void* stream) {
-  if (!params_ok(params) || params->weight_kind != WSR_WEIGHT_DIR || params->alpha_cut != 0.f || !globals ||
+  if (!params_ok(params) || params->weight_kind != WSR_WEIGHT_DIR || params->alpha_cut != 0.f ||
+      (params->flags & WSR_FLAG_OIT) || !globals ||
       !blend || !ws || !out_rgb ||
       !out_T || !pairs_ok(pairs, capacity))
     return WSR_ERR_INVALID;

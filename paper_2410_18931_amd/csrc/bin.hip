@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void make_items(const uint32_t* tile_start, in
 
 }  // namespace
 
-hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, hipStream_t st) {
+hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, bool oit, hipStream_t st) {
   DevFlags* flags = at<DevFlags>(ws, L.off_flags);
   uint32_t* hist = at<uint32_t>(ws, L.off_hist);
   uint32_t* parts = at<uint32_t>(ws, L.off_scan);
@@ -323,9 +323,11 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
   const size_t lds = static_cast<size_t>(a.rows_per_chunk) * L.max_tiles_x * sizeof(uint32_t);
   const dim3 grid(static_cast<unsigned>(L.nblk), static_cast<unsigned>(nchunks), static_cast<unsigned>(L.nv));
 
-  // split-tile accumulator of the forward raster starts at zero
+  // split-tile accumulators of the forward raster start at zero
   hipError_t e = launch_fill_zero(at<float>(ws, L.off_acc), sizeof(float) * 4 * L.total_pixels, st);
   if (e != hipSuccess) return e;
+  if (oit && (e = launch_fill_zero(at<float>(ws, L.off_acclog), sizeof(float) * L.total_pixels, st)) != hipSuccess)
+    return e;
   bin_pass<false><<<grid, kBinThreads, lds, st>>>(a);
   const int64_t tl = L.total_tiles + 1;
   column_scan<<<static_cast<unsigned>((tl + 255) / 256), 256, 0, st>>>(a.cams, L.nv, L.nblk, L.total_tiles, hist,

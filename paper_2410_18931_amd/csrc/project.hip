@@ -36,6 +36,7 @@ struct ProjArgs {
   int32_t weight_kind;
   int32_t tile;
   float tau, dilation, near_z, opacity_offset, alpha_cut;
+  int32_t oit;
 };
 
 // float -> fp16 bits, rounded towards +inf (the support extents must never
@@ -144,8 +145,9 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
       DevSplat ds;
       ds.s = r;
       // first pair slot filled in by binning; the camera depth orders the
-      // splats for the sorted-blending baseline
-      ds.slot = make_uint4(0u, rect.x, rect.y, __float_as_uint(static_cast<float>(g.tz)));
+      // splats for the sorted-blending baseline, the opacity enters Eq. 2's
+      // coverage term in OIT mode
+      ds.slot = make_uint4(0u, rect.x, rect.y, __float_as_uint(a.oit ? u : static_cast<float>(g.tz)));
       a.rec[slot] = ds;
     }
     a.rect[slot] = rect;
@@ -224,6 +226,7 @@ hipError_t launch_project(const wsr_scene* sc, const wsr_params* P, const float*
   a.tile = P->tile;
   a.tau = P->tau;
   a.alpha_cut = P->alpha_cut;
+  a.oit = (P->flags & WSR_FLAG_OIT) ? 1 : 0;
   a.dilation = P->dilation;
   a.near_z = P->near_z;
   a.opacity_offset = P->opacity_offset;

@@ -28,6 +28,7 @@ struct BwdArgs {
   const float* globals;
   const DevCamera* cams;
   const float* grad2d;       // per-(view, Gaussian) 2D gradients [nv][n][9]
+  const float* du2d;         // OIT: per-(view, Gaussian) dL/du of Eq. 2's coverage term, else null
   wsr_grads g;
   double* gpart;      // [blocks][2] = sigma, beta
   int64_t n;
@@ -72,7 +73,8 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
       float gv[9];
 #pragma unroll
       for (int j = 0; j < 9; ++j) gv[j] = g2[j];
-      bool nz = false;
+      const float du_cov = a.du2d ? a.du2d[static_cast<int64_t>(v) * n + i] : 0.f;
+      bool nz = du_cov != 0.f;
 #pragma unroll
       for (int j = 0; j < 9; ++j) nz |= gv[j] != 0.f;
       if (!nz) continue;
@@ -108,7 +110,8 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
         dw_dd = lin > 0.0 ? -lcv / sigma : 0.0;
       }
       const double gamp = gv[8];
-      const double du = gamp * w, dw = gamp * u;
+      // u enters the amplitude u w and, in OIT mode, the coverage term
+      const double du = gamp * w + du_cov, dw = gamp * u;
       if (a.weight_kind == WSR_WEIGHT_EXP) {
         const double db = pow(d, beta);
         gsig += dw * (-db * w);
@@ -337,6 +340,20 @@ __global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, c
   }
 }
 
+// OIT: each (view, Gaussian)'s dL/du through the coverage term, summed over
+// its contiguous range of pair slots.
+__global__ __launch_bounds__(256) void sum_pair_du(const uint32_t* goff, const float* du, uint32_t capacity,
+                                                   int64_t slots, float* du2d) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (k >= slots) return;
+  uint32_t s0 = goff[k], s1 = goff[k + 1];
+  s0 = s0 < capacity ? s0 : capacity;
+  s1 = s1 < capacity ? s1 : capacity;
+  float t = 0.f;
+  for (uint32_t j = s0; j < s1; ++j) t += du[j];
+  du2d[k] = t;
+}
+
 // Final reduction of the global parameters: dL/dsigma, dL/dbeta from the
 // per-block partials, dL/dw_B and dL/dc_B from the per-tile partials.
 __global__ __launch_bounds__(1024) void reduce_globals(const double* gpart, int64_t nblocks,
@@ -411,6 +428,12 @@ hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const fl
         at<uint32_t>(ws, L.off_goff), pv.part, static_cast<uint32_t>(capacity), slots, at<float>(ws, L.off_grad2d),
         out_grad2d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
+    if (oit) {
+      sum_pair_du<<<static_cast<unsigned>((slots + 255) / 256), 256, 0, st>>>(
+          at<uint32_t>(ws, L.off_goff), pv.du, static_cast<uint32_t>(capacity), slots, at<float>(ws, L.off_du2d));
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     BwdArgs a;
     a.means = sc->means;
     a.log_scales = sc->log_scales;
@@ -421,6 +444,7 @@ hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const fl
     a.globals = globals;
     a.cams = at<DevCamera>(ws, L.off_cams);
     a.grad2d = at<float>(ws, L.off_grad2d);
+    a.du2d = oit ? at<float>(ws, L.off_du2d) : nullptr;
     a.g = *g;
     a.gpart = gpart;
     a.n = L.n;

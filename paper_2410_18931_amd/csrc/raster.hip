@@ -139,6 +139,13 @@ struct RasterArgs {
   const uint32_t* items;
   int64_t total_tiles;
   float* acc;
+  // OIT (Eq. 2): per pixel (weighted average, coverage P) from the forward,
+  // the split-tile accumulator of ln P, the prepass's per-pixel coverage
+  // factor and the per-pair partial dL/du
+  float4* oit;
+  float* acclog;
+  float* pdk;
+  float* du;
 };
 
 __device__ __forceinline__ int find_view(const DevCamera* cams, int nv, int tile) {
@@ -207,10 +214,10 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
 // first slot plus this tile's row-major index in its tile rectangle, the
 // order in which binning enumerated its pairs -- and, per staged record, its
 // position in this wave's list (0xffff if culled).
-template <int T, int BATCH, bool SLOTS, bool CUT>
+template <int T, int BATCH, bool SLOTS, bool CUT, bool OIT = false>
 __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
                                               SplatRec* s_rec, uint32_t* s_slot, uint8_t* s_list,
-                                              uint16_t* s_pos) {
+                                              uint16_t* s_pos, float* s_u = nullptr) {
   using G = TileGeom<T>;
   __syncthreads();  // previous batch fully consumed
   for (int q = threadIdx.x; q < BATCH; q += G::kThreads) {
@@ -218,6 +225,7 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
     if (j < c.end) {
       const DevSplat* d = a.rec + static_cast<int64_t>(c.v) * c.n + a.ids[j];
       s_rec[q] = d->s;
+      if (OIT) s_u[q] = __uint_as_float(d->slot.w);  // the opacity u
       if (SLOTS) {
         const uint4 sl = d->slot;
         const uint32_t rx0 = sl.y & 0xffffu, rw = (sl.y >> 16) - rx0, ry0 = sl.z & 0xffffu;
@@ -271,69 +279,93 @@ __device__ __forceinline__ void write_pixel(const RasterArgs& a, int64_t pix, fl
   a.out_den[pix] = D;
 }
 
-template <int T, bool COUNT, bool CUT>
+// Eq. 2 for one pixel: C = P c_B + (1 - P) N / D (the average is 0 where
+// D = 0); D goes to out_den and (N / D, P) to the workspace for the backward.
+__device__ __forceinline__ void write_pixel_oit(const RasterArgs& a, int64_t pix, float nr, float ng, float nb,
+                                                float dd, float P) {
+  const float inv = dd != 0.f ? 1.f / dd : 0.f;
+  const float ar = nr * inv, ag = ng * inv, ab = nb * inv;
+  const float Q = 1.f - P;
+  a.out_rgb[3 * pix] = fmaf(P, a.globals[3], Q * ar);
+  a.out_rgb[3 * pix + 1] = fmaf(P, a.globals[4], Q * ag);
+  a.out_rgb[3 * pix + 2] = fmaf(P, a.globals[5], Q * ab);
+  a.out_den[pix] = dd;
+  a.oit[pix] = make_float4(ar, ag, ab, P);
+}
+
+template <int T, bool COUNT, bool CUT, bool OIT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
   __shared__ SplatRec s_rec[G::kBatch];
   __shared__ __align__(16) uint8_t s_list[G::kWaves * G::kBatch];
+  __shared__ float s_u[OIT ? G::kBatch : 1];
   TileCtx<T> c;
   const DevCamera* cam;
   if (!tile_setup<T>(a, c, cam)) return;
 
   float nr = 0.f, ng = 0.f, nb = 0.f, dd = 0.f;
+  float cov = 1.f;  // OIT: prod (1 - alpha)
   int cntp = 0;
   const float pcx = static_cast<float>(c.px) + 0.5f;
   const float pcy = static_cast<float>(c.py) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T, G::kBatch, false, CUT>(a, c, b, s_rec, nullptr, s_list, nullptr);
+    const int m = stage_and_cull<T, G::kBatch, false, CUT, OIT>(a, c, b, s_rec, nullptr, s_list, nullptr, s_u);
     const uint8_t* list = s_list + c.wave * G::kBatch;
     // four splats per step: one 4-byte read fetches their list entries and
     // all four records are requested before any arithmetic, so LDS latency
     // is paid once per four splats
-    auto accumulate = [&](const SplatRec& r) {
+    auto accumulate = [&](const SplatRec& r, int k) {
       float dx, dy;
       const float q = pair_q(r, pcx, pcy, &dx, &dy);
       const float cut = CUT ? r.r2.w : tau;
-      const float al = q <= cut ? r.r1.w * falloff(q) : 0.f;
+      const float G = q <= cut ? falloff(q) : 0.f;
+      const float al = r.r1.w * G;
       nr = fmaf(al, r.r2.x, nr);
       ng = fmaf(al, r.r2.y, ng);
       nb = fmaf(al, r.r2.z, nb);
       dd += al;
+      if (OIT) cov *= 1.f - __builtin_amdgcn_fmed3f(s_u[k] * G, 0.f, 1.f);
       if (COUNT) cntp += q <= cut ? 1 : 0;
     };
     int i = 0;
     for (; i + 4 <= m; i += 4) {
       const uint32_t k4 = *reinterpret_cast<const uint32_t*>(list + i);
-      const SplatRec r0 = s_rec[k4 & 0xffu];
-      const SplatRec r1 = s_rec[(k4 >> 8) & 0xffu];
-      const SplatRec r2 = s_rec[(k4 >> 16) & 0xffu];
-      const SplatRec r3 = s_rec[k4 >> 24];
-      accumulate(r0);
-      accumulate(r1);
-      accumulate(r2);
-      accumulate(r3);
+      const int k0 = k4 & 0xffu, k1 = (k4 >> 8) & 0xffu, k2 = (k4 >> 16) & 0xffu, k3 = k4 >> 24;
+      const SplatRec r0 = s_rec[k0];
+      const SplatRec r1 = s_rec[k1];
+      const SplatRec r2 = s_rec[k2];
+      const SplatRec r3 = s_rec[k3];
+      accumulate(r0, k0);
+      accumulate(r1, k1);
+      accumulate(r2, k2);
+      accumulate(r3, k3);
     }
-    for (; i < m; ++i) accumulate(s_rec[list[i]]);
+    for (; i < m; ++i) accumulate(s_rec[list[i]], list[i]);
   }
   if (c.px >= cam->width || c.py >= cam->height) return;
   const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
   if (COUNT) atomicAdd(a.out_count + pix, cntp);
   if (c.nk > 1) {
-    // split tile: partial sums, normalised by raster_fwd_finalize
+    // split tile: partial sums, normalised by raster_fwd_finalize (the
+    // coverage products of the parts multiply, so their logarithms add)
     float* ac = a.acc + 4 * pix;
     unsafeAtomicAdd(ac, nr);
     unsafeAtomicAdd(ac + 1, ng);
     unsafeAtomicAdd(ac + 2, nb);
     unsafeAtomicAdd(ac + 3, dd);
+    if (OIT) unsafeAtomicAdd(a.acclog + pix, __logf(cov));
     return;
   }
-  write_pixel(a, pix, nr, ng, nb, dd);
+  if (OIT)
+    write_pixel_oit(a, pix, nr, ng, nb, dd, cov);
+  else
+    write_pixel(a, pix, nr, ng, nb, dd);
 }
 
 // Normalisation of the tiles whose list was split over several work items:
 // their partial sums were accumulated in `acc`, which is cleared again here.
-template <int T>
+template <int T, bool OIT>
 __global__ __launch_bounds__(256) void raster_fwd_finalize(RasterArgs a) {
   const int64_t t = blockIdx.x;
   if (a.items[t + 1] - a.items[t] <= 1) return;
@@ -349,7 +381,13 @@ __global__ __launch_bounds__(256) void raster_fwd_finalize(RasterArgs a) {
     float4* ac = reinterpret_cast<float4*>(a.acc) + pix;
     const float4 s = *ac;
     *ac = make_float4(0.f, 0.f, 0.f, 0.f);
-    write_pixel(a, pix, s.x, s.y, s.z, s.w);
+    if (OIT) {
+      const float lg = a.acclog[pix];
+      a.acclog[pix] = 0.f;
+      write_pixel_oit(a, pix, s.x, s.y, s.z, s.w, __expf(lg));
+    } else {
+      write_pixel(a, pix, s.x, s.y, s.z, s.w);
+    }
   }
 }
 
@@ -431,12 +469,82 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
   out[8][l] = g_amp;
 }
 
+// The OIT chunk (Eq. 2): as bwd_chunk, plus the coverage term.  A layer's
+// opacity alpha = u G (clamped to [0, 1], no gradient where clamped) gets
+// dL/dalpha = -k / (1 - alpha) with k from the prepass, so per pixel
+// dq = -G (amp dL/da + u dL/dalpha) / 2, and the tenth output is
+// dL/du = sum G dL/dalpha.  The moments therefore carry the amplitude.
+template <int T>
+__device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
+                                              const SplatRec* s_rec, const float* s_u,
+                                              const float4* __restrict__ pd_wave, const float* __restrict__ pk_wave,
+                                              float (*out)[kWave], float tau) {
+  const int j = c0 + c.lane;
+  const bool valid = j < m;
+  const int kr = valid ? list[j] : 0;
+  const SplatRec r = s_rec[kr];
+  const float u = s_u[kr];
+  const float amp = r.r1.w, cr = r.r2.x, cg = r.r2.y, cb = r.r2.z;
+  float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+  float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f, g_u = 0.f;
+  const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
+  const float ex0 = (static_cast<float>(c.bx0) + 0.5f) - r.r1.y;
+  const float ey0 = (static_cast<float>(c.by0) + 0.5f) - r.r1.z;
+#pragma unroll 1
+  for (int row = 0; row < 8; ++row) {
+    const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
+    const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
+    float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+#pragma unroll
+    for (int col = 0; col < 8; ++col) {
+      const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
+      const float q = quad_form(A, B2dy, Cdy2, dx);
+      const float4 pd = pd_wave[row * 8 + col];  // wave-uniform: SGPRs
+      const float k = pk_wave[row * 8 + col];
+      const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
+      const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
+      const float al = u * Gq;
+      const float dLdal = (al > 0.f && al < 1.f) ? -k / (1.f - al) : 0.f;
+      const float e = Gq * fmaf(amp, dLda, u * dLdal);
+      S0 += e;
+      S1 = fmaf(e, dx, S1);
+      S2 = fmaf(e, dx * dx, S2);
+      g_r = fmaf(Gq, pd.x, g_r);
+      g_g = fmaf(Gq, pd.y, g_g);
+      g_b = fmaf(Gq, pd.z, g_b);
+      g_amp = fmaf(Gq, dLda, g_amp);
+      g_u = fmaf(Gq, dLdal, g_u);
+    }
+    Mx += S1;
+    My = fmaf(dy, S0, My);
+    Mxx += S2;
+    Mxy = fmaf(dy, S1, Mxy);
+    Myy = fmaf(dy * dy, S0, Myy);
+  }
+  const int l = c.lane;
+  out[0][l] = A * Mx + 0.5f * B2 * My;
+  out[1][l] = 0.5f * B2 * Mx + Cc * My;
+  out[2][l] = -0.5f * Mxx;
+  out[3][l] = -Mxy;
+  out[4][l] = -0.5f * Myy;
+  out[5][l] = amp * g_r;
+  out[6][l] = amp * g_g;
+  out[7][l] = amp * g_b;
+  out[8][l] = g_amp;
+  out[9][l] = g_u;
+}
+
 // Backward prepass, one workgroup per tile: the per-pixel factors
 // gbar = dL/dC / D and s = gbar . C (zero outside the image), stored padded to
 // whole tiles in the order the raster backward walks them
 // ([tile][wave block][row * 8 + col], i.e. thread order), and the tile's
 // partial sums of the background gradients dL/dc_B and dL/dw_B.
-template <int T>
+//
+// OIT (Eq. 2, C = P c_B + (1 - P) N / D): gbar = dL/dC (1 - P) / D and
+// s = gbar . (N / D), so that dL/da = gbar . c - s as for Eq. 7, and the
+// coverage factor k = P dL/dC . (c_B - N / D), so that a layer's opacity
+// alpha gets dL/dalpha = -k / (1 - alpha); dL/dc_B = P dL/dC, dL/dw_B = 0.
+template <int T, bool OIT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterArgs a, float4* pdg) {
   using G = TileGeom<T>;
   __shared__ float s_bg[G::kWaves][4];
@@ -451,11 +559,24 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterA
   const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
   float bacc[4] = {0.f, 0.f, 0.f, 0.f};  // dL/dc_B (rgb), dL/dw_B
   float4 pd = make_float4(0.f, 0.f, 0.f, 0.f);
+  float kcov = 0.f;
   if (px < cam.width && py < cam.height) {
     const int64_t pix = cam.pix_base + static_cast<int64_t>(py) * cam.width + px;
     const float D = a.den[pix];
     const float g0 = a.dL_drgb[3 * pix], g1 = a.dL_drgb[3 * pix + 1], g2 = a.dL_drgb[3 * pix + 2];
-    if (D != 0.f) {
+    if (OIT) {
+      const float4 o = a.oit[pix];  // (N / D, P)
+      const float P = o.w;
+      const float f = D != 0.f ? (1.f - P) / D : 0.f;
+      pd.x = g0 * f;
+      pd.y = g1 * f;
+      pd.z = g2 * f;
+      pd.w = pd.x * o.x + pd.y * o.y + pd.z * o.z;
+      kcov = P * (g0 * (bgr - o.x) + g1 * (bgg - o.y) + g2 * (bgb - o.z));
+      bacc[0] = g0 * P;
+      bacc[1] = g1 * P;
+      bacc[2] = g2 * P;
+    } else if (D != 0.f) {
       const float iD = 1.f / D;
       pd.x = g0 * iD;
       pd.y = g1 * iD;
@@ -473,6 +594,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterA
     }
   }
   pdg[static_cast<int64_t>(tile) * G::kThreads + threadIdx.x] = pd;
+  if (OIT) a.pdk[static_cast<int64_t>(tile) * G::kThreads + threadIdx.x] = kcov;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const float sj = wave_sum(bacc[j]);
@@ -497,18 +619,23 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterA
 // owner adds the entries of its record -- found through the per-wave list
 // positions recorded by the culling -- into registers, waves in a fixed
 // order.  At the end of the batch the owner stores the record's sums, zeros
-// included, with plain stores at the pair's Gaussian-major slot.  The
-// summation order is fixed, so the result does not vary from run to run.
-template <int T, bool CUT>
+// included, with plain stores at the pair's Gaussian-major slot.  For given
+// tile lists the summation order is fixed, so the result does not vary from
+// run to run (the order in which a record's per-wave sums are added follows
+// the rounds that reach them, i.e. the list positions).
+template <int T, bool CUT, bool OIT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(RasterArgs a,
-                                                                           const float4* __restrict__ pdg) {
+                                                                           const float4* __restrict__ pdg,
+                                                                           const float* __restrict__ pdk) {
   using G = TileGeom<T>;
   constexpr int kB = G::kBatch;
+  constexpr int NV = OIT ? 10 : 9;  // sums per (tile, splat) pair
   __shared__ SplatRec s_rec[kB];
   __shared__ uint32_t s_slot[kB];
   __shared__ __align__(16) uint8_t s_list[G::kWaves * kB];
   __shared__ uint16_t s_pos[G::kWaves * kB];
-  __shared__ float s_part[G::kWaves][9][kWave];
+  __shared__ float s_part[G::kWaves][NV][kWave];
+  __shared__ float s_u[OIT ? kB : 1];
   __shared__ int s_m[G::kWaves];
   TileCtx<T> c;
   const DevCamera* cam;
@@ -517,10 +644,11 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
   // this wave's 64 per-pixel factors (wave-uniform base address)
   const int wave_u = __builtin_amdgcn_readfirstlane(c.wave);
   const float4* __restrict__ pd_wave = pdg + (c.tile * G::kWaves + wave_u) * kWave;
+  const float* __restrict__ pk_wave = OIT ? pdk + (c.tile * G::kWaves + wave_u) * kWave : nullptr;
   const float tau = a.tau;
   const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
   for (uint32_t b = c.start; b < c.end; b += kB) {
-    const int m = stage_and_cull<T, kB, true, CUT>(a, c, b, s_rec, s_slot, s_list, s_pos);
+    const int m = stage_and_cull<T, kB, true, CUT, OIT>(a, c, b, s_rec, s_slot, s_list, s_pos, s_u);
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kB), c.end - b));
     if (c.lane == 0) s_m[c.wave] = m;
     __syncthreads();
@@ -528,11 +656,16 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
 #pragma unroll
     for (int w = 0; w < G::kWaves; ++w) rounds = max(rounds, (s_m[w] + kWave - 1) / kWave);
     const uint8_t* list = s_list + c.wave * kB;
-    float acc[9];
+    float acc[NV];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) acc[q] = 0.f;
+    for (int q = 0; q < NV; ++q) acc[q] = 0.f;
     for (int r = 0; r < rounds; ++r) {
-      if (r * kWave < m) bwd_chunk<T, CUT>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
+      if (r * kWave < m) {
+        if (OIT)
+          bwd_chunk_oit<T>(c, r * kWave, m, list, s_rec, s_u, pd_wave, pk_wave, s_part[c.wave], tau);
+        else
+          bwd_chunk<T, CUT>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
+      }
       __syncthreads();
       if (own < cnt) {
 #pragma unroll
@@ -540,7 +673,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
           const int p = s_pos[w * kB + own];  // 0xffff: culled by wave w
           if ((p >> 6) == r) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) acc[q] += s_part[w][q][p & (kWave - 1)];
+            for (int q = 0; q < NV; ++q) acc[q] += s_part[w][q][p & (kWave - 1)];
           }
         }
       }
@@ -553,6 +686,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
         dst[0] = make_float3(acc[0], acc[1], acc[2]);
         dst[1] = make_float3(acc[3], acc[4], acc[5]);
         dst[2] = make_float3(acc[6], acc[7], acc[8]);
+        if (OIT) a.du[sl] = acc[NV - 1];
       }
     }
   }
@@ -700,34 +834,51 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   a.items = at<uint32_t>(ws, L.off_items);
   a.total_tiles = L.total_tiles;
   a.acc = at<float>(ws, L.off_acc);
+  a.oit = at<float4>(ws, L.off_oit);
+  a.acclog = at<float>(ws, L.off_acclog);
+  a.pdk = at<float>(ws, L.off_pdk);
+  a.du = pv.du;
   return a;
 }
 
+template <int T, bool CUT, bool OIT>
+void fwd_k(const RasterArgs& a, const dim3& g, bool count, hipStream_t st) {
+  if (count)
+    raster_fwd_kernel<T, true, CUT, OIT><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
+  else
+    raster_fwd_kernel<T, false, CUT, OIT><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
+}
+
 template <int T>
-hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, bool count, bool cut, hipStream_t st) {
+hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, bool count, bool cut, bool oit, hipStream_t st) {
   const dim3 g(static_cast<unsigned>(grid));
-  if (cut) {
-    if (count)
-      raster_fwd_kernel<T, true, true><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
-    else
-      raster_fwd_kernel<T, false, true><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
-  } else {
-    if (count)
-      raster_fwd_kernel<T, true, false><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
-    else
-      raster_fwd_kernel<T, false, false><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
-  }
-  raster_fwd_finalize<T><<<dim3(static_cast<unsigned>(tiles)), 256, 0, st>>>(a);
+  if (oit)
+    fwd_k<T, false, true>(a, g, count, st);
+  else if (cut)
+    fwd_k<T, true, false>(a, g, count, st);
+  else
+    fwd_k<T, false, false>(a, g, count, st);
+  if (oit)
+    raster_fwd_finalize<T, true><<<dim3(static_cast<unsigned>(tiles)), 256, 0, st>>>(a);
+  else
+    raster_fwd_finalize<T, false><<<dim3(static_cast<unsigned>(tiles)), 256, 0, st>>>(a);
   return hipGetLastError();
 }
 
 template <int T>
-hipError_t bwd_t(const RasterArgs& a, float4* pd, int64_t grid, int64_t tiles, bool cut, hipStream_t st) {
-  raster_bwd_prep<T><<<dim3(static_cast<unsigned>(tiles)), TileGeom<T>::kThreads, 0, st>>>(a, pd);
-  if (cut)
-    raster_bwd_kernel<T, true><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a, pd);
-  else
-    raster_bwd_kernel<T, false><<<dim3(static_cast<unsigned>(grid)), TileGeom<T>::kThreads, 0, st>>>(a, pd);
+hipError_t bwd_t(const RasterArgs& a, float4* pd, int64_t grid, int64_t tiles, bool cut, bool oit, hipStream_t st) {
+  const dim3 gt(static_cast<unsigned>(tiles)), gi(static_cast<unsigned>(grid));
+  constexpr int kT = TileGeom<T>::kThreads;
+  if (oit) {
+    raster_bwd_prep<T, true><<<gt, kT, 0, st>>>(a, pd);
+    raster_bwd_kernel<T, false, true><<<gi, kT, 0, st>>>(a, pd, a.pdk);
+  } else {
+    raster_bwd_prep<T, false><<<gt, kT, 0, st>>>(a, pd);
+    if (cut)
+      raster_bwd_kernel<T, true, false><<<gi, kT, 0, st>>>(a, pd, a.pdk);
+    else
+      raster_bwd_kernel<T, false, false><<<gi, kT, 0, st>>>(a, pd, a.pdk);
+  }
   return hipGetLastError();
 }
 
@@ -747,10 +898,11 @@ hipError_t launch_raster_fwd(const Layout& L, void* ws, const void* pairs, int64
     if (e != hipSuccess) return e;
   }
   const int64_t grid = max_raster_items(L, capacity);
+  const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
   switch (L.tile) {
-    case 8: return fwd_t<8>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, st);
-    case 32: return fwd_t<32>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, st);
-    default: return fwd_t<16>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, st);
+    case 8: return fwd_t<8>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, oit, st);
+    case 32: return fwd_t<32>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, oit, st);
+    default: return fwd_t<16>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, oit, st);
   }
 }
 
@@ -765,10 +917,11 @@ hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t cap
   a.tilepart = at<float>(ws, L.off_tilepart);
   const int64_t grid = max_raster_items(L, capacity);
   float4* pd = at<float4>(ws, L.off_pd);
+  const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
   switch (L.tile) {
-    case 8: return bwd_t<8>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, st);
-    case 32: return bwd_t<32>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, st);
-    default: return bwd_t<16>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, st);
+    case 8: return bwd_t<8>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, oit, st);
+    case 32: return bwd_t<32>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, oit, st);
+    default: return bwd_t<16>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, oit, st);
   }
 }
 

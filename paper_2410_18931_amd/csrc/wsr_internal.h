@@ -45,7 +45,8 @@ struct __align__(16) SplatRec {
 //   pair slot (written by binning), its tile rectangle (x0 | x1 << 16,
 //   y0 | y1 << 16) and its camera depth t_z as float bits (the sort key of
 //   the sorted-blending baseline; positive, so the bits order like the
-//   values).
+//   values) -- in OIT mode the opacity u instead, which Eq. 2's coverage
+//   term needs beside the amplitude u w.
 struct __align__(64) DevSplat {
   SplatRec s;
   uint4 slot;
@@ -54,18 +55,22 @@ struct __align__(64) DevSplat {
 // The caller's pair buffer (capacity entries of kPairBytes bytes): per
 // (tile, Gaussian) pair a 36-byte partial 2D gradient, written by the raster
 // backward at the pair's Gaussian-major slot (the Gaussian's pair offset plus
-// the tile's row-major index inside the Gaussian's tile rectangle), and the
-// Gaussian id at each position of the per-tile lists.
-constexpr int64_t kPairBytes = 40;
+// the tile's row-major index inside the Gaussian's tile rectangle), the
+// Gaussian id at each position of the per-tile lists, and in OIT mode the
+// pair's partial dL/du through the coverage term (Gaussian-major, like the
+// 2D gradient).
+constexpr int64_t kPairBytes = 44;
 struct PairView {
   float3* part;        // [capacity][3] float3: (mu_x, mu_y, A) (B, C, r) (g, b, a)
   uint32_t* ids;       // [capacity]
+  float* du;           // [capacity]
 };
 __host__ __device__ inline PairView pair_view(const void* pairs, int64_t capacity) {
   char* b = static_cast<char*>(const_cast<void*>(pairs));
   PairView v;
   v.part = reinterpret_cast<float3*>(b);
   v.ids = reinterpret_cast<uint32_t*>(b + 36 * capacity);
+  v.du = reinterpret_cast<float*>(b + 40 * capacity);
   return v;
 }
 
@@ -95,7 +100,7 @@ struct Layout {
   int64_t scan_parts = 0;
   size_t off_cams = 0, off_flags = 0, off_rec = 0, off_rect = 0, off_hist = 0, off_scan = 0,
          off_goff = 0, off_grad2d = 0, off_tstart = 0, off_tilepart = 0, off_gpart = 0, off_items = 0, off_acc = 0,
-         off_pd = 0;
+         off_pd = 0, off_oit = 0, off_acclog = 0, off_du2d = 0, off_pdk = 0;
   int64_t gpart_blocks = 0;
   size_t bytes = 0;
 };
@@ -156,7 +161,7 @@ hipError_t launch_project(const wsr_scene* sc, const wsr_params* P, const float*
                           const Layout& L, void* ws, float* out_proj, hipStream_t st);
 hipError_t launch_upload_cameras(const DevCamera* dc, int32_t nv, void* ws, const Layout& L,
                                  hipStream_t st);
-hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, hipStream_t st);
+hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, bool oit, hipStream_t st);
 hipError_t launch_raster_fwd(const Layout& L, void* ws, const void* pairs, int64_t capacity,
                              const wsr_params* P, const float* globals, float* out_rgb,
                              float* out_den, int32_t* out_count, hipStream_t st);

@@ -416,14 +416,15 @@ def test_gaussian_shards_sum_to_the_full_render():
     for idx, c_s, d_s in parts:
         gs = c_s.render_bwd(d_s, g, dL, rgb, den)
         ti = torch.from_numpy(idx).cuda()
-        # a shard's backward forms every (tile, Gaussian) pair's sums exactly as
-        # the full backward does (same lanes, same fixed merge order), from the
-        # same dL/dC, C and D, so the per-Gaussian gradients agree to rounding
+        # same dL/dC, C and D, and every pair's per-wave sums are the same; the
+        # merge adds a record's per-wave sums in the order of the rounds that
+        # reach them, which depends on the composition of the tile lists, so
+        # the shard's gradients agree with the full scene's to float rounding
         for k in ("means", "log_scales", "quats", "lc_v"):
             ref = full[k][..., ti]
-            assert (gs[k] - ref).abs().max().item() <= 1e-6 * max(ref.abs().max().item(), 1e-12), k
+            assert (gs[k] - ref).abs().max().item() <= 2e-5 * max(ref.abs().max().item(), 1e-12), k
         ref = full["sh"][:, ti, :]
-        assert (gs["sh"] - ref).abs().max().item() <= 1e-6 * ref.abs().max().item()
+        assert (gs["sh"] - ref).abs().max().item() <= 2e-5 * ref.abs().max().item()
         # background gradients are per-pixel terms: every shard sees all of them
         assert torch.allclose(gs["globals"][2:], full["globals"][2:], rtol=1e-5, atol=1e-5)
         sig += gs["globals"][0].item()
