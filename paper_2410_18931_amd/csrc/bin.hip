@@ -7,9 +7,9 @@
 //      view v and counts their (tile, Gaussian) pairs into an LDS histogram
 //      of the tile rows of chunk z, written contiguously as row b of the
 //      block-major count matrix M[v][b][tile].
-//   2. column_scan: one thread per tile turns its column of M into exclusive
-//      prefixes over the blocks and produces the tile's total; a scan of the
-//      totals gives every tile the start of its list (tile_start).
+//   2. column_scan_wide: each tile's column of M becomes exclusive prefixes
+//      over the blocks, and the tile's total; tile_scan_single scans the
+//      totals into the start of every tile's list (tile_start).
 //   3. bin_pass<scatter>: the same blocks re-expand their pairs and place ids
 //      at tile_start[t] + M[v][b][t] + an LDS-atomic cursor.
 // Pairs are expanded load-balanced: per round of 256 Gaussians a block-wide
@@ -20,8 +20,8 @@
 //
 // The same step also lays out the backward's per-pair scratch: every
 // (view, Gaussian) gets a contiguous range of "Gaussian-major" slots, one per
-// tile of its rectangle in row-major order (gauss_counts + scan), and the
-// raster work items that split long tile lists (make_items + scan).
+// tile of its rectangle in row-major order (goff_reduce / goff_apply), and
+// the raster work items that split long tile lists (tile_scan_single).
 #include "wsr_internal.h"
 
 namespace wsr {
@@ -138,54 +138,194 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
   }
 }
 
-// One thread per tile: exclusive prefix of the tile's column of counts over
-// the blocks (in place), and the tile's total into tile_start[t].
-__global__ __launch_bounds__(256) void column_scan(const DevCamera* cams, int32_t nv, int32_t nblk,
-                                                   int64_t total_tiles, uint32_t* hist, uint32_t* tile_start) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (t > total_tiles) return;
-  if (t == total_tiles) {
-    tile_start[t] = 0u;
-    return;
+// Column prefixes of the count matrix, 16 waves per 64 tiles: lane = tile (coalesced
+// rows of the block-major matrix), wave w takes the w-th sixteenth of the
+// blocks.  Pass 1 sums each wave's share, the waves' bases follow from LDS,
+// pass 2 rewrites the share as exclusive prefixes.  Sixteen times the loads
+// in flight of one thread per tile.
+constexpr int kColWaves = 16;
+__global__ __launch_bounds__(kColWaves * kWave) void column_scan_wide(const DevCamera* cams, int32_t nv,
+                                                                      int32_t nblk, int64_t total_tiles,
+                                                                      uint32_t* hist, uint32_t* tile_start) {
+  __shared__ uint32_t s_sum[kColWaves][kWave];
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWave + lane;
+  const bool ok = t < total_tiles;
+  uint32_t* col = hist;
+  int64_t tiles_v = 0;
+  if (ok) {
+    int v = 0;
+    while (v + 1 < nv && cams[v + 1].tile_base <= t) ++v;
+    const DevCamera& cam = cams[v];
+    tiles_v = static_cast<int64_t>(cam.tiles_x) * cam.tiles_y;
+    col = hist + cam.hist_base + (t - cam.tile_base);
   }
-  int v = 0;
-  while (v + 1 < nv && cams[v + 1].tile_base <= t) ++v;
-  const DevCamera& cam = cams[v];
-  const int64_t tiles_v = static_cast<int64_t>(cam.tiles_x) * cam.tiles_y;
-  uint32_t* col = hist + cam.hist_base + (t - cam.tile_base);
-  uint32_t run = 0;
-  int b = 0;
-  for (; b + 8 <= nblk; b += 8) {  // eight independent loads in flight
-    uint32_t c[8];
+  const int b0 = static_cast<int>(static_cast<int64_t>(nblk) * wv / kColWaves);
+  const int b1 = static_cast<int>(static_cast<int64_t>(nblk) * (wv + 1) / kColWaves);
+  uint32_t sum = 0;
+  if (ok)
+    for (int b = b0; b < b1; ++b) sum += col[b * tiles_v];
+  s_sum[wv][lane] = sum;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) c[k] = col[(b + k) * tiles_v];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      col[(b + k) * tiles_v] = run;
-      run += c[k];
+  for (int w = 0; w < kColWaves; ++w) {
+    const uint32_t x = s_sum[w][lane];
+    if (w < wv) run += x;
+    total += x;
+  }
+  if (ok) {
+    for (int b = b0; b < b1; ++b) {
+      const uint32_t c = col[b * tiles_v];
+      col[b * tiles_v] = run;
+      run += c;
     }
+    if (wv == 0) tile_start[t] = total;
   }
-  for (; b < nblk; ++b) {
-    const uint32_t c = col[b * tiles_v];
-    col[b * tiles_v] = run;
-    run += c;
-  }
-  tile_start[t] = run;
+  if (wv == 0 && t == total_tiles) tile_start[t] = 0u;
 }
 
-// ---- device-wide exclusive scan of uint32 (in place), 3 phases ----
+// Exclusive scan over a 1024-thread block of one value per thread; *total
+// receives the block sum.  `sh` needs 16 words.
+__device__ inline uint32_t block_scan_1024(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  uint32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d, kWave);
+    if (lane >= d) inc += o;
+  }
+  if (lane == kWave - 1) sh[wv] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t x = sh[k];
+    if (k < wv) base += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
 
-__global__ __launch_bounds__(256) void scan_reduce(const uint32_t* x, int64_t len, uint32_t* parts) {
+// One workgroup, after the column prefixes: the exclusive scan of the tile
+// totals in place (tile_start; 64-bit running total, so a pair count beyond
+// 32 bits is detected), the overflow flags, and the raster work items --
+// max(1, ceil(list length / kItemSplats)) per tile -- with their exclusive
+// scan (items[total_tiles] = number of items).  Replaces three 3-kernel
+// scans for the tile-sized arrays.
+constexpr int kTileScanThreads = 1024;
+constexpr int kTileScanPer = 8;
+__global__ __launch_bounds__(kTileScanThreads) void tile_scan_single(uint32_t* tile_start, int64_t total_tiles,
+                                                                     uint32_t* items, DevFlags* flags,
+                                                                     int64_t capacity) {
+  __shared__ uint32_t sh[16];
+  const int64_t len = total_tiles + 1;
+  constexpr int64_t kChunk = static_cast<int64_t>(kTileScanThreads) * kTileScanPer;
+  uint64_t carry = 0;
+  for (int64_t c0 = 0; c0 < len; c0 += kChunk) {
+    const int64_t base = c0 + static_cast<int64_t>(threadIdx.x) * kTileScanPer;
+    uint32_t vals[kTileScanPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kTileScanPer; ++k) {
+      vals[k] = base + k < len ? tile_start[base + k] : 0u;
+      s += vals[k];
+    }
+    uint32_t tot;
+    uint64_t run = carry + block_scan_1024(s, sh, &tot);
+#pragma unroll
+    for (int k = 0; k < kTileScanPer; ++k) {
+      if (base + k < len) tile_start[base + k] = static_cast<uint32_t>(run);
+      run += vals[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    flags->total_pairs = carry;
+    flags->wrapped = carry > 0xffffffffull ? 1u : 0u;
+    flags->overflow = (carry > static_cast<uint64_t>(capacity) || carry > 0xffffffffull) ? 1u : 0u;
+    flags->sort_overflow = 0u;
+  }
+  __syncthreads();
+  const uint64_t cap = static_cast<uint64_t>(capacity);
+  uint32_t icarry = 0;
+  for (int64_t c0 = 0; c0 < len; c0 += kChunk) {
+    const int64_t base = c0 + static_cast<int64_t>(threadIdx.x) * kTileScanPer;
+    uint32_t vals[kTileScanPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kTileScanPer; ++k) {
+      const int64_t t = base + k;
+      uint32_t cnt = 0;
+      if (t < total_tiles) {
+        uint64_t a = tile_start[t], e = tile_start[t + 1];
+        a = a < cap ? a : cap;
+        e = e < cap ? e : cap;
+        const uint64_t l = e > a ? e - a : 0;
+        cnt = static_cast<uint32_t>(l == 0 ? 1 : (l + kItemSplats - 1) / kItemSplats);
+      }
+      vals[k] = cnt;
+      s += cnt;
+    }
+    uint32_t tot;
+    uint32_t run = icarry + block_scan_1024(s, sh, &tot);
+#pragma unroll
+    for (int k = 0; k < kTileScanPer; ++k) {
+      if (base + k < len) items[base + k] = run;
+      run += vals[k];
+    }
+    icarry += tot;
+  }
+}
+
+// Gaussian-major pair offsets: the exclusive scan of every (view, Gaussian)'s
+// rectangle size, computed from the rectangles on the fly; the apply phase
+// also stores each offset in the Gaussian's record (where the raster backward
+// reads it).  Three kernels for what took five.
+__device__ __forceinline__ uint32_t rect_count(const uint2* rect, int64_t k, int64_t slots) {
+  if (k >= slots) return 0u;
+  const uint2 r = rect[k];
+  const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
+  return (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
+}
+
+__global__ __launch_bounds__(256) void goff_reduce(const uint2* rect, int64_t slots, uint32_t* parts) {
   __shared__ uint32_t sh[4];
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanItems + threadIdx.x * 16;
   uint32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k)
-    if (base + k < len) s += x[base + k];
+  for (int k = 0; k < 16; ++k) s += rect_count(rect, base + k, slots);
   uint32_t total;
   block_scan_256(s, sh, &total);
   if (threadIdx.x == 0) parts[blockIdx.x] = total;
 }
+
+__global__ __launch_bounds__(256) void goff_apply(const uint2* rect, int64_t slots, const uint32_t* parts,
+                                                  uint32_t* goff, DevSplat* rec) {
+  __shared__ uint32_t sh[4];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanItems + threadIdx.x * 16;
+  uint32_t vals[16];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    vals[k] = rect_count(rect, base + k, slots);
+    s += vals[k];
+  }
+  uint32_t total;
+  uint32_t run = block_scan_256(s, sh, &total) + parts[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t i = base + k;
+    if (i <= slots) goff[i] = run;
+    if (i < slots) rec[i].slot.x = run;
+    run += vals[k];
+  }
+}
+
+// ---- device-wide exclusive scan of uint32 (in place), 3 phases ----
 
 // Scans the per-block partial sums; with `flags`, also records the grand
 // total and whether it exceeds `capacity` or 32 bits.
@@ -223,80 +363,6 @@ __global__ __launch_bounds__(1024) void scan_parts(uint32_t* parts, int64_t npar
   }
 }
 
-__global__ __launch_bounds__(256) void scan_apply(uint32_t* x, int64_t len, const uint32_t* parts) {
-  __shared__ uint32_t sh[4];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanItems + threadIdx.x * 16;
-  uint32_t vals[16];
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    vals[k] = base + k < len ? x[base + k] : 0u;
-    s += vals[k];
-  }
-  uint32_t total;
-  uint32_t run = block_scan_256(s, sh, &total) + parts[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    if (base + k < len) x[base + k] = run;
-    run += vals[k];
-  }
-}
-
-hipError_t scan_in_place(uint32_t* x, int64_t len, uint32_t* parts, DevFlags* flags, int64_t capacity,
-                         hipStream_t st) {
-  const unsigned np = static_cast<unsigned>((len + kScanItems - 1) / kScanItems);
-  scan_reduce<<<np, 256, 0, st>>>(x, len, parts);
-  scan_parts<<<1, 1024, 0, st>>>(parts, np, flags, capacity);
-  scan_apply<<<np, 256, 0, st>>>(x, len, parts);
-  return hipGetLastError();
-}
-
-// Number of (tile, Gaussian) pairs of every (view, Gaussian) slot, the
-// input of the scan that gives each Gaussian a contiguous range of
-// Gaussian-major pair slots (the raster backward writes a partial gradient
-// per pair there; the projection backward sums the range).
-__global__ __launch_bounds__(256) void gauss_counts(const uint2* rect, int64_t slots, uint32_t* goff) {
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (k > slots) return;
-  if (k == slots) {
-    goff[k] = 0u;
-    return;
-  }
-  const uint2 r = rect[k];
-  const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
-  goff[k] = (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
-}
-
-// Copies every (view, Gaussian)'s first pair slot into its record (the
-// projection stored the tile rectangle there), where the raster backward
-// reads it with the rest of the record: one cache line per pair instead of
-// three.
-__global__ __launch_bounds__(256) void record_slots(const uint32_t* goff, int64_t slots, DevSplat* rec) {
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (k >= slots) return;
-  rec[k].slot.x = goff[k];
-}
-
-// Raster work items: tile t's list is cut into max(1, ceil(L / kItemSplats))
-// items, so no single workgroup carries a tile many times heavier than the
-// mean.  items[t] receives the count here and its exclusive prefix after the
-// scan; items[total_tiles] ends up holding the number of items.
-__global__ __launch_bounds__(256) void make_items(const uint32_t* tile_start, int64_t capacity, int64_t total_tiles,
-                                                  uint32_t* items) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (t > total_tiles) return;
-  if (t == total_tiles) {
-    items[t] = 0u;
-    return;
-  }
-  const uint64_t cap = static_cast<uint64_t>(capacity);
-  uint64_t s = tile_start[t], e = tile_start[t + 1];
-  s = s < cap ? s : cap;
-  e = e < cap ? e : cap;
-  const uint64_t len = e > s ? e - s : 0;
-  items[t] = static_cast<uint32_t>(len == 0 ? 1 : (len + kItemSplats - 1) / kItemSplats);
-}
-
 }  // namespace
 
 hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, bool oit, hipStream_t st) {
@@ -329,29 +395,23 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
   if (oit && (e = launch_fill_zero(at<float>(ws, L.off_acclog), sizeof(float) * L.total_pixels, st)) != hipSuccess)
     return e;
   bin_pass<false><<<grid, kBinThreads, lds, st>>>(a);
-  const int64_t tl = L.total_tiles + 1;
-  column_scan<<<static_cast<unsigned>((tl + 255) / 256), 256, 0, st>>>(a.cams, L.nv, L.nblk, L.total_tiles, hist,
-                                                                      tstart);
+  column_scan_wide<<<static_cast<unsigned>((L.total_tiles + 1 + kWave - 1) / kWave), kColWaves * kWave, 0, st>>>(
+      a.cams, L.nv, L.nblk, L.total_tiles, hist, tstart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = scan_in_place(tstart, tl, parts, flags, capacity, st)) != hipSuccess) return e;
+  // tile starts, overflow flags and raster work items in one workgroup
+  tile_scan_single<<<1, kTileScanThreads, 0, st>>>(tstart, L.total_tiles, items, flags, capacity);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   bin_pass<true><<<grid, kBinThreads, lds, st>>>(a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
 
-  // Gaussian-major pair offsets (exclusive scan of the rectangle sizes)
-  const int64_t glen = L.n * L.nv + 1;
-  gauss_counts<<<static_cast<unsigned>((glen + 255) / 256), 256, 0, st>>>(a.rect, L.n * L.nv, goff);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = scan_in_place(goff, glen, parts, nullptr, 0, st)) != hipSuccess) return e;
-  if (L.n * L.nv > 0) {
-    record_slots<<<static_cast<unsigned>((L.n * L.nv + 255) / 256), 256, 0, st>>>(goff, L.n * L.nv,
-                                                                                  at<DevSplat>(ws, L.off_rec));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-
-  // raster work items per tile, then their exclusive prefix
-  make_items<<<static_cast<unsigned>((tl + 255) / 256), 256, 0, st>>>(tstart, capacity, L.total_tiles, items);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  return scan_in_place(items, tl, parts, nullptr, 0, st);
+  // Gaussian-major pair offsets (exclusive scan of the rectangle sizes),
+  // also stored in the records
+  const int64_t slots = L.n * L.nv;
+  const unsigned np = static_cast<unsigned>((slots + 1 + kScanItems - 1) / kScanItems);
+  goff_reduce<<<np, 256, 0, st>>>(a.rect, slots, parts);
+  scan_parts<<<1, 1024, 0, st>>>(parts, np, nullptr, 0);
+  goff_apply<<<np, 256, 0, st>>>(a.rect, slots, parts, goff, at<DevSplat>(ws, L.off_rec));
+  return hipGetLastError();
 }
 
 }  // namespace wsr

@@ -135,7 +135,7 @@ struct RasterArgs {
   const float* den;
   float3* part;           // per-pair partial 2D gradients, 3 float3 per slot
   float* tilepart;
-  // work items (see make_items) and the split-tile accumulator
+  // work items (see tile_scan_single) and the split-tile accumulator
   const uint32_t* items;
   int64_t total_tiles;
   float* acc;
