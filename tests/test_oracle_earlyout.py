@@ -1,6 +1,6 @@
-"""Pins of the opacity early-out (App. D proposes halting the evaluation of
-Gaussians whose opacity falls below a threshold): a pair contributes only
-while u exp(-q/2) >= alpha_cut.  Checked against a brute-force numpy sum of
+"""Pins of the opacity early-out (App. D proposes, without specifying it, to
+stop evaluating Gaussians of low opacity): a pair contributes only while
+u exp(-q/2) >= alpha_cut.  Checked against a brute-force numpy sum of
 Eq. 7 with that rule, against removing the Gaussians that can never pass it,
 and the backward against central differences away from the cutoffs."""
 import numpy as np
