@@ -39,11 +39,13 @@ BWD_FLOPS_PER_PAIR = 48
 # HBM traffic of the dominant kernel, from `rocprofv3 --pmc FETCH_SIZE` and
 # `--pmc WRITE_SIZE` runs of this benchmark (KiB per dispatch), each scaled by
 # what the same counter reads for a plain device copy of known size
-# (`--calibrate-copy`).  Valid only for the kernel source it was measured on.
+# (`--calibrate-copy`).  Valid only for the kernel source and the workload it
+# was measured on.
 TRAFFIC = {
-    "raster_bwd": {"source": "raster.hip", "source_sha": "3ef59bc352188e86",
-                   "fetch_kib": 1323096.0, "write_kib": 490067.1,
-                   "fetch_factor": 262157.6 / 524288.0, "write_factor": 524288.0 / 524288.0},
+    "raster_bwd": {"source": "raster.hip", "source_sha": "06e1e11b2a4b80ac",
+                   "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 0.0},
+                   "fetch_kib": 543440.9, "write_kib": 492407.8,
+                   "fetch_factor": 262157.9 / 524288.0, "write_factor": 524288.0 / 524288.0},
 }
 
 
@@ -53,9 +55,11 @@ def _source_sha(name: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_bytes(kernel: str):
+def traffic_bytes(kernel: str, args) -> float | None:
     t = TRAFFIC.get(kernel)
     if not t or t["source_sha"] != _source_sha(t["source"]):
+        return None
+    if any(getattr(args, k) != v for k, v in t["workload"].items()):
         return None
     return t["fetch_kib"] * 1024 / t["fetch_factor"] + t["write_kib"] * 1024 / t["write_factor"]
 
@@ -425,7 +429,7 @@ def main():
         "roofline": {"kernel": f"{dominant} (raster_{'fwd' if dominant == 'raster_fwd' else 'bwd'}_kernel)",
                      "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": traffic_bytes(dominant),
+                     "traffic": traffic_bytes(dominant, args),
                      "flops_per_pair": FWD_FLOPS_PER_PAIR if dominant == "raster_fwd" else BWD_FLOPS_PER_PAIR,
                      "launch_ms": round(stage_ms[dominant], 4), "algorithmic_bytes": ab[dominant]},
         "stage_hbm_gbs": {k: round(ab[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in names},
