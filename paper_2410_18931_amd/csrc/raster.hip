@@ -14,6 +14,8 @@
 // register accumulation.  The sums are commutative, so the list order does
 // not matter, and no per-pair data is stored between forward and backward:
 // the backward recomputes every pair.
+#include <type_traits>
+
 #include "wsr_internal.h"
 
 namespace wsr {
@@ -37,6 +39,15 @@ struct TileGeom {
 // their values), so both take the same support decision for every pair,
 // whatever the tile size.  dx is formed as (pixel centre - integer origin)
 // - fractional centre; the first difference is exact.
+//
+// Staged records carry the conic multiplied by log2(e) / 2 (see
+// stage_and_cull), so the form below is q log2(e) / 2, the falloff
+// exp(-q / 2) is one hardware exp2 of its negation, and every cutoff it is
+// compared with (tau, a record's own early-out cutoff) is scaled by the
+// same factor.
+constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
+constexpr float kTwoLn2 = 1.38629436111989061f;     // its inverse
+
 __device__ __forceinline__ float quad_form(float A, float B2dy, float Cdy2, float dx) {
   return fmaf(fmaf(A, dx, B2dy), dx, Cdy2);
 }
@@ -49,8 +60,8 @@ __device__ __forceinline__ float pair_q(const SplatRec& r, float pcx, float pcy,
   return quad_form(r.r0.z, r.r0.w * dy, (r.r1.x * dy) * dy, dx);
 }
 
-// exp(-q/2) as one hardware exp2 of q * (-log2(e) / 2)
-__device__ __forceinline__ float falloff(float q) { return __builtin_amdgcn_exp2f(q * -0.72134752044448170f); }
+// exp(-q/2) from the scaled form q log2(e) / 2
+__device__ __forceinline__ float falloff(float qs) { return __builtin_amdgcn_exp2f(-qs); }
 
 __device__ __forceinline__ float2 rec_extent(const SplatRec& r) {
   const uint32_t e = __float_as_uint(r.r2.w);
@@ -122,7 +133,7 @@ struct RasterArgs {
   int64_t n;
   int64_t capacity;
   int32_t nv;
-  float tau;
+  float tau;              // support cutoff, times log2(e) / 2 like the staged conic
   int32_t unnormalised;   // write the raw sums (no background, no division)
   const float* globals;
   // forward outputs
@@ -209,14 +220,19 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
 }
 
 // Stage one batch of records into LDS and build this wave's culled list.
-// Returns the list length.  With SLOTS (the backward), also the
-// Gaussian-major slot of each staged (tile, splat) pair -- the Gaussian's
-// first slot plus this tile's row-major index in its tile rectangle, the
-// order in which binning enumerated its pairs -- and, per staged record, its
-// position in this wave's list (0xffff if culled).
-template <int T, int BATCH, bool SLOTS, bool CUT, bool OIT = false>
+// Returns the list length.  The staged conic (and with CUT the record's own
+// cutoff) is scaled by log2(e) / 2.  With PREMUL (the forward) the staged
+// colour is premultiplied by the amplitude, so a pair adds G (amp c) and
+// G amp.  The list holds staged-record indices (uint8_t) or, as uint32_t,
+// their byte offsets in s_rec, which the forward uses as LDS addresses
+// directly.  With SLOTS (the backward), also the Gaussian-major slot of
+// each staged (tile, splat) pair -- the Gaussian's first slot plus this
+// tile's row-major index in its tile rectangle, the order in which binning
+// enumerated its pairs -- and, per staged record, its position in this
+// wave's list (0xffff if culled).
+template <int T, int BATCH, bool SLOTS, bool CUT, bool OIT, bool PREMUL, typename LT>
 __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
-                                              SplatRec* s_rec, uint32_t* s_slot, uint8_t* s_list,
+                                              SplatRec* s_rec, uint32_t* s_slot, LT* s_list,
                                               uint16_t* s_pos, float* s_u = nullptr) {
   using G = TileGeom<T>;
   __syncthreads();  // previous batch fully consumed
@@ -224,7 +240,17 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
     const uint32_t j = b + q;
     if (j < c.end) {
       const DevSplat* d = a.rec + static_cast<int64_t>(c.v) * c.n + a.ids[j];
-      s_rec[q] = d->s;
+      SplatRec r = d->s;
+      r.r0.z *= kHalfLog2e;
+      r.r0.w *= kHalfLog2e;
+      r.r1.x *= kHalfLog2e;
+      if (CUT) r.r2.w *= kHalfLog2e;
+      if (PREMUL) {
+        r.r2.x *= r.r1.w;
+        r.r2.y *= r.r1.w;
+        r.r2.z *= r.r1.w;
+      }
+      s_rec[q] = r;
       if (OIT) s_u[q] = __uint_as_float(d->slot.w);  // the opacity u
       if (SLOTS) {
         const uint4 sl = d->slot;
@@ -235,7 +261,7 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
   }
   __syncthreads();
   const int cnt = static_cast<int>(min(static_cast<uint32_t>(BATCH), c.end - b));
-  uint8_t* list = s_list + c.wave * BATCH;
+  LT* list = s_list + c.wave * BATCH;
   int m = 0;
   const float bx = c.bx0 + 0.5f, by = c.by0 + 0.5f;
   for (int k0 = 0; k0 < cnt; k0 += kWave) {
@@ -243,7 +269,7 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
     const bool hit = k < cnt && block_hits<CUT>(s_rec[k], bx, by, static_cast<float>(G::kSub - 1), a.tau);
     const uint64_t mask = __ballot(hit);
     const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
-    if (hit) list[pos] = static_cast<uint8_t>(k);
+    if (hit) list[pos] = static_cast<LT>(sizeof(LT) == 1 ? k : k * static_cast<int>(sizeof(SplatRec)));
     if (SLOTS && k < BATCH) s_pos[c.wave * BATCH + k] = hit ? static_cast<uint16_t>(pos) : 0xffffu;
     m += __popcll(mask);
   }
@@ -293,11 +319,18 @@ __device__ __forceinline__ void write_pixel_oit(const RasterArgs& a, int64_t pix
   a.oit[pix] = make_float4(ar, ag, ab, P);
 }
 
+__device__ __forceinline__ const SplatRec& rec_at(const SplatRec* base, uint32_t off) {
+  return *reinterpret_cast<const SplatRec*>(reinterpret_cast<const char*>(base) + off);
+}
+
+// Forward.  Lists hold LDS byte offsets of the staged records, except with
+// OIT, whose coverage term needs the record index for the opacity.
 template <int T, bool COUNT, bool CUT, bool OIT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
+  using LT = typename std::conditional<OIT, uint8_t, uint32_t>::type;
   __shared__ SplatRec s_rec[G::kBatch];
-  __shared__ __align__(16) uint8_t s_list[G::kWaves * G::kBatch];
+  __shared__ __align__(16) LT s_list[G::kWaves * G::kBatch];
   __shared__ float s_u[OIT ? G::kBatch : 1];
   TileCtx<T> c;
   const DevCamera* cam;
@@ -310,38 +343,53 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   const float pcy = static_cast<float>(c.py) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T, G::kBatch, false, CUT, OIT>(a, c, b, s_rec, nullptr, s_list, nullptr, s_u);
-    const uint8_t* list = s_list + c.wave * G::kBatch;
-    // four splats per step: one 4-byte read fetches their list entries and
-    // all four records are requested before any arithmetic, so LDS latency
-    // is paid once per four splats
+    const int m = stage_and_cull<T, G::kBatch, false, CUT, OIT, true, LT>(a, c, b, s_rec, nullptr, s_list, nullptr,
+                                                                         s_u);
+    const LT* list = s_list + c.wave * G::kBatch;
+    // four splats per step: one read fetches their list entries and all four
+    // records are requested before any arithmetic, so LDS latency is paid
+    // once per four splats.  The staged colour carries the amplitude.
     auto accumulate = [&](const SplatRec& r, int k) {
       float dx, dy;
       const float q = pair_q(r, pcx, pcy, &dx, &dy);
       const float cut = CUT ? r.r2.w : tau;
       const float G = q <= cut ? falloff(q) : 0.f;
-      const float al = r.r1.w * G;
-      nr = fmaf(al, r.r2.x, nr);
-      ng = fmaf(al, r.r2.y, ng);
-      nb = fmaf(al, r.r2.z, nb);
-      dd += al;
+      nr = fmaf(G, r.r2.x, nr);
+      ng = fmaf(G, r.r2.y, ng);
+      nb = fmaf(G, r.r2.z, nb);
+      dd = fmaf(G, r.r1.w, dd);
       if (OIT) cov *= 1.f - __builtin_amdgcn_fmed3f(s_u[k] * G, 0.f, 1.f);
       if (COUNT) cntp += q <= cut ? 1 : 0;
     };
     int i = 0;
-    for (; i + 4 <= m; i += 4) {
-      const uint32_t k4 = *reinterpret_cast<const uint32_t*>(list + i);
-      const int k0 = k4 & 0xffu, k1 = (k4 >> 8) & 0xffu, k2 = (k4 >> 16) & 0xffu, k3 = k4 >> 24;
-      const SplatRec r0 = s_rec[k0];
-      const SplatRec r1 = s_rec[k1];
-      const SplatRec r2 = s_rec[k2];
-      const SplatRec r3 = s_rec[k3];
-      accumulate(r0, k0);
-      accumulate(r1, k1);
-      accumulate(r2, k2);
-      accumulate(r3, k3);
+    if constexpr (OIT) {
+      for (; i + 4 <= m; i += 4) {
+        const uint32_t k4 = *reinterpret_cast<const uint32_t*>(list + i);
+        const int k0 = k4 & 0xffu, k1 = (k4 >> 8) & 0xffu, k2 = (k4 >> 16) & 0xffu, k3 = k4 >> 24;
+        const SplatRec r0 = s_rec[k0];
+        const SplatRec r1 = s_rec[k1];
+        const SplatRec r2 = s_rec[k2];
+        const SplatRec r3 = s_rec[k3];
+        accumulate(r0, k0);
+        accumulate(r1, k1);
+        accumulate(r2, k2);
+        accumulate(r3, k3);
+      }
+      for (; i < m; ++i) accumulate(s_rec[list[i]], list[i]);
+    } else {
+      for (; i + 4 <= m; i += 4) {
+        const uint4 o4 = *reinterpret_cast<const uint4*>(list + i);
+        const SplatRec r0 = rec_at(s_rec, o4.x);
+        const SplatRec r1 = rec_at(s_rec, o4.y);
+        const SplatRec r2 = rec_at(s_rec, o4.z);
+        const SplatRec r3 = rec_at(s_rec, o4.w);
+        accumulate(r0, 0);
+        accumulate(r1, 0);
+        accumulate(r2, 0);
+        accumulate(r3, 0);
+      }
+      for (; i < m; ++i) accumulate(rec_at(s_rec, list[i]), 0);
     }
-    for (; i < m; ++i) accumulate(s_rec[list[i]], list[i]);
   }
   if (c.px >= cam->width || c.py >= cam->height) return;
   const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
@@ -455,11 +503,13 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
   }
   // the sums above leave out the splat's constant amplitude (a = amp G):
   // dq = -amp e / 2, and with q = A dx^2 + B2 dx dy + C dy^2, dx = px - mu_x,
-  // dL/dmu_x = -sum dq (2A dx + B2 dy) = amp (A Mx + (B2/2) My), and so on;
+  // dL/dmu_x = -sum dq (2A dx + B2 dy) = amp (A Mx + (B2/2) My), and so on
+  // (the staged conic is scaled by log2(e) / 2, undone here);
   // dL/dc = amp sum G gbar, dL/damp = sum G dL/da
   const int l = c.lane;
-  out[0][l] = amp * (A * Mx + 0.5f * B2 * My);
-  out[1][l] = amp * (0.5f * B2 * Mx + Cc * My);
+  const float ampc = amp * kTwoLn2;
+  out[0][l] = ampc * (A * Mx + 0.5f * B2 * My);
+  out[1][l] = ampc * (0.5f * B2 * Mx + Cc * My);
   out[2][l] = -0.5f * amp * Mxx;
   out[3][l] = -amp * Mxy;
   out[4][l] = -0.5f * amp * Myy;
@@ -522,8 +572,8 @@ __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m
     Myy = fmaf(dy * dy, S0, Myy);
   }
   const int l = c.lane;
-  out[0][l] = A * Mx + 0.5f * B2 * My;
-  out[1][l] = 0.5f * B2 * Mx + Cc * My;
+  out[0][l] = kTwoLn2 * (A * Mx + 0.5f * B2 * My);  // staged conic scaled by log2(e) / 2
+  out[1][l] = kTwoLn2 * (0.5f * B2 * Mx + Cc * My);
   out[2][l] = -0.5f * Mxx;
   out[3][l] = -Mxy;
   out[4][l] = -0.5f * Myy;
@@ -648,7 +698,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
   const float tau = a.tau;
   const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
   for (uint32_t b = c.start; b < c.end; b += kB) {
-    const int m = stage_and_cull<T, kB, true, CUT, OIT>(a, c, b, s_rec, s_slot, s_list, s_pos, s_u);
+    const int m = stage_and_cull<T, kB, true, CUT, OIT, false, uint8_t>(a, c, b, s_rec, s_slot, s_list, s_pos, s_u);
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kB), c.end - b));
     if (c.lane == 0) s_m[c.wave] = m;
     __syncthreads();
@@ -790,7 +840,8 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_sorted_kernel(Ra
   const float pcy = static_cast<float>(c.py) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T, G::kBatch, false, false>(a, c, b, s_rec, nullptr, s_list, nullptr);
+    const int m = stage_and_cull<T, G::kBatch, false, false, false, false, uint8_t>(a, c, b, s_rec, nullptr, s_list,
+                                                                            nullptr);
     const uint8_t* list = s_list + c.wave * G::kBatch;
     for (int i = 0; i < m && live; ++i) {
       const SplatRec r = s_rec[list[i]];
@@ -828,7 +879,7 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   a.n = L.n;
   a.capacity = capacity;
   a.nv = L.nv;
-  a.tau = P->tau;
+  a.tau = P->tau * kHalfLog2e;  // in the scale of the staged conic
   a.unnormalised = (P->flags & WSR_FLAG_UNNORMALISED) ? 1 : 0;
   a.globals = globals;
   a.items = at<uint32_t>(ws, L.off_items);
