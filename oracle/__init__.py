@@ -66,11 +66,11 @@ def _load():
         P = C.c_void_p
         lib.ora_project.argtypes = [P, P, P, P]
         lib.ora_render.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
-                                   C.c_int32, C.c_double, P, P, P, P, P, P, P]
+                                   C.c_int32, C.c_double, C.c_double, P, P, P, P, P, P, P]
         lib.ora_render_bwd.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                        P, P, P, P, P, P, P, P, P]
         D = C.c_double
-        lib.ora_render_sorted.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, D, D, D, D,
+        lib.ora_render_sorted.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, D, D, D, D, D,
                                           P, P, P]
         lib.ora_sh_basis.argtypes = [P, C.c_int64, C.c_int32, P]
         lib.ora_quat_to_rot.argtypes = [P, C.c_int64, P]
@@ -138,11 +138,13 @@ def _window(cam, crop):
     return x0, y0, x1, y1
 
 
-def render(scene, cam, settings, crop=None, mode: str = "strict", eta: float = 1e-6) -> dict:
+def render(scene, cam, settings, crop=None, mode: str = "strict", eta: float = 1e-6, pos_h: float = 0.0) -> dict:
     """Weighted sum rendering of one view (Sec. 4.2, Eq. 7) over the pixel
     window ``crop = (x0, y0, x1, y1)`` (whole image by default).  ``amb`` /
     ``amb_c`` report the pairs within ``eta`` (relative to the magnitude of
-    the terms of q) of the support cutoff; ``abs_den`` is |w_B| + sum |a|."""
+    the terms of q) of the support cutoff, widened by the effect of a centre
+    rounded to float32 relative to a point within ``pos_h`` pixels;
+    ``abs_den`` is |w_B| + sum |a|."""
     pk = _Packed(scene, cam, settings)
     x0, y0, x1, y1 = _window(cam, crop)
     h, w = max(y1 - y0, 0), max(x1 - x0, 0)
@@ -154,25 +156,26 @@ def render(scene, cam, settings, crop=None, mode: str = "strict", eta: float = 1
     absden = np.zeros((h, w))
     cnt = np.zeros((h, w), dtype=np.int64)
     _load().ora_render(C.byref(pk.scene), C.byref(pk.cam), C.byref(pk.params), x0, y0, x1, y1,
-                       {"strict": 0, "aabb": 1}[mode], float(eta), _ptr(Cimg), _ptr(num),
+                       {"strict": 0, "aabb": 1}[mode], float(eta), float(pos_h), _ptr(Cimg), _ptr(num),
                        _ptr(den), _ptr(amb), _ptr(ambc), _ptr(absden), _ptr(cnt))
     return {"C": Cimg, "num": num, "den": den, "amb": amb, "amb_c": ambc, "abs_den": absden, "count": cnt}
 
 
 def render_sorted(scene, cam, settings, crop=None, alpha_max: float = 0.99, alpha_min: float = 0.0,
-                  t_min: float = 0.0, eta: float = 1e-6) -> dict:
+                  t_min: float = 0.0, eta: float = 1e-6, pos_h: float = 0.0) -> dict:
     """Sorted alpha blending (Eq. 6) of the same splats, front to back by
     camera depth, alpha = min(alpha_max, u exp(-q/2)) with u the opacity (no
     depth weight), layers below alpha_min skipped, composition stopped once
     the transmittance falls below t_min, background c_B behind.  Returns the
     colour, the final transmittance and the per-pixel sum of alpha over
-    layers within ``eta`` of the support cutoff."""
+    layers within the window of ``render`` of the support cutoff."""
     pk = _Packed(scene, cam, settings)
     x0, y0, x1, y1 = _window(cam, crop)
     h, w = max(y1 - y0, 0), max(x1 - x0, 0)
     out = {"C": np.zeros((h, w, 3)), "T": np.zeros((h, w)), "amb": np.zeros((h, w))}
     _load().ora_render_sorted(C.byref(pk.scene), C.byref(pk.cam), C.byref(pk.params), x0, y0, x1, y1,
-                              float(alpha_max), float(alpha_min), float(t_min), float(eta), _ptr(out["C"]),
+                              float(alpha_max), float(alpha_min), float(t_min), float(eta), float(pos_h),
+                              _ptr(out["C"]),
                               _ptr(out["T"]), _ptr(out["amb"]))
     return out
 

@@ -424,6 +424,19 @@ static void free_visible(vis_t *v)
 /* Forward render                                                            */
 /* ------------------------------------------------------------------------- */
 
+/* Test support, not part of the method: how far q can move when the
+ * centre is rounded to float32 relative to a frame origin within pos_h of
+ * the pixel centre (a relative error of at most 2^-24 of |d| + pos_h per
+ * axis): |dq/dmu_x| (|dx| + pos_h) 2^-24 + |dq/dmu_y| (|dy| + pos_h) 2^-24.
+ * Zero when pos_h <= 0. */
+static double amb_pos_window(const proj_t *g, double dx, double dy, double pos_h)
+{
+    if (pos_h <= 0.0) return 0.0;
+    const double gx = 2.0 * fabs(g->conic[0] * dx + g->conic[1] * dy);
+    const double gy = 2.0 * fabs(g->conic[1] * dx + g->conic[2] * dy);
+    return ldexp(gx * (fabs(dx) + pos_h) + gy * (fabs(dy) + pos_h), -24);
+}
+
 /*
  * Render the pixel window [x0, x1) x [y0, y1) of one view with Eq. 7.
  *   mode 0 ("strict"): every pixel is tested against every Gaussian in the
@@ -437,10 +450,13 @@ static void free_visible(vis_t *v)
  *   out_num [h][w][3] numerator including c_B w_B
  *   out_den [h][w]    denominator including w_B
  *   out_amb [h][w]    sum of |a| over the pairs whose support decision a
- *                     float32 evaluation of q may flip: |q - tau| <= eta * M
+ *                     float32 evaluation of q may flip:
+ *                     |q - tau| <= eta * M + amb_pos_window(..., pos_h)
  *                     with M = A dx^2 + 2|B dx dy| + C dy^2, the magnitude of
  *                     the terms q sums (rounding error scales with M, not q,
- *                     because the terms cancel for elongated splats)
+ *                     because the terms cancel for elongated splats); pos_h
+ *                     > 0 adds the effect of a centre rounded in float32
+ *                     relative to a point within pos_h of the pixel centre
  *   out_ambc [h][w]   sum over those pairs of |a| * max_c |rgb_c - C_c|
  *   out_absden [h][w] |w_B| + sum of |a| over pairs with q <= tau (with den,
  *                     the conditioning of the normalisation)
@@ -448,7 +464,7 @@ static void free_visible(vis_t *v)
  * Any output pointer may be NULL.
  */
 void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
-                int64_t x0, int64_t y0, int64_t x1, int64_t y1, int32_t mode, double eta,
+                int64_t x0, int64_t y0, int64_t x1, int64_t y1, int32_t mode, double eta, double pos_h,
                 double *out_C, double *out_num, double *out_den, double *out_amb,
                 double *out_ambc, double *out_absden, int64_t *out_cnt)
 {
@@ -567,7 +583,9 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                     const double dy = (double)(y0 + yy) + 0.5 - g->mu[1];
                     const double M = g->conic[0] * dx * dx + 2.0 * fabs(g->conic[1] * dx * dy) +
                                      g->conic[2] * dy * dy;
-                    if (fabs(q - g->cut) <= eta * M + (g->cut < tau ? 10.0 * eta * (fabs(g->cut) + 1.0) : 0.0)) {
+                    const double win = eta * M + amb_pos_window(g, dx, dy, pos_h) +
+                                       (g->cut < tau ? 10.0 * eta * (fabs(g->cut) + 1.0) : 0.0);
+                    if (fabs(q - g->cut) <= win) {
                         const double a = fabs(g->u * g->w * exp(-0.5 * q));
                         double md = 0.0;
                         for (int c = 0; c < 3; ++c) {
@@ -952,11 +970,11 @@ static int layer_cmp(const void *a, const void *b)
  * and composition stops after the layer that takes T below t_min (t_min = 0:
  * never).  Outputs: out_C [h][w][3], out_T [h][w] the final transmittance,
  * out_amb [h][w] the sum of alpha over layers whose support decision is within
- * eta * M of the cutoff (as in ora_render).  Any output may be NULL.
+ * the window of ora_render of the cutoff.  Any output may be NULL.
  */
 void ora_render_sorted(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                        int64_t x0, int64_t y0, int64_t x1, int64_t y1, double alpha_max,
-                       double alpha_min, double t_min, double eta,
+                       double alpha_min, double t_min, double eta, double pos_h,
                        double *out_C, double *out_T, double *out_amb)
 {
     const int64_t w = x1 - x0, h = y1 - y0;
@@ -981,7 +999,7 @@ void ora_render_sorted(const ora_scene *S, const ora_camera *cam, const ora_para
                                      g->conic[2] * dy * dy;
                     double a = g->u * exp(-0.5 * q);
                     if (a > alpha_max) a = alpha_max;
-                    if (fabs(q - tau) <= eta * M) amb += fabs(a);
+                    if (fabs(q - tau) <= eta * M + amb_pos_window(g, dx, dy, pos_h)) amb += fabs(a);
                     if (q > tau || a < alpha_min) continue;
                     lay[k].depth = g->depth;
                     lay[k].index = v.idx[j];

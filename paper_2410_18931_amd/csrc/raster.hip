@@ -33,45 +33,57 @@ struct TileGeom {
   static_assert(kBatch <= 256, "culled lists hold 8-bit record indices");
 };
 
+// A record as staged in LDS for one tile (48 bytes; stage_and_cull builds it
+// from the projected record):
+//   r0 = (mx, my, A, B2)   centre relative to the tile's centre; conic
+//                          (A, B2 = 2B, C) times log2(e) / 2
+//   r1 = (C, amp, c0, c1)  colour (times amp in the forward)
+//   r2 = (c2, ext | cut, 0, 0)  support half-extents (two halves), or with
+//                          the early-out the record's own cutoff times
+//                          log2(e) / 2
+// The tile-relative centre is (integer origin - tile centre) + fractional
+// centre: the difference is exact, the sum rounds once (to within 2^-24 of
+// its magnitude, which is at most the pixel's distance plus half the tile
+// size).  Pixel centres relative to the tile centre are exact, so dx and dy
+// round once more.  With the conic scaled, the form below is q log2(e) / 2, the
+// falloff exp(-q / 2) is one hardware exp2 of its negation, and every cutoff
+// it is compared with (tau, a record's own cutoff) carries the same factor.
+struct StagedRec {
+  float4 r0, r1, r2;
+};
+static_assert(sizeof(StagedRec) == 48, "staged record layout");
+
+constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
+constexpr float kTwoLn2 = 1.38629436111989061f;     // its inverse
+
 // The support predicate and the Gaussian falloff.  Forward and backward
 // evaluate q with exactly this sequence of float operations (the backward
 // hoists the row-constant products B2*dy and (C*dy)*dy, which does not change
 // their values), so both take the same support decision for every pair,
-// whatever the tile size.  dx is formed as (pixel centre - integer origin)
-// - fractional centre; the first difference is exact.
-//
-// Staged records carry the conic multiplied by log2(e) / 2 (see
-// stage_and_cull), so the form below is q log2(e) / 2, the falloff
-// exp(-q / 2) is one hardware exp2 of its negation, and every cutoff it is
-// compared with (tau, a record's own early-out cutoff) is scaled by the
-// same factor.
-constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
-constexpr float kTwoLn2 = 1.38629436111989061f;     // its inverse
-
+// whatever the tile size.
 __device__ __forceinline__ float quad_form(float A, float B2dy, float Cdy2, float dx) {
   return fmaf(fmaf(A, dx, B2dy), dx, Cdy2);
 }
 
-__device__ __forceinline__ float pair_q(const SplatRec& r, float pcx, float pcy, float* dx_o, float* dy_o) {
-  const float dx = (pcx - r.r1.y) - r.r0.x;
-  const float dy = (pcy - r.r1.z) - r.r0.y;
-  *dx_o = dx;
-  *dy_o = dy;
+// px, py: the pixel centre relative to the tile's centre
+__device__ __forceinline__ float pair_q(const StagedRec& r, float px, float py) {
+  const float dx = px - r.r0.x;
+  const float dy = py - r.r0.y;
   return quad_form(r.r0.z, r.r0.w * dy, (r.r1.x * dy) * dy, dx);
 }
 
 // exp(-q/2) from the scaled form q log2(e) / 2
 __device__ __forceinline__ float falloff(float qs) { return __builtin_amdgcn_exp2f(-qs); }
 
-__device__ __forceinline__ float2 rec_extent(const SplatRec& r) {
-  const uint32_t e = __float_as_uint(r.r2.w);
+__device__ __forceinline__ float2 rec_extent(const StagedRec& r) {
+  const uint32_t e = __float_as_uint(r.r2.y);
   const _Float16 ex = __builtin_bit_cast(_Float16, static_cast<uint16_t>(e & 0xffffu));
   const _Float16 ey = __builtin_bit_cast(_Float16, static_cast<uint16_t>(e >> 16));
   return make_float2(static_cast<float>(ex), static_cast<float>(ey));
 }
 
 // Does the splat's support reach the wave block whose pixel centres span
-// [bx, bx + sub1] x [by, by + sub1]?  First the (conservative) support box;
+// [bx, bx + sub1] x [by, by + sub1] (relative to the tile's centre)?  First the (conservative) support box;
 // then, unless the conic is badly conditioned, the exact minimum of q over
 // the block (the unconstrained minimum is the centre; otherwise the minimum
 // lies on an edge, at the clamped 1D minimiser of that edge) against tau with
@@ -85,11 +97,11 @@ __device__ __forceinline__ float2 rec_extent(const SplatRec& r) {
 // with det = A C - B^2 formed by Kahan's algorithm (B^2 split exactly with an
 // FMA) so that it stays accurate for needle-like conics.
 template <bool CUT>
-__device__ __forceinline__ bool block_hits(const SplatRec& r, float bx, float by, float sub1, float tau_in) {
+__device__ __forceinline__ bool block_hits(const StagedRec& r, float bx, float by, float sub1, float tau_in) {
   float2 e;
   float tau = tau_in;
   if (CUT) {
-    tau = r.r2.w;
+    tau = r.r2.y;
     const float A = r.r0.z, B = 0.5f * r.r0.w, C = r.r1.x;
     const float bb = B * B;
     const float det = fmaf(A, C, -bb) - fmaf(B, B, -bb);
@@ -98,8 +110,7 @@ __device__ __forceinline__ bool block_hits(const SplatRec& r, float bx, float by
   } else {
     e = rec_extent(r);
   }
-  const float ox = r.r1.y, oy = r.r1.z, fx = r.r0.x, fy = r.r0.y;
-  const float mx = ox + fx, my = oy + fy;
+  const float mx = r.r0.x, my = r.r0.y;
   const float sx = 1e-3f * fabsf(mx) + 1e-2f, sy = 1e-3f * fabsf(my) + 1e-2f;  // rounding slack
   if (!((mx + e.x + sx >= bx) && (mx - e.x - sx <= bx + sub1) && (my + e.y + sy >= by) &&
         (my - e.y - sy <= by + sub1)))
@@ -107,9 +118,9 @@ __device__ __forceinline__ bool block_hits(const SplatRec& r, float bx, float by
   const float A = r.r0.z, B = 0.5f * r.r0.w, C = r.r1.x;
   const float tr = A + C, det = A * C - B * B;
   if (!(tr * tr <= 102.f * det)) return true;
-  // block corners relative to the centre; (corner - origin) is exact
-  const float x0 = (bx - ox) - fx, x1 = (bx + sub1 - ox) - fx;
-  const float y0 = (by - oy) - fy, y1 = (by + sub1 - oy) - fy;
+  // block corners relative to the centre
+  const float x0 = bx - mx, x1 = (bx + sub1) - mx;
+  const float y0 = by - my, y1 = (by + sub1) - my;
   if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
   const float iA = 1.f / A, iC = 1.f / C;
   float qmin = 3.0e38f;
@@ -178,6 +189,7 @@ struct TileCtx {
   int wave, lane;
   int bx0, by0;                   // first pixel of this wave's block
   int px, py;                     // this lane's pixel
+  int fx0, fy0;                   // frame origin of the staged centres: the tile's centre
 };
 
 template <int T>
@@ -214,16 +226,17 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
   c.lane = threadIdx.x % kWave;
   c.bx0 = c.tx * T + (c.wave % (T / 8)) * G::kSub;
   c.by0 = c.ty * T + (c.wave / (T / 8)) * G::kSub;
+  c.fx0 = c.tx * T + T / 2;
+  c.fy0 = c.ty * T + T / 2;
   c.px = c.bx0 + (c.lane & 7);
   c.py = c.by0 + (c.lane >> 3);
   return true;
 }
 
-// Stage one batch of records into LDS and build this wave's culled list.
-// Returns the list length.  The staged conic (and with CUT the record's own
-// cutoff) is scaled by log2(e) / 2.  With PREMUL (the forward) the staged
-// colour is premultiplied by the amplitude, so a pair adds G (amp c) and
-// G amp.  The list holds staged-record indices (uint8_t) or, as uint32_t,
+// Stage one batch of records into LDS (as StagedRec) and build this wave's
+// culled list.  Returns the list length.  With PREMUL (the forward) the
+// staged colour is premultiplied by the amplitude, so a pair adds G (amp c)
+// and G amp.  The list holds staged-record indices (uint8_t) or, as uint32_t,
 // their byte offsets in s_rec, which the forward uses as LDS addresses
 // directly.  With SLOTS (the backward), also the Gaussian-major slot of
 // each staged (tile, splat) pair -- the Gaussian's first slot plus this
@@ -232,24 +245,28 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
 // wave's list (0xffff if culled).
 template <int T, int BATCH, bool SLOTS, bool CUT, bool OIT, bool PREMUL, typename LT>
 __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
-                                              SplatRec* s_rec, uint32_t* s_slot, LT* s_list,
+                                              StagedRec* s_rec, uint32_t* s_slot, LT* s_list,
                                               uint16_t* s_pos, float* s_u = nullptr) {
   using G = TileGeom<T>;
+  const float tox = static_cast<float>(c.fx0), toy = static_cast<float>(c.fy0);
   __syncthreads();  // previous batch fully consumed
   for (int q = threadIdx.x; q < BATCH; q += G::kThreads) {
     const uint32_t j = b + q;
     if (j < c.end) {
       const DevSplat* d = a.rec + static_cast<int64_t>(c.v) * c.n + a.ids[j];
-      SplatRec r = d->s;
-      r.r0.z *= kHalfLog2e;
-      r.r0.w *= kHalfLog2e;
-      r.r1.x *= kHalfLog2e;
-      if (CUT) r.r2.w *= kHalfLog2e;
+      const SplatRec s = d->s;  // (fx, fy, A, B2) (C, ox, oy, amp) (c0, c1, c2, ext | cut)
+      const float amp = s.r1.w;
+      float c0 = s.r2.x, c1 = s.r2.y, c2 = s.r2.z;
       if (PREMUL) {
-        r.r2.x *= r.r1.w;
-        r.r2.y *= r.r1.w;
-        r.r2.z *= r.r1.w;
+        c0 *= amp;
+        c1 *= amp;
+        c2 *= amp;
       }
+      StagedRec r;
+      r.r0 = make_float4((s.r1.y - tox) + s.r0.x, (s.r1.z - toy) + s.r0.y, s.r0.z * kHalfLog2e,
+                         s.r0.w * kHalfLog2e);
+      r.r1 = make_float4(s.r1.x * kHalfLog2e, amp, c0, c1);
+      r.r2 = make_float4(c2, CUT ? s.r2.w * kHalfLog2e : s.r2.w, 0.f, 0.f);
       s_rec[q] = r;
       if (OIT) s_u[q] = __uint_as_float(d->slot.w);  // the opacity u
       if (SLOTS) {
@@ -263,13 +280,13 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
   const int cnt = static_cast<int>(min(static_cast<uint32_t>(BATCH), c.end - b));
   LT* list = s_list + c.wave * BATCH;
   int m = 0;
-  const float bx = c.bx0 + 0.5f, by = c.by0 + 0.5f;
+  const float bx = static_cast<float>(c.bx0 - c.fx0) + 0.5f, by = static_cast<float>(c.by0 - c.fy0) + 0.5f;
   for (int k0 = 0; k0 < cnt; k0 += kWave) {
     const int k = k0 + c.lane;
     const bool hit = k < cnt && block_hits<CUT>(s_rec[k], bx, by, static_cast<float>(G::kSub - 1), a.tau);
     const uint64_t mask = __ballot(hit);
     const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
-    if (hit) list[pos] = static_cast<LT>(sizeof(LT) == 1 ? k : k * static_cast<int>(sizeof(SplatRec)));
+    if (hit) list[pos] = static_cast<LT>(sizeof(LT) == 1 ? k : k * static_cast<int>(sizeof(StagedRec)));
     if (SLOTS && k < BATCH) s_pos[c.wave * BATCH + k] = hit ? static_cast<uint16_t>(pos) : 0xffffu;
     m += __popcll(mask);
   }
@@ -319,8 +336,8 @@ __device__ __forceinline__ void write_pixel_oit(const RasterArgs& a, int64_t pix
   a.oit[pix] = make_float4(ar, ag, ab, P);
 }
 
-__device__ __forceinline__ const SplatRec& rec_at(const SplatRec* base, uint32_t off) {
-  return *reinterpret_cast<const SplatRec*>(reinterpret_cast<const char*>(base) + off);
+__device__ __forceinline__ const StagedRec& rec_at(const StagedRec* base, uint32_t off) {
+  return *reinterpret_cast<const StagedRec*>(reinterpret_cast<const char*>(base) + off);
 }
 
 // Forward.  Lists hold LDS byte offsets of the staged records, except with
@@ -329,7 +346,7 @@ template <int T, bool COUNT, bool CUT, bool OIT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
   using LT = typename std::conditional<OIT, uint8_t, uint32_t>::type;
-  __shared__ SplatRec s_rec[G::kBatch];
+  __shared__ StagedRec s_rec[G::kBatch];
   __shared__ __align__(16) LT s_list[G::kWaves * G::kBatch];
   __shared__ float s_u[OIT ? G::kBatch : 1];
   TileCtx<T> c;
@@ -339,8 +356,9 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   float nr = 0.f, ng = 0.f, nb = 0.f, dd = 0.f;
   float cov = 1.f;  // OIT: prod (1 - alpha)
   int cntp = 0;
-  const float pcx = static_cast<float>(c.px) + 0.5f;
-  const float pcy = static_cast<float>(c.py) + 0.5f;
+  // this lane's pixel centre relative to the tile's centre (exact)
+  const float pcx = static_cast<float>(c.px - c.fx0) + 0.5f;
+  const float pcy = static_cast<float>(c.py - c.fy0) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
     const int m = stage_and_cull<T, G::kBatch, false, CUT, OIT, true, LT>(a, c, b, s_rec, nullptr, s_list, nullptr,
@@ -349,15 +367,14 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
     // four splats per step: one read fetches their list entries and all four
     // records are requested before any arithmetic, so LDS latency is paid
     // once per four splats.  The staged colour carries the amplitude.
-    auto accumulate = [&](const SplatRec& r, int k) {
-      float dx, dy;
-      const float q = pair_q(r, pcx, pcy, &dx, &dy);
-      const float cut = CUT ? r.r2.w : tau;
+    auto accumulate = [&](const StagedRec& r, int k) {
+      const float q = pair_q(r, pcx, pcy);
+      const float cut = CUT ? r.r2.y : tau;
       const float G = q <= cut ? falloff(q) : 0.f;
-      nr = fmaf(G, r.r2.x, nr);
-      ng = fmaf(G, r.r2.y, ng);
-      nb = fmaf(G, r.r2.z, nb);
-      dd = fmaf(G, r.r1.w, dd);
+      nr = fmaf(G, r.r1.z, nr);
+      ng = fmaf(G, r.r1.w, ng);
+      nb = fmaf(G, r.r2.x, nb);
+      dd = fmaf(G, r.r1.y, dd);
       if (OIT) cov *= 1.f - __builtin_amdgcn_fmed3f(s_u[k] * G, 0.f, 1.f);
       if (COUNT) cntp += q <= cut ? 1 : 0;
     };
@@ -366,10 +383,10 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
       for (; i + 4 <= m; i += 4) {
         const uint32_t k4 = *reinterpret_cast<const uint32_t*>(list + i);
         const int k0 = k4 & 0xffu, k1 = (k4 >> 8) & 0xffu, k2 = (k4 >> 16) & 0xffu, k3 = k4 >> 24;
-        const SplatRec r0 = s_rec[k0];
-        const SplatRec r1 = s_rec[k1];
-        const SplatRec r2 = s_rec[k2];
-        const SplatRec r3 = s_rec[k3];
+        const StagedRec r0 = s_rec[k0];
+        const StagedRec r1 = s_rec[k1];
+        const StagedRec r2 = s_rec[k2];
+        const StagedRec r3 = s_rec[k3];
         accumulate(r0, k0);
         accumulate(r1, k1);
         accumulate(r2, k2);
@@ -379,10 +396,10 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
     } else {
       for (; i + 4 <= m; i += 4) {
         const uint4 o4 = *reinterpret_cast<const uint4*>(list + i);
-        const SplatRec r0 = rec_at(s_rec, o4.x);
-        const SplatRec r1 = rec_at(s_rec, o4.y);
-        const SplatRec r2 = rec_at(s_rec, o4.z);
-        const SplatRec r3 = rec_at(s_rec, o4.w);
+        const StagedRec r0 = rec_at(s_rec, o4.x);
+        const StagedRec r1 = rec_at(s_rec, o4.y);
+        const StagedRec r2 = rec_at(s_rec, o4.z);
+        const StagedRec r3 = rec_at(s_rec, o4.w);
         accumulate(r0, 0);
         accumulate(r1, 0);
         accumulate(r2, 0);
@@ -459,21 +476,21 @@ __device__ __forceinline__ float wave_sum(float x) {
 // a wave-uniform address and enter the FMAs as scalar operands.
 template <int T, bool CUT>
 __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
-                                          const SplatRec* s_rec, const float4* __restrict__ pd_wave,
+                                          const StagedRec* s_rec, const float4* __restrict__ pd_wave,
                                           float (*out)[kWave], float tau) {
   const int j = c0 + c.lane;
   const bool valid = j < m;
   const int kr = valid ? list[j] : 0;
-  const SplatRec r = s_rec[kr];
-  const float amp = r.r1.w, cr = r.r2.x, cg = r.r2.y, cb = r.r2.z;
+  const StagedRec r = s_rec[kr];
+  const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
   float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
   float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
   const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
-  const float cut = CUT ? r.r2.w : tau;
-  // first pixel centre of the block relative to the splat's integer origin
-  // (exact), so dx = (ex0 + col) - fx matches the forward's
-  const float ex0 = (static_cast<float>(c.bx0) + 0.5f) - r.r1.y;
-  const float ey0 = (static_cast<float>(c.by0) + 0.5f) - r.r1.z;
+  const float cut = CUT ? r.r2.y : tau;
+  // first pixel centre of the block relative to the tile's centre (exact),
+  // so dx = (ex0 + col) - mx matches the forward's
+  const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
+  const float ey0 = static_cast<float>(c.by0 - c.fy0) + 0.5f;
 #pragma unroll 1
   for (int row = 0; row < 8; ++row) {
     const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
@@ -526,20 +543,20 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
 // dL/du = sum G dL/dalpha.  The moments therefore carry the amplitude.
 template <int T>
 __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
-                                              const SplatRec* s_rec, const float* s_u,
+                                              const StagedRec* s_rec, const float* s_u,
                                               const float4* __restrict__ pd_wave, const float* __restrict__ pk_wave,
                                               float (*out)[kWave], float tau) {
   const int j = c0 + c.lane;
   const bool valid = j < m;
   const int kr = valid ? list[j] : 0;
-  const SplatRec r = s_rec[kr];
+  const StagedRec r = s_rec[kr];
   const float u = s_u[kr];
-  const float amp = r.r1.w, cr = r.r2.x, cg = r.r2.y, cb = r.r2.z;
+  const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
   float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
   float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f, g_u = 0.f;
   const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
-  const float ex0 = (static_cast<float>(c.bx0) + 0.5f) - r.r1.y;
-  const float ey0 = (static_cast<float>(c.by0) + 0.5f) - r.r1.z;
+  const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
+  const float ey0 = static_cast<float>(c.by0 - c.fy0) + 0.5f;
 #pragma unroll 1
   for (int row = 0; row < 8; ++row) {
     const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
@@ -680,7 +697,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
   using G = TileGeom<T>;
   constexpr int kB = G::kBatch;
   constexpr int NV = OIT ? 10 : 9;  // sums per (tile, splat) pair
-  __shared__ SplatRec s_rec[kB];
+  __shared__ StagedRec s_rec[kB];
   __shared__ uint32_t s_slot[kB];
   __shared__ __align__(16) uint8_t s_list[G::kWaves * kB];
   __shared__ uint16_t s_pos[G::kWaves * kB];
@@ -807,7 +824,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_sorted_kernel(Ra
                                                                               float alpha_min, float t_min,
                                                                               float* out_T) {
   using G = TileGeom<T>;
-  __shared__ SplatRec s_rec[G::kBatch];
+  __shared__ StagedRec s_rec[G::kBatch];
   __shared__ __align__(16) uint8_t s_list[G::kWaves * G::kBatch];
   TileCtx<T> c;
   const int tile = static_cast<int>(blockIdx.x);
@@ -831,28 +848,29 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_sorted_kernel(Ra
   c.lane = threadIdx.x % kWave;
   c.bx0 = c.tx * T + (c.wave % (T / 8)) * G::kSub;
   c.by0 = c.ty * T + (c.wave / (T / 8)) * G::kSub;
+  c.fx0 = c.tx * T + T / 2;
+  c.fy0 = c.ty * T + T / 2;
   c.px = c.bx0 + (c.lane & 7);
   c.py = c.by0 + (c.lane >> 3);
   const bool inside = c.px < cam->width && c.py < cam->height;
   bool live = inside;
   float cr = 0.f, cg = 0.f, cb = 0.f, Tr = 1.f;
-  const float pcx = static_cast<float>(c.px) + 0.5f;
-  const float pcy = static_cast<float>(c.py) + 0.5f;
+  const float pcx = static_cast<float>(c.px - c.fx0) + 0.5f;  // relative to the tile's centre
+  const float pcy = static_cast<float>(c.py - c.fy0) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
     const int m = stage_and_cull<T, G::kBatch, false, false, false, false, uint8_t>(a, c, b, s_rec, nullptr, s_list,
                                                                             nullptr);
     const uint8_t* list = s_list + c.wave * G::kBatch;
     for (int i = 0; i < m && live; ++i) {
-      const SplatRec r = s_rec[list[i]];
-      float dx, dy;
-      const float q = pair_q(r, pcx, pcy, &dx, &dy);
-      const float al = fminf(alpha_max, r.r1.w * falloff(q));
+      const StagedRec r = s_rec[list[i]];
+      const float q = pair_q(r, pcx, pcy);
+      const float al = fminf(alpha_max, r.r1.y * falloff(q));
       if (q <= tau && al >= alpha_min) {
         const float w = al * Tr;
-        cr = fmaf(w, r.r2.x, cr);
-        cg = fmaf(w, r.r2.y, cg);
-        cb = fmaf(w, r.r2.z, cb);
+        cr = fmaf(w, r.r1.z, cr);
+        cg = fmaf(w, r.r1.w, cg);
+        cb = fmaf(w, r.r2.x, cb);
         Tr *= 1.f - al;
         if (Tr < t_min) live = false;
       }

@@ -17,6 +17,14 @@ AMB_ETA = 1e-6      # pairs with |q - tau| <= AMB_ETA * (A dx^2 + 2|B dx dy| + C
 ILL_COND = 10.0     # (|w_B| + sum|a|) / |den| above this: ill-conditioned pixel, counted not gated
 
 
+def amb_kw(settings) -> dict:
+    """The checker's ambiguity window for the kernels' arithmetic: the
+    rounding of q (AMB_ETA of the magnitude of its terms) plus that of the
+    splat centre, which the kernels form in float32 relative to the tile's
+    centre, so within half a tile of every pixel centre they evaluate."""
+    return {"eta": AMB_ETA, "pos_h": settings.tile / 2}
+
+
 def log(msg: str) -> None:
     print(msg, flush=True)
     sys.stdout.flush()

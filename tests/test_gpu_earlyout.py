@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import wsr_synth as ws
-from tests.gpu_helpers import (AMB_ETA, compare_grads, compare_image, densest_crop, gpu_forward, grads_to_numpy,
+from tests.gpu_helpers import (amb_kw, compare_grads, compare_image, densest_crop, gpu_forward, grads_to_numpy,
                                log, to_views)
 from tests.test_gpu_parity import _check_globals, _grad_keys, _oracle_globals
 
@@ -27,7 +27,7 @@ def test_c2_early_out_image(c2):
     log("case: c2 early-out image")
     st_cut = st.copy(alpha_cut=CUT)
     ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st_cut)
-    ref = oracle.render(sc, cams[0], st_cut, mode="aabb", eta=AMB_ETA)
+    ref = oracle.render(sc, cams[0], st_cut, mode="aabb", **amb_kw(st_cut))
     compare_image(to_views(ctx, rgb)[0], ref, label="c2 early-out")
     ctx0, _, _, (rgb0, _) = gpu_forward(sc, cams, st)
     log(f"early-out: {ctx.last_pairs} binned pairs vs {ctx0.last_pairs} exact; image max-abs vs exact "
@@ -58,5 +58,5 @@ def test_c1_early_out_culls_faint_gaussians():
     st_cut = st.copy(alpha_cut=0.5)
     log("case: c1 high threshold")
     ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st_cut)
-    ref = oracle.render(sc, cams[0], st_cut, eta=AMB_ETA)
+    ref = oracle.render(sc, cams[0], st_cut, **amb_kw(st_cut))
     compare_image(to_views(ctx, rgb)[0], ref, label="c1 alpha_cut 0.5")

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import wsr_synth as ws
-from tests.gpu_helpers import (AMB_ETA, compare_grads, compare_image, densest_crop, gpu_forward, grads_to_numpy,
+from tests.gpu_helpers import (amb_kw, compare_grads, compare_image, densest_crop, gpu_forward, grads_to_numpy,
                                log, to_views)
 from tests.test_gpu_parity import _check_globals, _grad_keys, _oracle_globals
 
@@ -19,7 +19,7 @@ def test_c1_oit_image_and_gradients():
     st = st.copy(oit=True)
     log("case: c1 OIT")
     ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st)
-    ref = oracle.render(sc, cams[0], st, eta=AMB_ETA)
+    ref = oracle.render(sc, cams[0], st, **amb_kw(st))
     compare_image(to_views(ctx, rgb)[0], ref, label="c1 OIT")
     r = np.random.default_rng(3).standard_normal((128, 128, 3)).astype(np.float32)
     gg = grads_to_numpy(ctx.render_bwd(dev, g, torch.from_numpy(r.reshape(-1, 3)).cuda(), rgb, den))
@@ -36,7 +36,7 @@ def test_c2_oit_gradients_on_crop():
     log("case: c2 OIT gradients on a crop")
     ctx, dev, g, (rgb, den, cnt) = gpu_forward(sc, cams, st, count=True)
     x0, y0, x1, y1 = crop = densest_crop(to_views(ctx, cnt)[0])
-    ref = oracle.render(sc, cams[0], st, crop=crop, eta=AMB_ETA)
+    ref = oracle.render(sc, cams[0], st, crop=crop, **amb_kw(st))
     compare_image(to_views(ctx, rgb)[0][y0:y1, x0:x1], ref, label="c2 OIT crop")
     r = np.zeros((720, 1280, 3), np.float32)
     r[y0:y1, x0:x1] = np.random.default_rng(8).standard_normal((y1 - y0, x1 - x0, 3))
@@ -60,5 +60,5 @@ def test_headline_oit_split_tiles():
     log(f"headline OIT: binned pairs {tiles_pairs}, densest crop {crop}")
     for c in (crop, (928, 508, 992, 572)):
         x0, y0, x1, y1 = c
-        ref = oracle.render(sc, cams[0], st, crop=c, eta=AMB_ETA)
+        ref = oracle.render(sc, cams[0], st, crop=c, **amb_kw(st))
         compare_image(C[y0:y1, x0:x1], ref, label=f"headline OIT {c}")

@@ -9,7 +9,7 @@ import torch
 import oracle
 import wsr_synth as ws
 from paper_2410_18931_amd import WSRContext, globals_tensor, render, scene_to_device
-from tests.gpu_helpers import (AMB_ETA, compare_grads, compare_image, densest_crop, gpu_forward,
+from tests.gpu_helpers import (amb_kw, compare_grads, compare_image, densest_crop, gpu_forward,
                                grads_to_numpy, log, to_views)
 from tests.oracle_helpers import empty_like
 
@@ -76,7 +76,7 @@ def test_c1_image_and_counts(c1, tile):
     st = st.copy(tile=tile)
     log(f"case: c1 image tile={tile}")
     ctx, dev, g, (rgb, den, cnt) = gpu_forward(sc, cams, st, count=True)
-    ref = oracle.render(sc, cams[0], st, eta=AMB_ETA)
+    ref = oracle.render(sc, cams[0], st, **amb_kw(st))
     C = to_views(ctx, rgb)[0]
     compare_image(C, ref, label=f"c1 t{tile}")
     D = to_views(ctx, den)[0]
@@ -141,7 +141,7 @@ def test_c2_image_full_frame(c2):
     sc, cams, st = c2
     log("case: c2 full-frame image")
     ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st)
-    ref = oracle.render(sc, cams[0], st, mode="aabb", eta=AMB_ETA)
+    ref = oracle.render(sc, cams[0], st, mode="aabb", **amb_kw(st))
     compare_image(to_views(ctx, rgb)[0], ref, label="c2")
 
 
@@ -167,7 +167,7 @@ def test_c2_reduced_precision_storage(c2):
         q = ws.quantise(sc, dt)
         ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st, storage=dt)
         crop = (600, 320, 664, 384)
-        ref = oracle.render(q["f32"], cams[0], st, crop=crop, eta=AMB_ETA)
+        ref = oracle.render(q["f32"], cams[0], st, crop=crop, **amb_kw(st))
         C = to_views(ctx, rgb)[0][320:384, 600:664]
         compare_image(C, ref, label=f"c2 {dt} vs dequantised")
         src = oracle.render(sc, cams[0], st, crop=crop)
@@ -196,7 +196,7 @@ def test_1080p_crops(config):
     crops = [densest_crop(counts), (0, 0, 64, 64), (1856, 1016, 1920, 1080), (928, 508, 992, 572)]
     for crop in crops:
         x0, y0, x1, y1 = crop
-        ref = oracle.render(sc, cams[0], st, crop=crop, eta=AMB_ETA)
+        ref = oracle.render(sc, cams[0], st, crop=crop, **amb_kw(st))
         compare_image(C[y0:y1, x0:x1], ref, label=f"{config} {crop}")
     if config == "c3":
         x0, y0, x1, y1 = crops[0]
@@ -222,7 +222,7 @@ def test_multi_view_uneven_sizes():
     imgs = to_views(ctx, rgb)
     rs = ws.upstream_grad(cams, seed=8)
     for v, cam in enumerate(cams):
-        compare_image(imgs[v], oracle.render(sc, cam, st, mode="aabb", eta=AMB_ETA), label=f"view {v}")
+        compare_image(imgs[v], oracle.render(sc, cam, st, mode="aabb", **amb_kw(st)), label=f"view {v}")
     dL = torch.cat([torch.from_numpy(r.reshape(-1, 3)) for r in rs]).cuda()
     gg = grads_to_numpy(ctx.render_bwd(dev, g, dL, rgb, den))
     gref = oracle.render_bwd_views(sc, cams, st, rs)
@@ -257,7 +257,7 @@ def test_zero_background_weight_and_uncovered_pixels():
     st = st.copy(w_bg=0.0)
     log("case: w_B = 0")
     ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st)
-    ref = oracle.render(sc, cams[0], st, eta=AMB_ETA)
+    ref = oracle.render(sc, cams[0], st, **amb_kw(st))
     assert np.any(ref["den"] == 0)
     C = to_views(ctx, rgb)[0]
     compare_image(C, ref, label="w_B=0")
@@ -277,7 +277,7 @@ def test_ragged_image_and_single_gaussian():
         for tile in (8, 16, 32):
             log(f"case: single Gaussian {w}x{h} tile {tile}")
             ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st.copy(tile=tile))
-            compare_image(to_views(ctx, rgb)[0], oracle.render(sc, cams[0], st, eta=AMB_ETA), label=f"{w}x{h}")
+            compare_image(to_views(ctx, rgb)[0], oracle.render(sc, cams[0], st, **amb_kw(st)), label=f"{w}x{h}")
 
 
 def test_huge_and_degenerate_splats():
@@ -287,7 +287,7 @@ def test_huge_and_degenerate_splats():
     sc["log_scales"][:, 2] = [-30.0, -30.0, -30.0]  # vanishing: only the dilation remains
     log("case: huge / degenerate splats")
     ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st)
-    ref = oracle.render(sc, cams[0], st, eta=AMB_ETA)
+    ref = oracle.render(sc, cams[0], st, **amb_kw(st))
     compare_image(to_views(ctx, rgb)[0], ref, label="huge+degenerate")
     r = ws.upstream_grad(cams, seed=1)[0]
     gg = grads_to_numpy(ctx.render_bwd(dev, g, torch.from_numpy(r.reshape(-1, 3)).cuda(), rgb, den))
@@ -312,7 +312,7 @@ def test_capacity_overflow_is_reported_then_recovered():
     ctx.bin(grow=True)
     ctx.check()
     rgb, den = ctx.render_fwd(g)
-    compare_image(to_views(ctx, rgb)[0], oracle.render(sc, cams[0], st, eta=AMB_ETA), label="after regrow")
+    compare_image(to_views(ctx, rgb)[0], oracle.render(sc, cams[0], st, **amb_kw(st)), label="after regrow")
 
 
 # ---------------------------------------------------------------- graphs and autotuning
@@ -455,7 +455,7 @@ def test_reduced_precision_batched_errors(dt):
         crop = densest_crop(counts[v], 48)
         crops.append(crop)
         x0, y0, x1, y1 = crop
-        compare_image(imgs[v][y0:y1, x0:x1], oracle.render(q["f32"], cam, st, crop=crop, eta=AMB_ETA),
+        compare_image(imgs[v][y0:y1, x0:x1], oracle.render(q["f32"], cam, st, crop=crop, **amb_kw(st)),
                       label=f"{dt} view {v} vs dequantised")
         src = oracle.render(sc, cam, st, crop=crop)
         worst_src = max(worst_src, float(np.abs(imgs[v][y0:y1, x0:x1] - src["C"]).max()))

@@ -9,7 +9,7 @@ import torch
 import oracle
 import wsr_synth as ws
 from paper_2410_18931_amd import WSRContext, _lib, globals_tensor, scene_to_device
-from tests.gpu_helpers import AMB_ETA, IMG_TOL, densest_crop, log, to_views
+from tests.gpu_helpers import amb_kw, IMG_TOL, densest_crop, log, to_views
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def test_c1_sorted_full_frame(blend):
     st = st.copy(weight_kind="dir")
     log(f"case: c1 sorted {blend}")
     ctx, rgb, T = _sorted_gpu(sc, cams, st, **blend)
-    ref = oracle.render_sorted(sc, cams[0], st, eta=AMB_ETA, **blend)
+    ref = oracle.render_sorted(sc, cams[0], st, **amb_kw(st), **blend)
     _compare(to_views(ctx, rgb)[0], to_views(ctx, T)[0], ref, "c1")
 
 
@@ -61,7 +61,7 @@ def test_c2_sorted_densest_crop():
     x0, y0, x1, y1 = densest_crop(to_views(ctx0, cnt)[0])
     del ctx0
     ctx, rgb, T = _sorted_gpu(sc, cams, st)
-    ref = oracle.render_sorted(sc, cams[0], st, crop=(x0, y0, x1, y1), eta=AMB_ETA)
+    ref = oracle.render_sorted(sc, cams[0], st, crop=(x0, y0, x1, y1), **amb_kw(st))
     _compare(to_views(ctx, rgb)[0][y0:y1, x0:x1], to_views(ctx, T)[0][y0:y1, x0:x1], ref, "c2 crop")
 
 
@@ -72,7 +72,7 @@ def test_sorted_multi_view_uneven_sizes():
     log("case: sorted two views")
     ctx, rgb, T = _sorted_gpu(sc, cams, st)
     for v, cam in enumerate(cams):
-        ref = oracle.render_sorted(sc, cam, st, eta=AMB_ETA)
+        ref = oracle.render_sorted(sc, cam, st, **amb_kw(st))
         _compare(to_views(ctx, rgb)[v], to_views(ctx, T)[v], ref, f"view {v}")
 
 

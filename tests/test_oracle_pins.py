@@ -332,6 +332,22 @@ def test_strict_and_aabb_modes_agree(c1):
     assert np.array_equal(a["count"], b["count"])
 
 
+def test_ambiguity_window_widens_only_the_report(c1):
+    """The centre-rounding term of the ambiguity report (pos_h) only widens
+    the set of pairs reported near the cutoff; the image is unchanged, and
+    pos_h = 0 gives the plain window."""
+    sc, cams, st = c1
+    a = oracle.render(sc, cams[0], st, eta=1e-6)
+    b = oracle.render(sc, cams[0], st, eta=1e-6, pos_h=0.0)
+    c = oracle.render(sc, cams[0], st, eta=1e-6, pos_h=8.0)
+    assert np.array_equal(a["amb"], b["amb"]) and np.array_equal(a["C"], c["C"])
+    assert (c["amb"] >= a["amb"]).all() and (c["amb_c"] >= a["amb_c"]).all()
+    assert (oracle.render(sc, cams[0], st, eta=1e-6, pos_h=1e5)["amb"] > a["amb"]).any()
+    s0 = oracle.render_sorted(sc, cams[0], st.copy(weight_kind="dir"), eta=1e-6)
+    s1 = oracle.render_sorted(sc, cams[0], st.copy(weight_kind="dir"), eta=1e-6, pos_h=8.0)
+    assert np.array_equal(s0["C"], s1["C"]) and (s1["amb"] >= s0["amb"]).all()
+
+
 def test_crop_is_window_of_full_image(c1):
     sc, cams, st = c1
     full = oracle.render(sc, cams[0], st)["C"]
