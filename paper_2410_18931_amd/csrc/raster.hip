@@ -59,8 +59,9 @@ constexpr float kTwoLn2 = 1.38629436111989061f;     // its inverse
 // The support predicate and the Gaussian falloff.  Forward and backward
 // evaluate q with exactly this sequence of float operations (the backward
 // hoists the row-constant products B2*dy and (C*dy)*dy, which does not change
-// their values), so both take the same support decision for every pair,
-// whatever the tile size.
+// their values), so both take the same support decision for every pair.
+// Different tile sizes round the tile-relative centre differently, so they
+// can disagree on a pair within that rounding of the cutoff.
 __device__ __forceinline__ float quad_form(float A, float B2dy, float Cdy2, float dx) {
   return fmaf(fmaf(A, dx, B2dy), dx, Cdy2);
 }

@@ -88,14 +88,24 @@ def test_c1_image_and_counts(c1, tile):
 
 
 def test_c1_tile_size_invariance(c1):
+    """Tiles 8, 16 and 32 evaluate the same expression per pair; only the
+    float32 rounding of the tile-relative centre differs, so the images agree
+    to 1e-6 except where a pair lies within that rounding of the cutoff (the
+    checker's ambiguity report for the largest tile bounds those pixels)."""
     sc, cams, st = c1
     imgs = []
     for tile in (8, 16, 32):
         log(f"case: c1 tile invariance tile={tile}")
         ctx, dev, g, (rgb, den) = gpu_forward(sc, cams, st.copy(tile=tile))
-        imgs.append(rgb.cpu().numpy())
-    assert np.abs(imgs[0] - imgs[1]).max() <= 1e-6
-    assert np.abs(imgs[0] - imgs[2]).max() <= 1e-6
+        imgs.append(rgb.cpu().numpy().reshape(cams[0]["height"], cams[0]["width"], 3))
+    ref = oracle.render(sc, cams[0], st, **amb_kw(st.copy(tile=32)))
+    den = np.abs(ref["den"])
+    bound = 1e-6 + 4.0 * ref["amb_c"] / np.where(den == 0, 1.0, den)
+    for other in (imgs[1], imgs[2]):
+        diff = np.abs(imgs[0] - other).max(axis=-1)
+        log(f"tile invariance: max diff {diff.max():.3g}, ambiguous px {int((ref['amb_c'] > 0).sum())}")
+        assert (diff <= bound).all()
+        assert diff[ref["amb_c"] == 0].max() <= 1e-6
 
 
 def test_c1_gradients(c1):
