@@ -537,6 +537,86 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
   out[8][l] = g_amp;
 }
 
+// A short chunk (at most 64 / K splats, K = 2, 4 or 8), which would leave
+// most lanes of bwd_chunk idle: K lanes share a splat, lane group g walking
+// rows [g 8/K, (g+1) 8/K) of the block, and the groups' sums are added with
+// cross-lane shuffles in a fixed order.  The groups visit different pixels
+// at the same time, so the per-pixel factors come from this wave's copy in
+// LDS (s_pd, 64 entries) instead of scalar loads.  The arithmetic per pixel
+// is that of bwd_chunk.
+template <int T, bool CUT, int K>
+__device__ __forceinline__ void bwd_chunk_split(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
+                                                const StagedRec* s_rec, const float4* s_pd, float (*out)[kWave],
+                                                float tau) {
+  constexpr int S = kWave / K;  // splats per chunk
+  constexpr int R = 8 / K;      // rows per lane group
+  const int g = c.lane / S;
+  const int slot = c.lane % S;
+  const int j = c0 + slot;
+  const bool valid = j < m;
+  const int kr = valid ? list[j] : 0;
+  const StagedRec r = s_rec[kr];
+  const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
+  float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+  float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
+  const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
+  const float cut = CUT ? r.r2.y : tau;
+  const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
+  const float ey0 = static_cast<float>(c.by0 - c.fy0 + g * R) + 0.5f;  // first row of this group
+  const float4* pd_rows = s_pd + g * R * 8;
+#pragma unroll
+  for (int row = 0; row < R; ++row) {
+    const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
+    const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
+    float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+#pragma unroll
+    for (int col = 0; col < 8; ++col) {
+      const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
+      const float q = quad_form(A, B2dy, Cdy2, dx);
+      const float4 pd = pd_rows[row * 8 + col];
+      const float Gq = (valid && q <= cut) ? falloff(q) : 0.f;
+      const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
+      const float e = Gq * dLda;
+      S0 += e;
+      S1 = fmaf(e, dx, S1);
+      S2 = fmaf(e, dx * dx, S2);
+      g_r = fmaf(Gq, pd.x, g_r);
+      g_g = fmaf(Gq, pd.y, g_g);
+      g_b = fmaf(Gq, pd.z, g_b);
+    }
+    g_amp += S0;
+    Mx += S1;
+    My = fmaf(dy, S0, My);
+    Mxx += S2;
+    Mxy = fmaf(dy, S1, Mxy);
+    Myy = fmaf(dy * dy, S0, Myy);
+  }
+#pragma unroll
+  for (int d = S; d < kWave; d <<= 1) {
+    Mx += __shfl_xor(Mx, d, kWave);
+    My += __shfl_xor(My, d, kWave);
+    Mxx += __shfl_xor(Mxx, d, kWave);
+    Mxy += __shfl_xor(Mxy, d, kWave);
+    Myy += __shfl_xor(Myy, d, kWave);
+    g_r += __shfl_xor(g_r, d, kWave);
+    g_g += __shfl_xor(g_g, d, kWave);
+    g_b += __shfl_xor(g_b, d, kWave);
+    g_amp += __shfl_xor(g_amp, d, kWave);
+  }
+  if (g == 0) {
+    const float ampc = amp * kTwoLn2;
+    out[0][slot] = ampc * (A * Mx + 0.5f * B2 * My);
+    out[1][slot] = ampc * (0.5f * B2 * Mx + Cc * My);
+    out[2][slot] = -0.5f * amp * Mxx;
+    out[3][slot] = -amp * Mxy;
+    out[4][slot] = -0.5f * amp * Myy;
+    out[5][slot] = amp * g_r;
+    out[6][slot] = amp * g_g;
+    out[7][slot] = amp * g_b;
+    out[8][slot] = g_amp;
+  }
+}
+
 // The OIT chunk (Eq. 2): as bwd_chunk, plus the coverage term.  A layer's
 // opacity alpha = u G (clamped to [0, 1], no gradient where clamped) gets
 // dL/dalpha = -k / (1 - alpha) with k from the prepass, so per pixel
@@ -677,9 +757,19 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterA
   }
 }
 
+// Tile 16 asks the compiler for five resident waves per SIMD (at most 102
+// VGPRs): the short-chunk path would otherwise raise the register count and
+// cost a wave.
+template <int T>
+constexpr int bwd_min_blocks() {
+  return T == 16 ? 5 : 1;
+}
+
 // Backward: the same staging and per-wave culling as the forward, but lanes
 // own splats of the wave's culled list and walk the wave's pixel block (see
-// bwd_chunk), so a splat's nine gradient sums stay in registers.
+// bwd_chunk), so a splat's nine gradient sums stay in registers.  A chunk of
+// at most 32 splats (the tail of a wave's list) shares each splat among 2, 4
+// or 8 lanes instead (bwd_chunk_split); Eq. 2 keeps one lane per splat.
 //
 // The waves of a tile merge their sums without atomics.  Thread k owns
 // staged record k.  The waves process their chunks in lockstep rounds (one
@@ -692,9 +782,8 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterA
 // run to run (the order in which a record's per-wave sums are added follows
 // the rounds that reach them, i.e. the list positions).
 template <int T, bool CUT, bool OIT>
-__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(RasterArgs a,
-                                                                           const float4* __restrict__ pdg,
-                                                                           const float* __restrict__ pdk) {
+__global__ __launch_bounds__(TileGeom<T>::kThreads, bwd_min_blocks<T>()) void raster_bwd_kernel(
+    RasterArgs a, const float4* __restrict__ pdg, const float* __restrict__ pdk) {
   using G = TileGeom<T>;
   constexpr int kB = G::kBatch;
   constexpr int NV = OIT ? 10 : 9;  // sums per (tile, splat) pair
@@ -705,13 +794,16 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
   __shared__ float s_part[G::kWaves][NV][kWave];
   __shared__ float s_u[OIT ? kB : 1];
   __shared__ int s_m[G::kWaves];
+  __shared__ float4 s_pd[OIT ? 1 : G::kThreads];  // per-pixel factors, thread order
   TileCtx<T> c;
   const DevCamera* cam;
   if (!tile_setup<T>(a, c, cam)) return;
 
-  // this wave's 64 per-pixel factors (wave-uniform base address)
+  // this wave's 64 per-pixel factors (wave-uniform base address), and a copy
+  // in LDS for the short chunks (made visible by the first staging barrier)
   const int wave_u = __builtin_amdgcn_readfirstlane(c.wave);
   const float4* __restrict__ pd_wave = pdg + (c.tile * G::kWaves + wave_u) * kWave;
+  if (!OIT) s_pd[threadIdx.x] = pd_wave[c.lane];
   const float* __restrict__ pk_wave = OIT ? pdk + (c.tile * G::kWaves + wave_u) * kWave : nullptr;
   const float tau = a.tau;
   const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
@@ -728,11 +820,21 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_kernel(Raste
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.f;
     for (int r = 0; r < rounds; ++r) {
-      if (r * kWave < m) {
-        if (OIT)
+      const int left = m - r * kWave;  // splats in this wave's chunk of the round
+      if (left > 0) {
+        if (OIT) {
           bwd_chunk_oit<T>(c, r * kWave, m, list, s_rec, s_u, pd_wave, pk_wave, s_part[c.wave], tau);
-        else
-          bwd_chunk<T, CUT>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
+        } else {
+          const float4* pdl = s_pd + c.wave * kWave;
+          if (left > kWave / 2)
+            bwd_chunk<T, CUT>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
+          else if (left > kWave / 4)
+            bwd_chunk_split<T, CUT, 2>(c, r * kWave, m, list, s_rec, pdl, s_part[c.wave], tau);
+          else if (left > kWave / 8)
+            bwd_chunk_split<T, CUT, 4>(c, r * kWave, m, list, s_rec, pdl, s_part[c.wave], tau);
+          else
+            bwd_chunk_split<T, CUT, 8>(c, r * kWave, m, list, s_rec, pdl, s_part[c.wave], tau);
+        }
       }
       __syncthreads();
       if (own < cnt) {
