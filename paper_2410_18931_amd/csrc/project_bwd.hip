@@ -299,7 +299,17 @@ __global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, c
   const bool heavy = s1 - s0 > kHeavySlots;
   float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (!heavy) {
+    // four slots per step keep twelve loads in flight per lane
     uint32_t j = s0;
+    for (; j + 4 <= s1; j += 4) {
+      const float3* p = part + 3 * static_cast<int64_t>(j);
+      const float3 x0 = p[0], x1 = p[1], x2 = p[2], y0 = p[3], y1 = p[4], y2 = p[5];
+      const float3 z0 = p[6], z1 = p[7], z2 = p[8], w0 = p[9], w1 = p[10], w2 = p[11];
+      add3(g, 0, x0); add3(g, 3, x1); add3(g, 6, x2);
+      add3(g, 0, y0); add3(g, 3, y1); add3(g, 6, y2);
+      add3(g, 0, z0); add3(g, 3, z1); add3(g, 6, z2);
+      add3(g, 0, w0); add3(g, 3, w1); add3(g, 6, w2);
+    }
     for (; j + 2 <= s1; j += 2) {
       const float3* p = part + 3 * static_cast<int64_t>(j);
       const float3 x0 = p[0], x1 = p[1], x2 = p[2], y0 = p[3], y1 = p[4], y2 = p[5];
@@ -360,10 +370,13 @@ __global__ __launch_bounds__(1024) void reduce_globals(const double* gpart, int6
                                                        const float* tilepart, int64_t ntiles, float* out) {
   __shared__ double sh[16][6];
   double acc[6] = {0, 0, 0, 0, 0, 0};
+  // unrolled so that a thread's loads are in flight together
+#pragma unroll 8
   for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
     acc[0] += gpart[2 * b];
     acc[1] += gpart[2 * b + 1];
   }
+#pragma unroll 8
   for (int64_t t = threadIdx.x; t < ntiles; t += 1024) {
     acc[3] += tilepart[4 * t];
     acc[4] += tilepart[4 * t + 1];
