@@ -42,10 +42,10 @@ BWD_FLOPS_PER_PAIR = 48
 # (`--calibrate-copy`).  Valid only for the kernel source and the workload it
 # was measured on.
 TRAFFIC = {
-    "raster_bwd": {"source": "raster.hip", "source_sha": "885065a8da579bc9",
+    "raster_bwd": {"source": "raster.hip", "source_sha": "1895f09600362a74",
                    "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 0.0},
-                   "fetch_kib": 544630.8, "write_kib": 492382.2,
-                   "fetch_factor": 262157.7 / 524288.0, "write_factor": 524288.0 / 524288.0},
+                   "fetch_kib": 554256.7, "write_kib": 492314.1,
+                   "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
 }
 
 
