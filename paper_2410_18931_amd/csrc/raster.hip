@@ -84,8 +84,9 @@ __device__ __forceinline__ float2 rec_extent(const StagedRec& r) {
 }
 
 // Does the splat's support reach the wave block whose pixel centres span
-// [bx, bx + sub1] x [by, by + sub1] (relative to the tile's centre)?  First the (conservative) support box;
-// then, unless the conic is badly conditioned, the exact minimum of q over
+// [bx, bx + sub1] x [by, by + sub1] (relative to the tile's centre)?  First
+// the (conservative) support box; then, unless the conic is badly
+// conditioned, the exact minimum of q over
 // the block (the unconstrained minimum is the centre; otherwise the minimum
 // lies on an edge, at the clamped 1D minimiser of that edge) against tau with
 // a margin far above the float error of q.  For needle-like splats
@@ -106,7 +107,7 @@ __device__ __forceinline__ bool block_hits(const StagedRec& r, float bx, float b
     const float A = r.r0.z, B = 0.5f * r.r0.w, C = r.r1.x;
     const float bb = B * B;
     const float det = fmaf(A, C, -bb) - fmaf(B, B, -bb);
-    const float s = det > 0.f ? tau / det : __builtin_inff();
+    const float s = det > 0.f ? tau * __builtin_amdgcn_rcpf(det) : __builtin_inff();
     e = make_float2(sqrtf(s * C) * 1.0001f, sqrtf(s * A) * 1.0001f);
   } else {
     e = rec_extent(r);
@@ -123,7 +124,9 @@ __device__ __forceinline__ bool block_hits(const StagedRec& r, float bx, float b
   const float x0 = bx - mx, x1 = (bx + sub1) - mx;
   const float y0 = by - my, y1 = (by + sub1) - my;
   if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
-  const float iA = 1.f / A, iC = 1.f / C;
+  // hardware reciprocals (within 1 ulp): they only place the edge minimisers,
+  // whose error changes q there by a second-order amount far inside the margin
+  const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
   float qmin = 3.0e38f;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -652,7 +655,8 @@ __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m
       const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
       const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
       const float al = u * Gq;
-      const float dLdal = (al > 0.f && al < 1.f) ? -k / (1.f - al) : 0.f;
+      // hardware reciprocal (within 1 ulp) instead of an IEEE division
+      const float dLdal = (al > 0.f && al < 1.f) ? -k * __builtin_amdgcn_rcpf(1.f - al) : 0.f;
       const float e = Gq * fmaf(amp, dLda, u * dLdal);
       S0 += e;
       S1 = fmaf(e, dx, S1);
