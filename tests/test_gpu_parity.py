@@ -290,6 +290,46 @@ def test_ragged_image_and_single_gaussian():
             compare_image(to_views(ctx, rgb)[0], oracle.render(sc, cams[0], st, **amb_kw(st)), label=f"{w}x{h}")
 
 
+@pytest.mark.parametrize("count", [1, 5, 8, 9, 16, 17, 32, 33, 64, 65, 100])
+def test_one_block_lists_of_every_length(count):
+    """count small splats inside the first 8x8 pixel block of a 32x32 view:
+    that wave's culled list has exactly count entries, so the backward's last
+    chunk takes each of its shapes (8, 4, 2 lanes per splat for tails of at
+    most 8, 16, 32 splats, one lane above) and 65 and 100 add a full chunk."""
+    from tests.oracle_helpers import dc_for_colour, scene_from
+    rng = np.random.default_rng(1000 + count)
+    cam = ws.look_at_camera((0.0, 0.0, -4.0), 32, 32)
+    V = np.asarray(cam["viewmat"])
+    R, Tv = V[:, :3], V[:, 3]
+    px = rng.uniform(2.5, 5.5, (count, 2))
+    pc = np.stack([(px[:, 0] - cam["cx"]) * 4.0 / cam["fx"], (px[:, 1] - cam["cy"]) * 4.0 / cam["fy"],
+                   np.full(count, 4.0)], axis=1)
+    means = (pc - Tv) @ R  # world positions (R is a rotation)
+    sh = np.zeros((1, count, 4))
+    sh[0, :, :3] = dc_for_colour(rng.uniform(0.05, 0.95, (count, 3)))
+    quats = rng.normal(size=(4, count))
+    sc = scene_from(means, log_scales=rng.uniform(-4.3, -3.7, (3, count)), quats=quats, sh=sh,
+                    logit=rng.normal(0.0, 1.0, count), dtype=np.float32)
+    st = ws.Settings()
+    cams = [cam]
+    p = oracle.project(sc, cam, st)
+    assert p["visible"].all()
+    log(f"case: one-block lists, {count} splats")
+    ctx, dev, g, (rgb, den, cnt) = gpu_forward(sc, cams, st, count=True)
+    compare_image(to_views(ctx, rgb)[0], oracle.render(sc, cam, st, **amb_kw(st)), label=f"{count} splats")
+    counts = to_views(ctx, cnt)[0]
+    assert counts[8:].sum() == 0 and counts[:, 8:].sum() == 0  # every pair lies in the first block
+    r = rng.standard_normal((32, 32, 3)).astype(np.float32)
+    grad2d = torch.zeros((1, ctx.n, 9), dtype=torch.float32, device="cuda")
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, torch.from_numpy(r.reshape(-1, 3)).cuda(), rgb, den,
+                                       grad2d=grad2d))
+    gref = oracle.render_bwd(sc, cam, st, r)
+    compare_grads(gg, gref, _grad_keys(st, 1), label=f"{count} splats")
+    compare_grads({"grad2d": grad2d[0].cpu().numpy()}, {"grad2d": gref["grad2d"]}, ["grad2d"],
+                  label=f"{count} splats 2d")
+    _check_globals(gg["globals"], _oracle_globals(st, gref["globals"]), f"{count} splats")
+
+
 def test_huge_and_degenerate_splats():
     sc, cams, st = ws.make_scene("c1", n=50)
     sc["log_scales"][:, 0] = 1.0          # covers the whole image
