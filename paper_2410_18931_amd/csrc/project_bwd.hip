@@ -46,19 +46,27 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
   const int64_t n = a.n;
   double gsig = 0.0, gbeta = 0.0;
   if (i < n) {
-    const double p0 = load_attr<S>(a.means, i);
-    const double p1 = load_attr<S>(a.means, n + i);
-    const double p2 = load_attr<S>(a.means, 2 * n + i);
+    // Every load of the attributes and of the first view's 2D gradient is
+    // issued before any arithmetic (the scheduling barrier keeps them
+    // together), so each thread pays one memory round trip up front.
+    const float m0 = load_attr<S>(a.means, i), m1 = load_attr<S>(a.means, n + i),
+                m2 = load_attr<S>(a.means, 2 * n + i);
     const float rq[4] = {load_attr<S>(a.quats, i), load_attr<S>(a.quats, n + i),
                          load_attr<S>(a.quats, 2 * n + i), load_attr<S>(a.quats, 3 * n + i)};
-    QuatScale qs;
-    const Sigma3 S3 = make_sigma3(rq[0], rq[1], rq[2], rq[3], load_attr<S>(a.log_scales, i),
-                                  load_attr<S>(a.log_scales, n + i), load_attr<S>(a.log_scales, 2 * n + i), &qs);
+    const float l0 = load_attr<S>(a.log_scales, i), l1 = load_attr<S>(a.log_scales, n + i),
+                l2 = load_attr<S>(a.log_scales, 2 * n + i);
     float4 coef[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) coef[k] = load_attr4<S>(a.sh, k * n + i);
     const float logit = a.opa_mode == WSR_OPACITY_LOGIT ? a.logit[i] : 0.f;
     const float lcv = a.weight_kind == WSR_WEIGHT_LC ? a.lc_v[i] : 0.f;
+    float gv0[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) gv0[j] = a.grad2d[i * 9 + j];
+    __builtin_amdgcn_sched_barrier(0);
+    const double p0 = m0, p1 = m1, p2 = m2;
+    QuatScale qs;
+    const Sigma3 S3 = make_sigma3(rq[0], rq[1], rq[2], rq[3], l0, l1, l2, &qs);
     const double sigma = a.globals[0], beta = a.globals[1];
 
     double dp[3] = {0.0, 0.0, 0.0};
@@ -72,7 +80,7 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
       const float* g2 = a.grad2d + (static_cast<int64_t>(v) * n + i) * 9;
       float gv[9];
 #pragma unroll
-      for (int j = 0; j < 9; ++j) gv[j] = g2[j];
+      for (int j = 0; j < 9; ++j) gv[j] = v == 0 ? gv0[j] : g2[j];
       const float du_cov = a.du2d ? a.du2d[static_cast<int64_t>(v) * n + i] : 0.f;
       bool nz = du_cov != 0.f;
 #pragma unroll
