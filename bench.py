@@ -42,9 +42,9 @@ BWD_FLOPS_PER_PAIR = 48
 # (`--calibrate-copy`).  Valid only for the kernel source and the workload it
 # was measured on.
 TRAFFIC = {
-    "raster_bwd": {"source": "raster.hip", "source_sha": "1895f09600362a74",
+    "raster_bwd": {"source": "raster.hip", "source_sha": "068234f07705e6e4",
                    "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 0.0},
-                   "fetch_kib": 554256.7, "write_kib": 492314.1,
+                   "fetch_kib": 552677.9, "write_kib": 492363.2,
                    "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
 }
 
