@@ -42,7 +42,7 @@ BWD_FLOPS_PER_PAIR = 48
 # (`--calibrate-copy`).  Valid only for the kernel source and the workload it
 # was measured on.
 TRAFFIC = {
-    "raster_bwd": {"source": "raster.hip", "source_sha": "068234f07705e6e4",
+    "raster_bwd": {"source": "raster.hip", "source_sha": "ede7a33b7b4c140d",
                    "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 0.0},
                    "fetch_kib": 552677.9, "write_kib": 492363.2,
                    "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},

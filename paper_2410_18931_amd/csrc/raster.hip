@@ -6,14 +6,16 @@
 //   backward: per pixel gbar = dL/dC / D and s = gbar . C; per pair
 //             dL/da = gbar . c_i - s, then the chain to (mu, conic, c, amp).
 //
-// One workgroup per (view, tile).  Each wave owns a square block of the tile
-// (8x8 pixels for tiles 8 and 16, 16x16 for tile 32).  Per batch the group
-// stages splat records into LDS; each wave then keeps only the splats whose
-// support box meets its own block (wave ballot + compaction into an LDS
-// list), and every lane evaluates its pixel(s) against that list with FP32
-// register accumulation.  The sums are commutative, so the list order does
-// not matter, and no per-pair data is stored between forward and backward:
-// the backward recomputes every pair.
+// One workgroup per work item (at most 1024 splats of one tile's list).
+// Each wave owns an 8x8 pixel block of the tile.  Per batch the group stages
+// splat records into LDS; each wave then keeps only the splats whose support
+// reaches its own block (support box, then the exact minimum of q over the
+// block; wave ballot + compaction into an LDS list).  In the forward every
+// lane evaluates its pixel against that list with FP32 register
+// accumulation; in the backward every lane takes one splat of the list and
+// walks the block.  The sums are commutative, so the list order does not
+// matter, and no per-pair data is stored between forward and backward: the
+// backward recomputes every pair.
 #include <type_traits>
 
 #include "wsr_internal.h"
@@ -30,7 +32,7 @@ struct TileGeom {
   static constexpr int kWaves = (T / 8) * (T / 8);
   static constexpr int kThreads = kWaves * kWave;
   static constexpr int kBatch = kThreads < 256 ? kThreads : 256;
-  static_assert(kBatch <= 256, "culled lists hold 8-bit record indices");
+  static_assert(kBatch <= 256, "the backward's lists hold 8-bit record indices");
 };
 
 // A record as staged in LDS for one tile (48 bytes; stage_and_cull builds it
