@@ -688,6 +688,87 @@ __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m
   out[9][l] = g_u;
 }
 
+// bwd_chunk_oit for a short chunk, with K lanes per splat as in
+// bwd_chunk_split (per-pixel factors and coverage factors from LDS).
+template <int T, int K>
+__device__ __forceinline__ void bwd_chunk_oit_split(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
+                                                    const StagedRec* s_rec, const float* s_u, const float4* s_pd,
+                                                    const float* s_pk, float (*out)[kWave], float tau) {
+  constexpr int S = kWave / K;  // splats per chunk
+  constexpr int R = 8 / K;      // rows per lane group
+  const int g = c.lane / S;
+  const int slot = c.lane % S;
+  const int j = c0 + slot;
+  const bool valid = j < m;
+  const int kr = valid ? list[j] : 0;
+  const StagedRec r = s_rec[kr];
+  const float u = s_u[kr];
+  const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
+  float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+  float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f, g_u = 0.f;
+  const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
+  const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
+  const float ey0 = static_cast<float>(c.by0 - c.fy0 + g * R) + 0.5f;  // first row of this group
+  const float4* pd_rows = s_pd + g * R * 8;
+  const float* pk_rows = s_pk + g * R * 8;
+#pragma unroll
+  for (int row = 0; row < R; ++row) {
+    const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
+    const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
+    float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+#pragma unroll
+    for (int col = 0; col < 8; ++col) {
+      const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
+      const float q = quad_form(A, B2dy, Cdy2, dx);
+      const float4 pd = pd_rows[row * 8 + col];
+      const float k = pk_rows[row * 8 + col];
+      const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
+      const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
+      const float al = u * Gq;
+      const float dLdal = (al > 0.f && al < 1.f) ? -k * __builtin_amdgcn_rcpf(1.f - al) : 0.f;
+      const float e = Gq * fmaf(amp, dLda, u * dLdal);
+      S0 += e;
+      S1 = fmaf(e, dx, S1);
+      S2 = fmaf(e, dx * dx, S2);
+      g_r = fmaf(Gq, pd.x, g_r);
+      g_g = fmaf(Gq, pd.y, g_g);
+      g_b = fmaf(Gq, pd.z, g_b);
+      g_amp = fmaf(Gq, dLda, g_amp);
+      g_u = fmaf(Gq, dLdal, g_u);
+    }
+    Mx += S1;
+    My = fmaf(dy, S0, My);
+    Mxx += S2;
+    Mxy = fmaf(dy, S1, Mxy);
+    Myy = fmaf(dy * dy, S0, Myy);
+  }
+#pragma unroll
+  for (int d = S; d < kWave; d <<= 1) {
+    Mx += __shfl_xor(Mx, d, kWave);
+    My += __shfl_xor(My, d, kWave);
+    Mxx += __shfl_xor(Mxx, d, kWave);
+    Mxy += __shfl_xor(Mxy, d, kWave);
+    Myy += __shfl_xor(Myy, d, kWave);
+    g_r += __shfl_xor(g_r, d, kWave);
+    g_g += __shfl_xor(g_g, d, kWave);
+    g_b += __shfl_xor(g_b, d, kWave);
+    g_amp += __shfl_xor(g_amp, d, kWave);
+    g_u += __shfl_xor(g_u, d, kWave);
+  }
+  if (g == 0) {
+    out[0][slot] = kTwoLn2 * (A * Mx + 0.5f * B2 * My);  // staged conic scaled by log2(e) / 2
+    out[1][slot] = kTwoLn2 * (0.5f * B2 * Mx + Cc * My);
+    out[2][slot] = -0.5f * Mxx;
+    out[3][slot] = -Mxy;
+    out[4][slot] = -0.5f * Myy;
+    out[5][slot] = amp * g_r;
+    out[6][slot] = amp * g_g;
+    out[7][slot] = amp * g_b;
+    out[8][slot] = g_amp;
+    out[9][slot] = g_u;
+  }
+}
+
 // Backward prepass, one workgroup per tile: the per-pixel factors
 // gbar = dL/dC / D and s = gbar . C (zero outside the image), stored padded to
 // whole tiles in the order the raster backward walks them
@@ -765,17 +846,17 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterA
 
 // Tile 16 asks the compiler for five resident waves per SIMD (at most 102
 // VGPRs): the short-chunk path would otherwise raise the register count and
-// cost a wave.
-template <int T>
+// cost a wave.  With Eq. 2 the LDS already limits a CU to four workgroups.
+template <int T, bool OIT>
 constexpr int bwd_min_blocks() {
-  return T == 16 ? 5 : 1;
+  return T == 16 && !OIT ? 5 : 1;
 }
 
 // Backward: the same staging and per-wave culling as the forward, but lanes
 // own splats of the wave's culled list and walk the wave's pixel block (see
 // bwd_chunk), so a splat's nine gradient sums stay in registers.  A chunk of
 // at most 32 splats (the tail of a wave's list) shares each splat among 2, 4
-// or 8 lanes instead (bwd_chunk_split); Eq. 2 keeps one lane per splat.
+// or 8 lanes instead (bwd_chunk_split, bwd_chunk_oit_split).
 //
 // The waves of a tile merge their sums without atomics.  Thread k owns
 // staged record k.  The waves process their chunks in lockstep rounds (one
@@ -788,7 +869,7 @@ constexpr int bwd_min_blocks() {
 // run to run (the order in which a record's per-wave sums are added follows
 // the rounds that reach them, i.e. the list positions).
 template <int T, bool CUT, bool OIT>
-__global__ __launch_bounds__(TileGeom<T>::kThreads, bwd_min_blocks<T>()) void raster_bwd_kernel(
+__global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) void raster_bwd_kernel(
     RasterArgs a, const float4* __restrict__ pdg, const float* __restrict__ pdk) {
   using G = TileGeom<T>;
   constexpr int kB = G::kBatch;
@@ -800,7 +881,8 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, bwd_min_blocks<T>()) void ra
   __shared__ float s_part[G::kWaves][NV][kWave];
   __shared__ float s_u[OIT ? kB : 1];
   __shared__ int s_m[G::kWaves];
-  __shared__ float4 s_pd[OIT ? 1 : G::kThreads];  // per-pixel factors, thread order
+  __shared__ float4 s_pd[G::kThreads];            // per-pixel factors, thread order
+  __shared__ float s_pk[OIT ? G::kThreads : 1];   // OIT: per-pixel coverage factors
   TileCtx<T> c;
   const DevCamera* cam;
   if (!tile_setup<T>(a, c, cam)) return;
@@ -809,8 +891,9 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, bwd_min_blocks<T>()) void ra
   // in LDS for the short chunks (made visible by the first staging barrier)
   const int wave_u = __builtin_amdgcn_readfirstlane(c.wave);
   const float4* __restrict__ pd_wave = pdg + (c.tile * G::kWaves + wave_u) * kWave;
-  if (!OIT) s_pd[threadIdx.x] = pd_wave[c.lane];
   const float* __restrict__ pk_wave = OIT ? pdk + (c.tile * G::kWaves + wave_u) * kWave : nullptr;
+  s_pd[threadIdx.x] = pd_wave[c.lane];
+  if (OIT) s_pk[threadIdx.x] = pk_wave[c.lane];
   const float tau = a.tau;
   const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
   for (uint32_t b = c.start; b < c.end; b += kB) {
@@ -828,10 +911,18 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, bwd_min_blocks<T>()) void ra
     for (int r = 0; r < rounds; ++r) {
       const int left = m - r * kWave;  // splats in this wave's chunk of the round
       if (left > 0) {
+        const float4* pdl = s_pd + c.wave * kWave;
         if (OIT) {
-          bwd_chunk_oit<T>(c, r * kWave, m, list, s_rec, s_u, pd_wave, pk_wave, s_part[c.wave], tau);
+          const float* pkl = s_pk + c.wave * kWave;
+          if (left > kWave / 2)
+            bwd_chunk_oit<T>(c, r * kWave, m, list, s_rec, s_u, pd_wave, pk_wave, s_part[c.wave], tau);
+          else if (left > kWave / 4)
+            bwd_chunk_oit_split<T, 2>(c, r * kWave, m, list, s_rec, s_u, pdl, pkl, s_part[c.wave], tau);
+          else if (left > kWave / 8)
+            bwd_chunk_oit_split<T, 4>(c, r * kWave, m, list, s_rec, s_u, pdl, pkl, s_part[c.wave], tau);
+          else
+            bwd_chunk_oit_split<T, 8>(c, r * kWave, m, list, s_rec, s_u, pdl, pkl, s_part[c.wave], tau);
         } else {
-          const float4* pdl = s_pd + c.wave * kWave;
           if (left > kWave / 2)
             bwd_chunk<T, CUT>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
           else if (left > kWave / 4)
