@@ -76,11 +76,9 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   L->off_gpart = off;    off = align256(off + sizeof(double) * 2 * L->gpart_blocks);
   L->off_items = off;    off = align256(off + sizeof(uint32_t) * (tiles + 1));
   L->off_acc = off;      off = align256(off + sizeof(float) * 4 * pixels);
-  L->off_pd = off;       off = align256(off + sizeof(float) * 4 * tiles * tile * tile);
   L->off_oit = off;      off = align256(off + sizeof(float) * 4 * pixels);
   L->off_acclog = off;   off = align256(off + sizeof(float) * pixels);
   L->off_du2d = off;     off = align256(off + sizeof(float) * (slots > 0 ? slots : 1));
-  L->off_pdk = off;      off = align256(off + sizeof(float) * tiles * tile * tile);
   L->bytes = off;
   return true;
 }

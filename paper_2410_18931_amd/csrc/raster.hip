@@ -168,11 +168,9 @@ struct RasterArgs {
   int64_t total_tiles;
   float* acc;
   // OIT (Eq. 2): per pixel (weighted average, coverage P) from the forward,
-  // the split-tile accumulator of ln P, the prepass's per-pixel coverage
-  // factor and the per-pair partial dL/du
+  // the split-tile accumulator of ln P and the per-pair partial dL/du
   float4* oit;
   float* acclog;
-  float* pdk;
   float* du;
 };
 
@@ -478,11 +476,10 @@ __device__ __forceinline__ float wave_sum(float x) {
 // lane's nine partial 2D gradient sums are written to out[j][lane].
 //
 // All lanes walk the same pixel at the same time, so the per-pixel factors
-// (gbar, s) from the prepass (raster_bwd_prep) are read with scalar loads at
-// a wave-uniform address and enter the FMAs as scalar operands.
+// (gbar, s) are read from LDS at a wave-uniform address (a broadcast).
 template <int T, bool CUT>
 __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
-                                          const StagedRec* s_rec, const float4* __restrict__ pd_wave,
+                                          const StagedRec* s_rec, const float4* pd_wave,
                                           float (*out)[kWave], float tau) {
   const int j = c0 + c.lane;
   const bool valid = j < m;
@@ -506,7 +503,7 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
     for (int col = 0; col < 8; ++col) {
       const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
       const float q = quad_form(A, B2dy, Cdy2, dx);
-      const float4 pd = pd_wave[row * 8 + col];  // wave-uniform: SGPRs
+      const float4 pd = pd_wave[row * 8 + col];  // wave-uniform LDS address: a broadcast read
       const float Gq = (valid && q <= cut) ? falloff(q) : 0.f;
       const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
       const float e = Gq * dLda;
@@ -624,13 +621,13 @@ __device__ __forceinline__ void bwd_chunk_split(const TileCtx<T>& c, int c0, int
 
 // The OIT chunk (Eq. 2): as bwd_chunk, plus the coverage term.  A layer's
 // opacity alpha = u G (clamped to [0, 1], no gradient where clamped) gets
-// dL/dalpha = -k / (1 - alpha) with k from the prepass, so per pixel
+// dL/dalpha = -k / (1 - alpha) with k from pixel_factors, so per pixel
 // dq = -G (amp dL/da + u dL/dalpha) / 2, and the tenth output is
 // dL/du = sum G dL/dalpha.  The moments therefore carry the amplitude.
 template <int T>
 __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
                                               const StagedRec* s_rec, const float* s_u,
-                                              const float4* __restrict__ pd_wave, const float* __restrict__ pk_wave,
+                                              const float4* pd_wave, const float* pk_wave,
                                               float (*out)[kWave], float tau) {
   const int j = c0 + c.lane;
   const bool valid = j < m;
@@ -652,7 +649,7 @@ __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m
     for (int col = 0; col < 8; ++col) {
       const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
       const float q = quad_form(A, B2dy, Cdy2, dx);
-      const float4 pd = pd_wave[row * 8 + col];  // wave-uniform: SGPRs
+      const float4 pd = pd_wave[row * 8 + col];  // wave-uniform LDS address: a broadcast read
       const float k = pk_wave[row * 8 + col];
       const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
       const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
@@ -769,32 +766,22 @@ __device__ __forceinline__ void bwd_chunk_oit_split(const TileCtx<T>& c, int c0,
   }
 }
 
-// Backward prepass, one workgroup per tile: the per-pixel factors
-// gbar = dL/dC / D and s = gbar . C (zero outside the image), stored padded to
-// whole tiles in the order the raster backward walks them
-// ([tile][wave block][row * 8 + col], i.e. thread order), and the tile's
-// partial sums of the background gradients dL/dc_B and dL/dw_B.
+// The backward's per-pixel factors for pixel (px, py) of view `cam`:
+// gbar = dL/dC / D and s = gbar . C (zero outside the image), and the pixel's
+// share of the background gradients dL/dc_B (rgb) and dL/dw_B.
 //
 // OIT (Eq. 2, C = P c_B + (1 - P) N / D): gbar = dL/dC (1 - P) / D and
 // s = gbar . (N / D), so that dL/da = gbar . c - s as for Eq. 7, and the
 // coverage factor k = P dL/dC . (c_B - N / D), so that a layer's opacity
 // alpha gets dL/dalpha = -k / (1 - alpha); dL/dc_B = P dL/dC, dL/dw_B = 0.
-template <int T, bool OIT>
-__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterArgs a, float4* pdg) {
-  using G = TileGeom<T>;
-  __shared__ float s_bg[G::kWaves][4];
-  const int tile = static_cast<int>(blockIdx.x);
-  const int v = find_view(a.cams, a.nv, tile);
-  const DevCamera& cam = a.cams[v];
-  const int local = tile - cam.tile_base;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int px = (local % cam.tiles_x) * T + (wave % (T / 8)) * 8 + (lane & 7);
-  const int py = (local / cam.tiles_x) * T + (wave / (T / 8)) * 8 + (lane >> 3);
+template <bool OIT>
+__device__ __forceinline__ void pixel_factors(const RasterArgs& a, const DevCamera& cam, int px, int py,
+                                              float4* pd_o, float* kcov_o, float* bacc) {
   const float wbg = a.globals[2];
   const float bgr = a.globals[3], bgg = a.globals[4], bgb = a.globals[5];
-  float bacc[4] = {0.f, 0.f, 0.f, 0.f};  // dL/dc_B (rgb), dL/dw_B
   float4 pd = make_float4(0.f, 0.f, 0.f, 0.f);
   float kcov = 0.f;
+  bacc[0] = bacc[1] = bacc[2] = bacc[3] = 0.f;
   if (px < cam.width && py < cam.height) {
     const int64_t pix = cam.pix_base + static_cast<int64_t>(py) * cam.width + px;
     const float D = a.den[pix];
@@ -828,20 +815,8 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_bwd_prep(RasterA
       bacc[2] = g2;
     }
   }
-  pdg[static_cast<int64_t>(tile) * G::kThreads + threadIdx.x] = pd;
-  if (OIT) a.pdk[static_cast<int64_t>(tile) * G::kThreads + threadIdx.x] = kcov;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const float sj = wave_sum(bacc[j]);
-    if (lane == 0) s_bg[wave][j] = sj;
-  }
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    float sj = 0.f;
-#pragma unroll
-    for (int w = 0; w < G::kWaves; ++w) sj += s_bg[w][threadIdx.x];
-    a.tilepart[tile * 4 + threadIdx.x] = sj;
-  }
+  *pd_o = pd;
+  *kcov_o = kcov;
 }
 
 // Tile 16 asks the compiler for five resident waves per SIMD (at most 102
@@ -852,11 +827,14 @@ constexpr int bwd_min_blocks() {
   return T == 16 && !OIT ? 5 : 1;
 }
 
-// Backward: the same staging and per-wave culling as the forward, but lanes
-// own splats of the wave's culled list and walk the wave's pixel block (see
-// bwd_chunk), so a splat's nine gradient sums stay in registers.  A chunk of
-// at most 32 splats (the tail of a wave's list) shares each splat among 2, 4
-// or 8 lanes instead (bwd_chunk_split, bwd_chunk_oit_split).
+// Backward: each thread first forms its pixel's factors (pixel_factors)
+// into LDS; the tile's first work item also stores the tile's
+// background-gradient partial sums.  Then the same staging and per-wave
+// culling as the forward, but lanes own splats of the wave's culled list and
+// walk the wave's pixel block (see bwd_chunk), so a splat's nine gradient
+// sums stay in registers.  A chunk of at most 32 splats (the tail of a
+// wave's list) shares each splat among 2, 4 or 8 lanes instead
+// (bwd_chunk_split, bwd_chunk_oit_split).
 //
 // The waves of a tile merge their sums without atomics.  Thread k owns
 // staged record k.  The waves process their chunks in lockstep rounds (one
@@ -870,7 +848,7 @@ constexpr int bwd_min_blocks() {
 // the rounds that reach them, i.e. the list positions).
 template <int T, bool CUT, bool OIT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) void raster_bwd_kernel(
-    RasterArgs a, const float4* __restrict__ pdg, const float* __restrict__ pdk) {
+    RasterArgs a) {
   using G = TileGeom<T>;
   constexpr int kB = G::kBatch;
   constexpr int NV = OIT ? 10 : 9;  // sums per (tile, splat) pair
@@ -883,17 +861,37 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
   __shared__ int s_m[G::kWaves];
   __shared__ float4 s_pd[G::kThreads];            // per-pixel factors, thread order
   __shared__ float s_pk[OIT ? G::kThreads : 1];   // OIT: per-pixel coverage factors
+  __shared__ float s_bg[G::kWaves][4];
   TileCtx<T> c;
   const DevCamera* cam;
   if (!tile_setup<T>(a, c, cam)) return;
 
-  // this wave's 64 per-pixel factors (wave-uniform base address), and a copy
-  // in LDS for the short chunks (made visible by the first staging barrier)
-  const int wave_u = __builtin_amdgcn_readfirstlane(c.wave);
-  const float4* __restrict__ pd_wave = pdg + (c.tile * G::kWaves + wave_u) * kWave;
-  const float* __restrict__ pk_wave = OIT ? pdk + (c.tile * G::kWaves + wave_u) * kWave : nullptr;
-  s_pd[threadIdx.x] = pd_wave[c.lane];
-  if (OIT) s_pk[threadIdx.x] = pk_wave[c.lane];
+  // every thread's per-pixel factors into LDS, where the chunks read them at
+  // wave-uniform (broadcast) or per-lane addresses; the tile's first work
+  // item also stores the tile's background-gradient partial sums
+  {
+    float4 pd;
+    float kcov, bacc[4];
+    pixel_factors<OIT>(a, *cam, c.px, c.py, &pd, &kcov, bacc);
+    s_pd[threadIdx.x] = pd;
+    if (OIT) s_pk[threadIdx.x] = kcov;
+    if (c.k == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float sj = wave_sum(bacc[j]);
+        if (c.lane == 0) s_bg[c.wave][j] = sj;
+      }
+      __syncthreads();
+      if (threadIdx.x < 4) {
+        float sj = 0.f;
+#pragma unroll
+        for (int w = 0; w < G::kWaves; ++w) sj += s_bg[w][threadIdx.x];
+        a.tilepart[c.tile * 4 + threadIdx.x] = sj;
+      }
+    }
+  }
+  const float4* pd_wave = s_pd + c.wave * kWave;
+  const float* pk_wave = OIT ? s_pk + c.wave * kWave : nullptr;
   const float tau = a.tau;
   const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
   for (uint32_t b = c.start; b < c.end; b += kB) {
@@ -911,9 +909,9 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
     for (int r = 0; r < rounds; ++r) {
       const int left = m - r * kWave;  // splats in this wave's chunk of the round
       if (left > 0) {
-        const float4* pdl = s_pd + c.wave * kWave;
+        const float4* pdl = pd_wave;
         if (OIT) {
-          const float* pkl = s_pk + c.wave * kWave;
+          const float* pkl = pk_wave;
           if (left > kWave / 2)
             bwd_chunk_oit<T>(c, r * kWave, m, list, s_rec, s_u, pd_wave, pk_wave, s_part[c.wave], tau);
           else if (left > kWave / 4)
@@ -1105,7 +1103,6 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   a.acc = at<float>(ws, L.off_acc);
   a.oit = at<float4>(ws, L.off_oit);
   a.acclog = at<float>(ws, L.off_acclog);
-  a.pdk = at<float>(ws, L.off_pdk);
   a.du = pv.du;
   return a;
 }
@@ -1135,19 +1132,15 @@ hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, bool count, b
 }
 
 template <int T>
-hipError_t bwd_t(const RasterArgs& a, float4* pd, int64_t grid, int64_t tiles, bool cut, bool oit, hipStream_t st) {
-  const dim3 gt(static_cast<unsigned>(tiles)), gi(static_cast<unsigned>(grid));
+hipError_t bwd_t(const RasterArgs& a, int64_t grid, bool cut, bool oit, hipStream_t st) {
+  const dim3 gi(static_cast<unsigned>(grid));
   constexpr int kT = TileGeom<T>::kThreads;
-  if (oit) {
-    raster_bwd_prep<T, true><<<gt, kT, 0, st>>>(a, pd);
-    raster_bwd_kernel<T, false, true><<<gi, kT, 0, st>>>(a, pd, a.pdk);
-  } else {
-    raster_bwd_prep<T, false><<<gt, kT, 0, st>>>(a, pd);
-    if (cut)
-      raster_bwd_kernel<T, true, false><<<gi, kT, 0, st>>>(a, pd, a.pdk);
-    else
-      raster_bwd_kernel<T, false, false><<<gi, kT, 0, st>>>(a, pd, a.pdk);
-  }
+  if (oit)
+    raster_bwd_kernel<T, false, true><<<gi, kT, 0, st>>>(a);
+  else if (cut)
+    raster_bwd_kernel<T, true, false><<<gi, kT, 0, st>>>(a);
+  else
+    raster_bwd_kernel<T, false, false><<<gi, kT, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -1185,12 +1178,11 @@ hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t cap
   a.den = den;
   a.tilepart = at<float>(ws, L.off_tilepart);
   const int64_t grid = max_raster_items(L, capacity);
-  float4* pd = at<float4>(ws, L.off_pd);
   const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
   switch (L.tile) {
-    case 8: return bwd_t<8>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, oit, st);
-    case 32: return bwd_t<32>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, oit, st);
-    default: return bwd_t<16>(a, pd, grid, L.total_tiles, P->alpha_cut > 0.f, oit, st);
+    case 8: return bwd_t<8>(a, grid, P->alpha_cut > 0.f, oit, st);
+    case 32: return bwd_t<32>(a, grid, P->alpha_cut > 0.f, oit, st);
+    default: return bwd_t<16>(a, grid, P->alpha_cut > 0.f, oit, st);
   }
 }
 
