@@ -42,9 +42,9 @@ BWD_FLOPS_PER_PAIR = 48
 # (`--calibrate-copy`).  Valid only for the kernel source and the workload it
 # was measured on.
 TRAFFIC = {
-    "raster_bwd": {"source": "raster.hip", "source_sha": "ede7a33b7b4c140d",
+    "raster_bwd": {"source": "raster.hip", "source_sha": "db5e5a01f8ab9d90",
                    "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 0.0},
-                   "fetch_kib": 552677.9, "write_kib": 492363.2,
+                   "fetch_kib": 515535.2, "write_kib": 529781.6,
                    "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
 }
 
