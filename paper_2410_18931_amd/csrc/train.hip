@@ -201,6 +201,8 @@ __global__ __launch_bounds__(256) void loss_pass2(LossArgs a, LossViews lv) {
 __global__ __launch_bounds__(256) void loss_finalize(const double* part, int64_t n, float* loss) {
   __shared__ double s_red[4];
   double s = 0.0;
+  // unrolled so that a thread's loads are in flight together (same order of additions)
+#pragma unroll 8
   for (int64_t k = threadIdx.x; k < n; k += 256) s += part[k];
   s = block_sum_256(s, s_red);
   if (threadIdx.x == 0) *loss = static_cast<float>(s);
