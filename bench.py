@@ -31,9 +31,18 @@ if ROOT not in sys.path:
 METRIC = "fwd+bwd frames/s and Gaussian-pixel evals/s at 1M splats 1080p; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# algorithmic FP32 work per in-support (pixel, Gaussian) pair
+# algorithmic FP32 work per in-support (pixel, Gaussian) pair: Eq. 7, and
+# weighted-blended OIT (Eq. 2), which adds the coverage product
 FWD_FLOPS_PER_PAIR = 20
 BWD_FLOPS_PER_PAIR = 48
+FWD_FLOPS_PER_PAIR_OIT = 23
+BWD_FLOPS_PER_PAIR_OIT = 56
+
+
+def flops_per_pair(kernel: str, oit: bool) -> int:
+    if kernel == "raster_fwd":
+        return FWD_FLOPS_PER_PAIR_OIT if oit else FWD_FLOPS_PER_PAIR
+    return BWD_FLOPS_PER_PAIR_OIT if oit else BWD_FLOPS_PER_PAIR
 
 
 # HBM traffic of the dominant kernel, from `rocprofv3 --pmc FETCH_SIZE` and
@@ -41,12 +50,20 @@ BWD_FLOPS_PER_PAIR = 48
 # what the same counter reads for a plain device copy of known size
 # (`--calibrate-copy`).  Valid only for the kernel source and the workload it
 # was measured on.
-TRAFFIC = {
-    "raster_bwd": {"source": "raster.hip", "source_sha": "db5e5a01f8ab9d90",
-                   "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 0.0},
-                   "fetch_kib": 515535.2, "write_kib": 529781.6,
-                   "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
-}
+TRAFFIC = [
+    {"kernel": "raster_bwd", "source": "raster.hip", "source_sha": "db5e5a01f8ab9d90",
+     "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 0.0},
+     "fetch_kib": 515535.2, "write_kib": 529781.6,
+     "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
+    {"kernel": "raster_bwd", "source": "raster.hip", "source_sha": "db5e5a01f8ab9d90",
+     "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": True, "alpha_cut": 0.0},
+     "fetch_kib": 484746.3, "write_kib": 740417.9,
+     "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
+    {"kernel": "raster_bwd", "source": "raster.hip", "source_sha": "db5e5a01f8ab9d90",
+     "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 1.0 / 255.0},
+     "fetch_kib": 473302.6, "write_kib": 485379.1,
+     "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
+]
 
 
 def _source_sha(name: str) -> str:
@@ -56,12 +73,13 @@ def _source_sha(name: str) -> str:
 
 
 def traffic_bytes(kernel: str, args) -> float | None:
-    t = TRAFFIC.get(kernel)
-    if not t or t["source_sha"] != _source_sha(t["source"]):
-        return None
-    if any(getattr(args, k) != v for k, v in t["workload"].items()):
-        return None
-    return t["fetch_kib"] * 1024 / t["fetch_factor"] + t["write_kib"] * 1024 / t["write_factor"]
+    for t in TRAFFIC:
+        if t["kernel"] != kernel or t["source_sha"] != _source_sha(t["source"]):
+            continue
+        if any(getattr(args, k) != v for k, v in t["workload"].items()):
+            continue
+        return t["fetch_kib"] * 1024 / t["fetch_factor"] + t["write_kib"] * 1024 / t["write_factor"]
+    return None
 
 
 def calibrate_copy(mb: int, reps: int = 5) -> None:
@@ -404,7 +422,8 @@ def main():
     fps = 1e3 / ms * ctx.nv      # views rendered (fwd+bwd) per second
     ab = algorithmic_bytes(n, P, args.storage, binned)
     dominant = max(("raster_fwd", "raster_bwd"), key=lambda s: stage_ms[s])
-    flops = pairs * (FWD_FLOPS_PER_PAIR if dominant == "raster_fwd" else BWD_FLOPS_PER_PAIR)
+    fpp = flops_per_pair(dominant, args.oit)
+    flops = pairs * fpp
     achieved = flops / (stage_ms[dominant] * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": round(fps, 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
@@ -430,7 +449,7 @@ def main():
                      "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": traffic_bytes(dominant, args),
-                     "flops_per_pair": FWD_FLOPS_PER_PAIR if dominant == "raster_fwd" else BWD_FLOPS_PER_PAIR,
+                     "flops_per_pair": fpp,
                      "launch_ms": round(stage_ms[dominant], 4), "algorithmic_bytes": ab[dominant]},
         "stage_hbm_gbs": {k: round(ab[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in names},
     }

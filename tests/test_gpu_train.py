@@ -49,16 +49,23 @@ def test_loss_of_identical_images_is_zero():
     assert dL.abs().max().item() < 1e-8
 
 
-@pytest.mark.parametrize("n", [1, 1000, 257 * 256 + 3])
-def test_adam_matches_reference(n):
-    log(f"case: adam n={n}")
+@pytest.mark.parametrize("n,offset", [(1, 0), (1000, 0), (257 * 256 + 3, 0), (1 << 20, 0), (5000, 1),
+                                      (300_001, 2)])
+def test_adam_matches_reference(n, offset):
+    """Short and long arrays, and views that start off the 16-byte boundary."""
+    log(f"case: adam n={n} offset={offset}")
     rng = np.random.default_rng(n)
     p = rng.standard_normal(n).astype(np.float32)
-    pd, md, vd = [torch.from_numpy(x).cuda() for x in (p.copy(), np.zeros(n, np.float32), np.zeros(n, np.float32))]
+
+    def dev(x):
+        buf = torch.zeros(n + offset, dtype=torch.float32, device="cuda")
+        buf[offset:] = torch.from_numpy(x).cuda()
+        return buf[offset:]
+    pd, md, vd = dev(p.copy()), dev(np.zeros(n, np.float32)), dev(np.zeros(n, np.float32))
     pr, mr, vr = p.astype(np.float64), np.zeros(n), np.zeros(n)
     for step in range(1, 4):
         g = rng.standard_normal(n).astype(np.float32)
-        adam_(pd, torch.from_numpy(g).cuda(), md, vd, step, 0.01)
+        adam_(pd, dev(g), md, vd, step, 0.01)
         # the entry point takes float32 hyperparameters: the reference uses
         # the same rounded values (0.999f differs from 0.999 by 1.3e-8)
         f32 = lambda x: float(np.float32(x))  # noqa: E731
