@@ -284,6 +284,8 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
 // slot.  A lane sums the range of its own Gaussian when it is short; a long
 // range (a splat covering many tiles) is summed by the whole wave, lanes
 // striding through it, so the largest splats do not form a serial tail.
+// With OIT (DU) the same pass also sums each pair's dL/du through the
+// coverage term, which the raster stores in an array of its own.
 constexpr uint32_t kHeavySlots = 32;
 
 __device__ __forceinline__ void add3(float* g, int o, const float3 v) {
@@ -292,8 +294,10 @@ __device__ __forceinline__ void add3(float* g, int o, const float3 v) {
   g[o + 2] += v.z;
 }
 
-__global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, const float3* part, uint32_t capacity,
-                                                         int64_t slots, float* grad2d, float* out_grad2d) {
+template <bool DU>
+__global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, const float3* part, const float* du,
+                                                         uint32_t capacity, int64_t slots, float* grad2d,
+                                                         float* out_grad2d, float* du2d) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   const int lane = threadIdx.x % kWave;
   uint32_t s0 = 0, s1 = 0;
@@ -306,6 +310,7 @@ __global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, c
   }
   const bool heavy = s1 - s0 > kHeavySlots;
   float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float gu = 0.f;
   if (!heavy) {
     // four slots per step keep twelve loads in flight per lane
     uint32_t j = s0;
@@ -317,16 +322,29 @@ __global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, c
       add3(g, 0, y0); add3(g, 3, y1); add3(g, 6, y2);
       add3(g, 0, z0); add3(g, 3, z1); add3(g, 6, z2);
       add3(g, 0, w0); add3(g, 3, w1); add3(g, 6, w2);
+      if (DU) {
+        const float u0 = du[j], u1 = du[j + 1], u2 = du[j + 2], u3 = du[j + 3];
+        gu += u0;
+        gu += u1;
+        gu += u2;
+        gu += u3;
+      }
     }
     for (; j + 2 <= s1; j += 2) {
       const float3* p = part + 3 * static_cast<int64_t>(j);
       const float3 x0 = p[0], x1 = p[1], x2 = p[2], y0 = p[3], y1 = p[4], y2 = p[5];
       add3(g, 0, x0); add3(g, 3, x1); add3(g, 6, x2);
       add3(g, 0, y0); add3(g, 3, y1); add3(g, 6, y2);
+      if (DU) {
+        const float u0 = du[j], u1 = du[j + 1];
+        gu += u0;
+        gu += u1;
+      }
     }
     if (j < s1) {
       const float3* p = part + 3 * static_cast<int64_t>(j);
       add3(g, 0, p[0]); add3(g, 3, p[1]); add3(g, 6, p[2]);
+      if (DU) gu += du[j];
     }
   }
   // the wave sums its heavy Gaussians one after another
@@ -335,17 +353,21 @@ __global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, c
     const int src = __ffsll(static_cast<long long>(hmask)) - 1;
     hmask &= hmask - 1;
     const uint32_t h0 = __shfl(s0, src, kWave), h1 = __shfl(s1, src, kWave);
-    float w[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float w[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (uint32_t j = h0 + lane; j < h1; j += kWave) {
       const float3* p = part + 3 * static_cast<int64_t>(j);
       add3(w, 0, p[0]); add3(w, 3, p[1]); add3(w, 6, p[2]);
+      if (DU) w[9] += du[j];
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
+    for (int q = 0; q < (DU ? 10 : 9); ++q) {
       float x = w[q];
 #pragma unroll
       for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
-      if (lane == src) g[q] = x;
+      if (lane == src) {
+        if (q < 9) g[q] = x;
+        else gu = x;
+      }
     }
   }
   if (k >= slots) return;
@@ -356,20 +378,7 @@ __global__ __launch_bounds__(256) void sum_pair_partials(const uint32_t* goff, c
 #pragma unroll
     for (int q = 0; q < 9; ++q) out_grad2d[9 * k + q] = g[q];
   }
-}
-
-// OIT: each (view, Gaussian)'s dL/du through the coverage term, summed over
-// its contiguous range of pair slots.
-__global__ __launch_bounds__(256) void sum_pair_du(const uint32_t* goff, const float* du, uint32_t capacity,
-                                                   int64_t slots, float* du2d) {
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (k >= slots) return;
-  uint32_t s0 = goff[k], s1 = goff[k + 1];
-  s0 = s0 < capacity ? s0 : capacity;
-  s1 = s1 < capacity ? s1 : capacity;
-  float t = 0.f;
-  for (uint32_t j = s0; j < s1; ++j) t += du[j];
-  du2d[k] = t;
+  if (DU) du2d[k] = gu;
 }
 
 // Final reduction of the global parameters: dL/dsigma, dL/dbeta from the
@@ -445,16 +454,18 @@ hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const fl
   if (L.n > 0) {
     const PairView pv = pair_view(pairs, capacity);
     const int64_t slots = L.n * L.nv;
-    sum_pair_partials<<<static_cast<unsigned>((slots + 255) / 256), 256, 0, st>>>(
-        at<uint32_t>(ws, L.off_goff), pv.part, static_cast<uint32_t>(capacity), slots, at<float>(ws, L.off_grad2d),
-        out_grad2d);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
-    if (oit) {
-      sum_pair_du<<<static_cast<unsigned>((slots + 255) / 256), 256, 0, st>>>(
-          at<uint32_t>(ws, L.off_goff), pv.du, static_cast<uint32_t>(capacity), slots, at<float>(ws, L.off_du2d));
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    const unsigned sblocks = static_cast<unsigned>((slots + 255) / 256);
+    if (oit)
+      sum_pair_partials<true><<<sblocks, 256, 0, st>>>(at<uint32_t>(ws, L.off_goff), pv.part, pv.du,
+                                                       static_cast<uint32_t>(capacity), slots,
+                                                       at<float>(ws, L.off_grad2d), out_grad2d,
+                                                       at<float>(ws, L.off_du2d));
+    else
+      sum_pair_partials<false><<<sblocks, 256, 0, st>>>(at<uint32_t>(ws, L.off_goff), pv.part, nullptr,
+                                                        static_cast<uint32_t>(capacity), slots,
+                                                        at<float>(ws, L.off_grad2d), out_grad2d, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     BwdArgs a;
     a.means = sc->means;
     a.log_scales = sc->log_scales;

@@ -40,9 +40,9 @@ struct TileGeom {
 //   r0 = (mx, my, A, B2)   centre relative to the tile's centre; conic
 //                          (A, B2 = 2B, C) times log2(e) / 2
 //   r1 = (C, amp, c0, c1)  colour (times amp in the forward)
-//   r2 = (c2, ext | cut, 0, 0)  support half-extents (two halves), or with
+//   r2 = (c2, ext | cut, u, 0)  support half-extents (two halves), or with
 //                          the early-out the record's own cutoff times
-//                          log2(e) / 2
+//                          log2(e) / 2; u = the opacity, used by OIT only
 // The tile-relative centre is (integer origin - tile centre) + fractional
 // centre: the difference is exact, the sum rounds once (to within 2^-24 of
 // its magnitude, which is at most the pixel's distance plus half the tile
@@ -250,7 +250,7 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
 template <int T, int BATCH, bool SLOTS, bool CUT, bool OIT, bool PREMUL, typename LT>
 __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
                                               StagedRec* s_rec, uint32_t* s_slot, LT* s_list,
-                                              uint16_t* s_pos, float* s_u = nullptr) {
+                                              uint16_t* s_pos) {
   using G = TileGeom<T>;
   const float tox = static_cast<float>(c.fx0), toy = static_cast<float>(c.fy0);
   __syncthreads();  // previous batch fully consumed
@@ -270,9 +270,9 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
       r.r0 = make_float4((s.r1.y - tox) + s.r0.x, (s.r1.z - toy) + s.r0.y, s.r0.z * kHalfLog2e,
                          s.r0.w * kHalfLog2e);
       r.r1 = make_float4(s.r1.x * kHalfLog2e, amp, c0, c1);
-      r.r2 = make_float4(c2, CUT ? s.r2.w * kHalfLog2e : s.r2.w, 0.f, 0.f);
+      // OIT: the opacity u rides in the record's third word
+      r.r2 = make_float4(c2, CUT ? s.r2.w * kHalfLog2e : s.r2.w, OIT ? __uint_as_float(d->slot.w) : 0.f, 0.f);
       s_rec[q] = r;
-      if (OIT) s_u[q] = __uint_as_float(d->slot.w);  // the opacity u
       if (SLOTS) {
         const uint4 sl = d->slot;
         const uint32_t rx0 = sl.y & 0xffffu, rw = (sl.y >> 16) - rx0, ry0 = sl.z & 0xffffu;
@@ -344,15 +344,13 @@ __device__ __forceinline__ const StagedRec& rec_at(const StagedRec* base, uint32
   return *reinterpret_cast<const StagedRec*>(reinterpret_cast<const char*>(base) + off);
 }
 
-// Forward.  Lists hold LDS byte offsets of the staged records, except with
-// OIT, whose coverage term needs the record index for the opacity.
+// Forward.  Lists hold LDS byte offsets of the staged records.
 template <int T, bool COUNT, bool CUT, bool OIT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
-  using LT = typename std::conditional<OIT, uint8_t, uint32_t>::type;
+  using LT = uint32_t;
   __shared__ StagedRec s_rec[G::kBatch];
   __shared__ __align__(16) LT s_list[G::kWaves * G::kBatch];
-  __shared__ float s_u[OIT ? G::kBatch : 1];
   TileCtx<T> c;
   const DevCamera* cam;
   if (!tile_setup<T>(a, c, cam)) return;
@@ -365,13 +363,12 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   const float pcy = static_cast<float>(c.py - c.fy0) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T, G::kBatch, false, CUT, OIT, true, LT>(a, c, b, s_rec, nullptr, s_list, nullptr,
-                                                                         s_u);
+    const int m = stage_and_cull<T, G::kBatch, false, CUT, OIT, true, LT>(a, c, b, s_rec, nullptr, s_list, nullptr);
     const LT* list = s_list + c.wave * G::kBatch;
     // four splats per step: one read fetches their list entries and all four
     // records are requested before any arithmetic, so LDS latency is paid
     // once per four splats.  The staged colour carries the amplitude.
-    auto accumulate = [&](const StagedRec& r, int k) {
+    auto accumulate = [&](const StagedRec& r) {
       const float q = pair_q(r, pcx, pcy);
       const float cut = CUT ? r.r2.y : tau;
       const float G = q <= cut ? falloff(q) : 0.f;
@@ -379,38 +376,22 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
       ng = fmaf(G, r.r1.w, ng);
       nb = fmaf(G, r.r2.x, nb);
       dd = fmaf(G, r.r1.y, dd);
-      if (OIT) cov *= 1.f - __builtin_amdgcn_fmed3f(s_u[k] * G, 0.f, 1.f);
+      if (OIT) cov *= 1.f - __builtin_amdgcn_fmed3f(r.r2.z * G, 0.f, 1.f);
       if (COUNT) cntp += q <= cut ? 1 : 0;
     };
     int i = 0;
-    if constexpr (OIT) {
-      for (; i + 4 <= m; i += 4) {
-        const uint32_t k4 = *reinterpret_cast<const uint32_t*>(list + i);
-        const int k0 = k4 & 0xffu, k1 = (k4 >> 8) & 0xffu, k2 = (k4 >> 16) & 0xffu, k3 = k4 >> 24;
-        const StagedRec r0 = s_rec[k0];
-        const StagedRec r1 = s_rec[k1];
-        const StagedRec r2 = s_rec[k2];
-        const StagedRec r3 = s_rec[k3];
-        accumulate(r0, k0);
-        accumulate(r1, k1);
-        accumulate(r2, k2);
-        accumulate(r3, k3);
-      }
-      for (; i < m; ++i) accumulate(s_rec[list[i]], list[i]);
-    } else {
-      for (; i + 4 <= m; i += 4) {
-        const uint4 o4 = *reinterpret_cast<const uint4*>(list + i);
-        const StagedRec r0 = rec_at(s_rec, o4.x);
-        const StagedRec r1 = rec_at(s_rec, o4.y);
-        const StagedRec r2 = rec_at(s_rec, o4.z);
-        const StagedRec r3 = rec_at(s_rec, o4.w);
-        accumulate(r0, 0);
-        accumulate(r1, 0);
-        accumulate(r2, 0);
-        accumulate(r3, 0);
-      }
-      for (; i < m; ++i) accumulate(rec_at(s_rec, list[i]), 0);
+    for (; i + 4 <= m; i += 4) {
+      const uint4 o4 = *reinterpret_cast<const uint4*>(list + i);
+      const StagedRec r0 = rec_at(s_rec, o4.x);
+      const StagedRec r1 = rec_at(s_rec, o4.y);
+      const StagedRec r2 = rec_at(s_rec, o4.z);
+      const StagedRec r3 = rec_at(s_rec, o4.w);
+      accumulate(r0);
+      accumulate(r1);
+      accumulate(r2);
+      accumulate(r3);
     }
+    for (; i < m; ++i) accumulate(rec_at(s_rec, list[i]));
   }
   if (c.px >= cam->width || c.py >= cam->height) return;
   const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
@@ -626,14 +607,14 @@ __device__ __forceinline__ void bwd_chunk_split(const TileCtx<T>& c, int c0, int
 // dL/du = sum G dL/dalpha.  The moments therefore carry the amplitude.
 template <int T>
 __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
-                                              const StagedRec* s_rec, const float* s_u,
+                                              const StagedRec* s_rec,
                                               const float4* pd_wave, const float* pk_wave,
                                               float (*out)[kWave], float tau) {
   const int j = c0 + c.lane;
   const bool valid = j < m;
   const int kr = valid ? list[j] : 0;
   const StagedRec r = s_rec[kr];
-  const float u = s_u[kr];
+  const float u = r.r2.z;
   const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
   float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
   float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f, g_u = 0.f;
@@ -689,7 +670,7 @@ __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m
 // bwd_chunk_split (per-pixel factors and coverage factors from LDS).
 template <int T, int K>
 __device__ __forceinline__ void bwd_chunk_oit_split(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
-                                                    const StagedRec* s_rec, const float* s_u, const float4* s_pd,
+                                                    const StagedRec* s_rec, const float4* s_pd,
                                                     const float* s_pk, float (*out)[kWave], float tau) {
   constexpr int S = kWave / K;  // splats per chunk
   constexpr int R = 8 / K;      // rows per lane group
@@ -699,7 +680,7 @@ __device__ __forceinline__ void bwd_chunk_oit_split(const TileCtx<T>& c, int c0,
   const bool valid = j < m;
   const int kr = valid ? list[j] : 0;
   const StagedRec r = s_rec[kr];
-  const float u = s_u[kr];
+  const float u = r.r2.z;
   const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
   float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
   float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f, g_u = 0.f;
@@ -819,12 +800,14 @@ __device__ __forceinline__ void pixel_factors(const RasterArgs& a, const DevCame
   *kcov_o = kcov;
 }
 
-// Tile 16 asks the compiler for five resident waves per SIMD (at most 102
-// VGPRs): the short-chunk path would otherwise raise the register count and
-// cost a wave.  With Eq. 2 the LDS already limits a CU to four workgroups.
+// Tile 16 asks the compiler for five resident waves per SIMD with Eq. 7 (at
+// most 102 VGPRs): the short-chunk path would otherwise raise the register
+// count and cost a wave.  With Eq. 2 the LDS limits a CU to four workgroups;
+// asking for four (at most 128 VGPRs, no spills) keeps the registers from
+// being the tighter limit.
 template <int T, bool OIT>
 constexpr int bwd_min_blocks() {
-  return T == 16 && !OIT ? 5 : 1;
+  return T == 16 ? (OIT ? 4 : 5) : 1;
 }
 
 // Backward: each thread first forms its pixel's factors (pixel_factors)
@@ -857,7 +840,6 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
   __shared__ __align__(16) uint8_t s_list[G::kWaves * kB];
   __shared__ uint16_t s_pos[G::kWaves * kB];
   __shared__ float s_part[G::kWaves][NV][kWave];
-  __shared__ float s_u[OIT ? kB : 1];
   __shared__ int s_m[G::kWaves];
   __shared__ float4 s_pd[G::kThreads];            // per-pixel factors, thread order
   __shared__ float s_pk[OIT ? G::kThreads : 1];   // OIT: per-pixel coverage factors
@@ -895,7 +877,7 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
   const float tau = a.tau;
   const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
   for (uint32_t b = c.start; b < c.end; b += kB) {
-    const int m = stage_and_cull<T, kB, true, CUT, OIT, false, uint8_t>(a, c, b, s_rec, s_slot, s_list, s_pos, s_u);
+    const int m = stage_and_cull<T, kB, true, CUT, OIT, false, uint8_t>(a, c, b, s_rec, s_slot, s_list, s_pos);
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kB), c.end - b));
     if (c.lane == 0) s_m[c.wave] = m;
     __syncthreads();
@@ -913,13 +895,13 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
         if (OIT) {
           const float* pkl = pk_wave;
           if (left > kWave / 2)
-            bwd_chunk_oit<T>(c, r * kWave, m, list, s_rec, s_u, pd_wave, pk_wave, s_part[c.wave], tau);
+            bwd_chunk_oit<T>(c, r * kWave, m, list, s_rec, pd_wave, pk_wave, s_part[c.wave], tau);
           else if (left > kWave / 4)
-            bwd_chunk_oit_split<T, 2>(c, r * kWave, m, list, s_rec, s_u, pdl, pkl, s_part[c.wave], tau);
+            bwd_chunk_oit_split<T, 2>(c, r * kWave, m, list, s_rec, pdl, pkl, s_part[c.wave], tau);
           else if (left > kWave / 8)
-            bwd_chunk_oit_split<T, 4>(c, r * kWave, m, list, s_rec, s_u, pdl, pkl, s_part[c.wave], tau);
+            bwd_chunk_oit_split<T, 4>(c, r * kWave, m, list, s_rec, pdl, pkl, s_part[c.wave], tau);
           else
-            bwd_chunk_oit_split<T, 8>(c, r * kWave, m, list, s_rec, s_u, pdl, pkl, s_part[c.wave], tau);
+            bwd_chunk_oit_split<T, 8>(c, r * kWave, m, list, s_rec, pdl, pkl, s_part[c.wave], tau);
         } else {
           if (left > kWave / 2)
             bwd_chunk<T, CUT>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
