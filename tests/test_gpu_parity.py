@@ -122,6 +122,34 @@ def test_c1_gradients(c1):
     _check_globals(gg["globals"], _oracle_globals(st, gref["globals"]), "c1")
 
 
+@pytest.mark.parametrize("oit", [False, True])
+def test_every_pair_slot_is_written_by_the_backward(c1, oit):
+    """The raster backward stores every binned pair's partial sums, zeros
+    included, and the per-Gaussian sums read only those slots: with the
+    partial-gradient regions of the pair buffer filled with NaN beforehand,
+    the gradients still match the reference."""
+    sc, cams, st = c1
+    st = st.copy(oit=oit)
+    log(f"case: c1 pair slots over a NaN-filled buffer, oit={oit}")
+    ctx = WSRContext(sc["means"].shape[1], cams, st)
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    ctx.project(dev, g)
+    ctx.bin(grow=True)
+    ctx.pairs[: 36 * ctx.capacity].fill_(0xFF)                     # every partial slot NaN
+    ctx.pairs[40 * ctx.capacity: 44 * ctx.capacity].fill_(0xFF)    # and every dL/du slot
+    ctx.bin(grow=False)
+    rgb, den = ctx.render_fwd(g)
+    r = ws.upstream_grad(cams, seed=3)
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, torch.from_numpy(r[0].reshape(-1, 3)).cuda(), rgb, den))
+    torch.cuda.synchronize()
+    ctx.check()
+    for k, v in gg.items():
+        assert np.isfinite(v).all(), k
+    gref = oracle.render_bwd(sc, cams[0], st, r[0])
+    compare_grads(gg, gref, _grad_keys(st, 1), label="c1 NaN-filled pair buffer")
+
+
 def test_autograd_function_matches_direct_backward(c1):
     sc, cams, st = c1
     log("case: autograd wrapper")
