@@ -88,6 +88,15 @@ def compare_grads(g_gpu: dict, g_ref: dict, keys, tol=GRAD_TOL, label=""):
             assert err <= tol * scale, (k, err, scale)
 
 
+def unambiguous(ref) -> np.ndarray:
+    """[H][W][1] mask, 0 on the pixels where the reference reports a pair
+    within float32 rounding of the support cutoff.  There either support
+    decision is correct, and a flipped pair changes the gradients of that
+    pixel's Gaussians by up to its whole term; an upstream gradient of zero
+    there takes those pixels out of the comparison on both sides."""
+    return (ref["amb_c"] == 0)[..., None].astype(np.float32)
+
+
 def grads_to_numpy(g: dict) -> dict:
     return {k: v.detach().cpu().numpy() for k, v in g.items()}
 

@@ -8,7 +8,7 @@ import torch
 import oracle
 import wsr_synth as ws
 from tests.gpu_helpers import (amb_kw, compare_grads, compare_image, densest_crop, gpu_forward, grads_to_numpy,
-                               log, to_views)
+                               log, to_views, unambiguous)
 from tests.test_gpu_parity import _check_globals, _grad_keys, _oracle_globals
 
 pytestmark = pytest.mark.gpu
@@ -58,7 +58,16 @@ def test_headline_oit_split_tiles():
     crop = densest_crop(counts)
     tiles_pairs = ctx.last_pairs
     log(f"headline OIT: binned pairs {tiles_pairs}, densest crop {crop}")
+    refs = []
     for c in (crop, (928, 508, 992, 572)):
         x0, y0, x1, y1 = c
-        ref = oracle.render(sc, cams[0], st, crop=c, **amb_kw(st))
-        compare_image(C[y0:y1, x0:x1], ref, label=f"headline OIT {c}")
+        refs.append(oracle.render(sc, cams[0], st, crop=c, **amb_kw(st)))
+        compare_image(C[y0:y1, x0:x1], refs[-1], label=f"headline OIT {c}")
+    # gradients through the densest crop
+    x0, y0, x1, y1 = crop
+    r = np.zeros((1080, 1920, 3), np.float32)
+    r[y0:y1, x0:x1] = np.random.default_rng(12).standard_normal((y1 - y0, x1 - x0, 3)) * unambiguous(refs[0])
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, torch.from_numpy(r.reshape(-1, 3)).cuda(), rgb, den))
+    gref = oracle.render_bwd(sc, cams[0], st, r[y0:y1, x0:x1], crop=crop)
+    compare_grads(gg, gref, _grad_keys(st, 16), label="headline OIT crop")
+    _check_globals(gg["globals"], _oracle_globals(st, gref["globals"]), "headline OIT crop")
