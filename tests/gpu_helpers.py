@@ -44,13 +44,14 @@ def to_views(ctx, t):
     return [v.detach().cpu().numpy() for v in ctx.views(t)]
 
 
-def compare_image(C_gpu, ref, tol=IMG_TOL, label=""):
+def compare_image(C_gpu, ref, tol=IMG_TOL, label="", max_amb_frac=0.02):
     """Max-abs comparison that accounts for pairs whose support decision is
     within float32 rounding of the cutoff (the reference reports, per pixel,
     the sum over such pairs of |a| * max|rgb - C|): those pixels may differ by
     up to 2 * that sum / |den| more.  Pixels whose denominator cancels
-    ((|w_B| + sum|a|) / |den| > ILL_COND) are counted, not gated.  Returns a
-    dict of statistics."""
+    ((|w_B| + sum|a|) / |den| > ILL_COND) are counted, not gated.  At most
+    max_amb_frac of the pixels may hold such a pair (a wider window would
+    hide errors).  Returns a dict of statistics."""
     C_ref, den = ref["C"], ref["den"]
     err = np.abs(C_gpu.astype(np.float64) - C_ref).max(axis=-1)
     zero = den == 0
@@ -70,7 +71,7 @@ def compare_image(C_gpu, ref, tol=IMG_TOL, label=""):
     assert st["max_err_clean"] <= tol, st
     assert st["over_bound"] == 0, st
     assert st["ill_px"] <= max(2, 0.001 * err.size), st
-    assert st["ambiguous_px"] <= max(20, 0.02 * err.size), st
+    assert st["ambiguous_px"] <= max(20, max_amb_frac * err.size), st
     return st
 
 

@@ -9,7 +9,7 @@ import torch
 import oracle
 import wsr_synth as ws
 from tests.gpu_helpers import (amb_kw, compare_grads, compare_image, densest_crop, gpu_forward, grads_to_numpy,
-                               log, to_views)
+                               log, to_views, unambiguous)
 from tests.test_gpu_parity import _check_globals, _grad_keys, _oracle_globals
 
 pytestmark = pytest.mark.gpu
@@ -48,6 +48,29 @@ def test_c2_early_out_gradients_on_crop(c2):
     gref = oracle.render_bwd(sc, cams[0], st_cut, r[y0:y1, x0:x1], crop=crop)
     compare_grads(gg, gref, _grad_keys(st_cut, 16), label="c2 early-out crop")
     _check_globals(gg["globals"], _oracle_globals(st_cut, gref["globals"]), "c2 early-out crop")
+
+
+def test_headline_early_out_densest_crop():
+    """1 M Gaussians, one 1080p view, as the benchmark runs the early-out:
+    the densest crop's image, and every Gaussian's gradient through it (with
+    an upstream gradient of zero on pixels whose support decision is within
+    float32 rounding of a cutoff)."""
+    sc, cams, st = ws.make_scene("headline")
+    st_cut = st.copy(alpha_cut=CUT)
+    log("case: headline early-out densest crop")
+    ctx, dev, g, (rgb, den, cnt) = gpu_forward(sc, cams, st_cut, count=True)
+    x0, y0, x1, y1 = crop = densest_crop(to_views(ctx, cnt)[0])
+    ref = oracle.render(sc, cams[0], st_cut, crop=crop, mode="aabb", **amb_kw(st_cut))
+    # every splat has a cutoff of its own, 2 ln(u / alpha_cut), and most pairs
+    # end there rather than at tau: in the densest crop about twice as many
+    # pixels hold a pair within rounding of its cutoff as without the cut
+    compare_image(to_views(ctx, rgb)[0][y0:y1, x0:x1], ref, label="headline early-out crop", max_amb_frac=0.04)
+    r = np.zeros((1080, 1920, 3), np.float32)
+    r[y0:y1, x0:x1] = np.random.default_rng(9).standard_normal((y1 - y0, x1 - x0, 3)) * unambiguous(ref)
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, torch.from_numpy(r.reshape(-1, 3)).cuda(), rgb, den))
+    gref = oracle.render_bwd(sc, cams[0], st_cut, r[y0:y1, x0:x1], crop=crop)
+    compare_grads(gg, gref, _grad_keys(st_cut, 16), label="headline early-out crop")
+    _check_globals(gg["globals"], _oracle_globals(st_cut, gref["globals"]), "headline early-out crop")
 
 
 def test_c1_early_out_culls_faint_gaussians():

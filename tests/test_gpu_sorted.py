@@ -65,6 +65,24 @@ def test_c2_sorted_densest_crop():
     _compare(to_views(ctx, rgb)[0][y0:y1, x0:x1], to_views(ctx, T)[0][y0:y1, x0:x1], ref, "c2 crop")
 
 
+@pytest.mark.parametrize("blend", [{}, {"alpha_min": 1.0 / 255.0, "t_min": 1e-4}])
+def test_headline_sorted_densest_crop(blend):
+    """1 M Gaussians, one 1080p view, as the benchmark compares them: the
+    densest tile lists (up to about 8,000 splats) sorted and composited."""
+    sc, cams, st = ws.make_scene("headline")
+    st = st.copy(weight_kind="dir")
+    log(f"case: headline sorted densest crop {blend}")
+    ctx0 = WSRContext(sc["means"].shape[1], cams, st)
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    _, _, cnt = ctx0.forward(dev, g, count=True)
+    x0, y0, x1, y1 = densest_crop(to_views(ctx0, cnt)[0])
+    del ctx0
+    ctx, rgb, T = _sorted_gpu(sc, cams, st, **blend)
+    ref = oracle.render_sorted(sc, cams[0], st, crop=(x0, y0, x1, y1), **amb_kw(st), **blend)
+    _compare(to_views(ctx, rgb)[0][y0:y1, x0:x1], to_views(ctx, T)[0][y0:y1, x0:x1], ref, "headline crop")
+
+
 def test_sorted_multi_view_uneven_sizes():
     sc, _, st = ws.make_scene("c1", n=2000)
     st = st.copy(weight_kind="dir", tile=8)
