@@ -21,7 +21,7 @@ def _cams(sizes):
     return [ws.look_at_camera((0.0, 0.0, -4.0), w, h) for w, h in sizes]
 
 
-@pytest.mark.parametrize("sizes", [[(37, 53)], [(64, 40), (19, 70), (128, 128)]])
+@pytest.mark.parametrize("sizes", [[(37, 53)], [(64, 40), (19, 70), (128, 128)], [(1920, 1080)]])
 def test_loss_and_gradient_match_reference(sizes):
     log(f"case: loss {sizes}")
     rng = np.random.default_rng(len(sizes))
