@@ -802,9 +802,9 @@ __device__ __forceinline__ void pixel_factors(const RasterArgs& a, const DevCame
 
 // Tile 16 asks the compiler for five resident waves per SIMD with Eq. 7 (at
 // most 102 VGPRs): the short-chunk path would otherwise raise the register
-// count and cost a wave.  With Eq. 2 the LDS limits a CU to four workgroups;
-// asking for four (at most 128 VGPRs, no spills) keeps the registers from
-// being the tighter limit.
+// count and cost a wave.  With Eq. 2 it asks for four (at most 128 VGPRs, no
+// spills; the unbounded kernel takes 165, three waves): five would fit the
+// LDS but spill 19 registers, which measured slower.
 template <int T, bool OIT>
 constexpr int bwd_min_blocks() {
   return T == 16 ? (OIT ? 4 : 5) : 1;
