@@ -269,6 +269,36 @@ def test_multi_view_uneven_sizes():
     compare_grads(gg, gref, _grad_keys(st, 16), label="multi-view")
 
 
+def test_c4_sixteen_uneven_views_at_full_size():
+    """The 16-view batch of the benchmark (1 M Gaussians, views from 697x392
+    to 1902x1070, 14.5 Mpx in one launch sequence): densest crops of four
+    views, and every Gaussian's gradient through the densest crops of two
+    views (per-view gradients add up; pixels with a pair within rounding of
+    the cutoff carry no upstream gradient)."""
+    sc, cams, st = ws.make_scene("c4")
+    log(f"case: c4 {len(cams)} views, {sum(c['width'] * c['height'] for c in cams)} px")
+    ctx, dev, g, (rgb, den, cnt) = gpu_forward(sc, cams, st, count=True)
+    imgs, counts = to_views(ctx, rgb), to_views(ctx, cnt)
+    refs = {}
+    for v in (0, 2, 9, 15):
+        crop = densest_crop(counts[v])
+        x0, y0, x1, y1 = crop
+        refs[v] = (crop, oracle.render(sc, cams[v], st, crop=crop, mode="aabb", **amb_kw(st)))
+        compare_image(imgs[v][y0:y1, x0:x1], refs[v][1], label=f"c4 view {v} {crop}")
+    rng = np.random.default_rng(21)
+    rs = [np.zeros((c["height"], c["width"], 3), np.float32) for c in cams]
+    gsum = None
+    for v in (2, 9):
+        (x0, y0, x1, y1), ref = refs[v]
+        rs[v][y0:y1, x0:x1] = rng.standard_normal((y1 - y0, x1 - x0, 3)) * unambiguous(ref)
+        gv = oracle.render_bwd(sc, cams[v], st, rs[v][y0:y1, x0:x1], crop=refs[v][0])
+        gsum = gv if gsum is None else {k: gsum[k] + gv[k] for k in gv if k != "grad2d"}
+    dL = torch.cat([torch.from_numpy(r.reshape(-1, 3)) for r in rs]).cuda()
+    gg = grads_to_numpy(ctx.render_bwd(dev, g, dL, rgb, den))
+    compare_grads(gg, gsum, _grad_keys(st, 16), label="c4 two-view crops")
+    _check_globals(gg["globals"], _oracle_globals(st, gsum["globals"]), "c4 two-view crops")
+
+
 # ---------------------------------------------------------------- edge cases
 
 def test_empty_scene_and_all_culled():
