@@ -17,21 +17,26 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wsr_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# WSR_ORACLE_LIB loads another build of the same source (the mutation tests
+# load copies with a planted mistake)
+_LIB = os.environ.get("WSR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 PROJ_STRIDE = 25
 WEIGHT_KINDS = {"dir": 0, "exp": 1, "lc": 2}
 OPACITY_MODES = {"logit": 0, "sh": 1}
 
 
-def build(force: bool = True) -> str:
-    """Compile the checker (gcc, -O2, OpenMP) into oracle/liboracle.so."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+def build(force: bool = True, src: str | None = None, out: str | None = None) -> str:
+    """Compile the checker (gcc, -O2, OpenMP) into oracle/liboracle.so, or
+    the source `src` into `out`."""
+    src = src or _SRC
+    out = out or _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-march=x86-64-v2", "-fopenmp", "-fPIC", "-shared",
-               "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"]
+               "-Wall", "-Wno-unknown-pragmas", "-o", tmp, src, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
 class _Scene(C.Structure):
