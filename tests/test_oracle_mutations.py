@@ -35,6 +35,22 @@ MUTATIONS = [
     ("Eq. 7 numerator: background weight dropped", "N3[c] = P->bg[c] * P->w_bg + num[3 * o + c];",
      "N3[c] = P->bg[c] + num[3 * o + c];"),
     ("backward: sign of dL/dq", "double dq = -0.5 * a * dLda;", "double dq = 0.5 * a * dLda;"),
+    ("backward: factor 2 of the conic cross term dropped", "dcon[1] += dq * 2.0 * dx * dy;",
+     "dcon[1] += dq * dx * dy;"),
+    ("backward: mean gradient with dx and dy swapped",
+     "dmu[1] += -dq * (2.0 * g->conic[1] * dx + 2.0 * g->conic[2] * dy);",
+     "dmu[1] += -dq * (2.0 * g->conic[1] * dy + 2.0 * g->conic[2] * dx);"),
+    ("backward: weight gradient through the wrong factor", "const double dw = das * g->u;",
+     "const double dw = das * g->w;"),
+    ("backward: sigmoid derivative term dropped", "g_logit[i] = du * g->u * (1.0 - g->u);",
+     "g_logit[i] = du * g->u;"),
+    ("backward: EXP beta gradient without its logarithm", "gbeta[j] = dw * (-P->sigma * db * log(d) * g->w);",
+     "gbeta[j] = dw * (-P->sigma * db * g->w);"),
+    ("OIT backward: 1 / (1 - alpha) dropped", "const double dLdal = -kfac[o] / (1.0 - al);",
+     "const double dLdal = -kfac[o];"),
+    ("early-out: cutoff without its factor 2", "const double c = 2.0 * log(o->u / P->alpha_cut);",
+     "const double c = log(o->u / P->alpha_cut);"),
+    ("sorted blending: transmittance not attenuated", "T *= 1.0 - a;", "T *= 1.0;"),
 ]
 
 
