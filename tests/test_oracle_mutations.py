@@ -1,8 +1,9 @@
-"""Planted mistakes in the FP64 reference: each test compiles a copy of
-oracle/wsr_oracle.c with one plausible error (a flipped sign, a dropped
-term, a swapped operand or index, a wrong constant) and runs the reference's
-own pins against it in a child process.  At least one pin must fail for
-every mistake; a mistake that passes would mean the pins cannot tell a wrong
+"""Planted mistakes in the FP64 reference: each test builds a copy of the
+renderer reference (oracle/wsr_oracle.c) or of the training reference
+(oracle/train.py) with one plausible error (a flipped sign, a dropped term, a
+swapped operand or index, a wrong constant) and runs the reference's own pins
+against it in a child process.  At least one pin must fail for every
+mistake; a mistake that passes would mean the pins cannot tell a wrong
 reference from a right one."""
 import os
 import subprocess
@@ -54,7 +55,12 @@ MUTATIONS = [
 ]
 
 
-@pytest.mark.parametrize("what,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+# an empty replacement: the unchanged copy, whose pins must all pass (shows that
+# the failures below come from the planted mistakes, not from the set-up)
+CONTROL = ("unchanged copy", "", "")
+
+
+@pytest.mark.parametrize("what,old,new", [CONTROL] + MUTATIONS, ids=[m[0] for m in [CONTROL] + MUTATIONS])
 def test_a_planted_mistake_fails_a_pin(tmp_path, what, old, new):
     text = open(SRC).read()
     assert old in text, what
@@ -65,4 +71,35 @@ def test_a_planted_mistake_fails_a_pin(tmp_path, what, old, new):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"]
                        + PINS, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     # exit status 1: tests ran and one failed (not a collection or usage error)
-    assert r.returncode == 1, (what, r.returncode, r.stdout[-2000:])
+    assert r.returncode == (0 if not old else 1), (what, r.returncode, r.stdout[-2000:])
+
+
+# the training reference (numpy): loss, its gradient and Adam
+TRAIN_MUTATIONS = [
+    ("SSIM: C1 not squared", "C1 = 0.01 ** 2", "C1 = 0.01"),
+    ("SSIM: sign in the covariance term", "a2 = 2.0 * (sxy - u * v) + C2", "a2 = 2.0 * (sxy + u * v) + C2"),
+    ("SSIM derivative: sign of dS/dSxx", "d_sxx = -s / b2", "d_sxx = s / b2"),
+    ("loss gradient: x for y in the cross term", '+ y[..., ch] * filter2(t["d_sxy"], g)) / P',
+     '+ x[..., ch] * filter2(t["d_sxy"], g)) / P'),
+    ("l1 gradient: sign flipped", "grad = (1.0 - lam) * np.sign(x - y) / P", "grad = (1.0 - lam) * np.sign(y - x) / P"),
+    ("Adam: first-moment bias correction dropped", "m_hat = m / (1.0 - beta1 ** step)", "m_hat = m"),
+]
+
+
+@pytest.mark.parametrize("what,old,new", [CONTROL] + TRAIN_MUTATIONS,
+                         ids=[m[0] for m in [CONTROL] + TRAIN_MUTATIONS])
+def test_a_planted_mistake_in_the_training_reference_fails_a_pin(tmp_path, what, old, new):
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    text = open(os.path.join(ROOT, "oracle", "train.py")).read()
+    assert old in text, what
+    (pkg / "train.py").write_text(text.replace(old, new, 1))
+    (pkg / "__init__.py").write_text(open(os.path.join(ROOT, "oracle", "__init__.py")).read())
+    env = dict(os.environ, WSR_ORACLE_LIB=oracle.build(force=False))
+    # the copy is imported first, so the pins' own import finds it
+    code = (f"import sys; sys.path.insert(0, {str(tmp_path)!r}); import oracle.train; "
+            f"assert oracle.train.__file__.startswith({str(tmp_path)!r}); import pytest; "
+            "sys.exit(pytest.main(['-x', '-q', '-p', 'no:cacheprovider', 'tests/test_oracle_train.py']))")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == (0 if not old else 1), (what, r.returncode, r.stdout[-2000:], r.stderr[-2000:])
