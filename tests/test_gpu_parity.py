@@ -136,6 +136,8 @@ def test_every_pair_slot_is_written_by_the_backward(c1, oit):
     g = globals_tensor(st)
     ctx.project(dev, g)
     ctx.bin(grow=True)
+    # pair buffer layout: [capacity][36 B] partials, [capacity] ids, [capacity] dL/du
+    assert ctx.pair_bytes == 44
     ctx.pairs[: 36 * ctx.capacity].fill_(0xFF)                     # every partial slot NaN
     ctx.pairs[40 * ctx.capacity: 44 * ctx.capacity].fill_(0xFF)    # and every dL/du slot
     ctx.bin(grow=False)
