@@ -5,6 +5,7 @@ swapped operand or index, a wrong constant) and runs the reference's own pins
 against it in a child process.  At least one pin must fail for every
 mistake; a mistake that passes would mean the pins cannot tell a wrong
 reference from a right one."""
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -59,21 +60,6 @@ MUTATIONS = [
 # the failures below come from the planted mistakes, not from the set-up)
 CONTROL = ("unchanged copy", "", "")
 
-
-@pytest.mark.parametrize("what,old,new", [CONTROL] + MUTATIONS, ids=[m[0] for m in [CONTROL] + MUTATIONS])
-def test_a_planted_mistake_fails_a_pin(tmp_path, what, old, new):
-    text = open(SRC).read()
-    assert old in text, what
-    src = tmp_path / "wsr_oracle.c"
-    src.write_text(text.replace(old, new, 1))
-    lib = oracle.build(force=True, src=str(src), out=str(tmp_path / "liboracle.so"))
-    env = dict(os.environ, WSR_ORACLE_LIB=lib)
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"]
-                       + PINS, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-    # exit status 1: tests ran and one failed (not a collection or usage error)
-    assert r.returncode == (0 if not old else 1), (what, r.returncode, r.stdout[-2000:])
-
-
 # the training reference (numpy): loss, its gradient and Adam
 TRAIN_MUTATIONS = [
     ("SSIM: C1 not squared", "C1 = 0.01 ** 2", "C1 = 0.01"),
@@ -86,20 +72,73 @@ TRAIN_MUTATIONS = [
 ]
 
 
-@pytest.mark.parametrize("what,old,new", [CONTROL] + TRAIN_MUTATIONS,
-                         ids=[m[0] for m in [CONTROL] + TRAIN_MUTATIONS])
-def test_a_planted_mistake_in_the_training_reference_fails_a_pin(tmp_path, what, old, new):
-    pkg = tmp_path / "oracle"
-    pkg.mkdir()
+def _run_renderer_copy(tmp, old, new):
+    """Build the C reference with `old` replaced by `new` and run its pins."""
+    text = open(SRC).read()
+    if old not in text:
+        return None
+    tmp.mkdir(parents=True)
+    src = tmp / "wsr_oracle.c"
+    src.write_text(text.replace(old, new, 1))
+    lib = oracle.build(force=True, src=str(src), out=str(tmp / "liboracle.so"))
+    env = dict(os.environ, WSR_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"]
+                          + PINS, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def _run_training_copy(tmp, old, new):
+    """Import a copy of the training reference with `old` replaced by `new`
+    ahead of the original and run its pins."""
     text = open(os.path.join(ROOT, "oracle", "train.py")).read()
-    assert old in text, what
+    if old not in text:
+        return None
+    pkg = tmp / "oracle"
+    pkg.mkdir(parents=True)
     (pkg / "train.py").write_text(text.replace(old, new, 1))
     (pkg / "__init__.py").write_text(open(os.path.join(ROOT, "oracle", "__init__.py")).read())
-    env = dict(os.environ, WSR_ORACLE_LIB=oracle.build(force=False))
+    env = dict(os.environ, WSR_ORACLE_LIB=oracle.build(force=False), OMP_NUM_THREADS="2")
     # the copy is imported first, so the pins' own import finds it
-    code = (f"import sys; sys.path.insert(0, {str(tmp_path)!r}); import oracle.train; "
-            f"assert oracle.train.__file__.startswith({str(tmp_path)!r}); import pytest; "
+    code = (f"import sys; sys.path.insert(0, {str(tmp)!r}); import oracle.train; "
+            f"assert oracle.train.__file__.startswith({str(tmp)!r}); import pytest; "
             "sys.exit(pytest.main(['-x', '-q', '-p', 'no:cacheprovider', 'tests/test_oracle_train.py']))")
-    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
-                       timeout=600)
+    return subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                          timeout=600)
+
+
+RENDERER_CASES = [CONTROL] + MUTATIONS
+TRAINING_CASES = [CONTROL] + TRAIN_MUTATIONS
+
+
+@pytest.fixture(scope="module")
+def results(tmp_path_factory):
+    """Every copy built and run once, four at a time; keyed by (reference, case)."""
+    oracle.build(force=False)
+    jobs = [("renderer", i, m) for i, m in enumerate(RENDERER_CASES)] + \
+           [("training", i, m) for i, m in enumerate(TRAINING_CASES)]
+
+    def run(job):
+        kind, i, (_, old, new) = job
+        tmp = tmp_path_factory.mktemp(f"{kind}{i}")
+        fn = _run_renderer_copy if kind == "renderer" else _run_training_copy
+        return (kind, i), fn(tmp / "copy", old, new)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as pool:
+        return dict(pool.map(run, jobs))
+
+
+def _check(r, what, old):
+    assert r is not None, f"{what}: the text to replace is not in the source"
+    # exit status 1: tests ran and one failed (not a collection or usage error)
     assert r.returncode == (0 if not old else 1), (what, r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+
+
+@pytest.mark.parametrize("i", range(len(RENDERER_CASES)), ids=[m[0] for m in RENDERER_CASES])
+def test_a_planted_mistake_fails_a_pin(results, i):
+    what, old, _ = RENDERER_CASES[i]
+    _check(results[("renderer", i)], what, old)
+
+
+@pytest.mark.parametrize("i", range(len(TRAINING_CASES)), ids=[m[0] for m in TRAINING_CASES])
+def test_a_planted_mistake_in_the_training_reference_fails_a_pin(results, i):
+    what, old, _ = TRAINING_CASES[i]
+    _check(results[("training", i)], what, old)
