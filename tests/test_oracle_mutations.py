@@ -53,6 +53,20 @@ MUTATIONS = [
     ("early-out: cutoff without its factor 2", "const double c = 2.0 * log(o->u / P->alpha_cut);",
      "const double c = log(o->u / P->alpha_cut);"),
     ("sorted blending: transmittance not attenuated", "T *= 1.0 - a;", "T *= 1.0;"),
+    ("projection backward: factor 2 of d(T S T^T)/dT dropped", "dTm[c] = 2.0 * da * ST0[c] + dbv * ST1[c];",
+     "dTm[c] = da * ST0[c] + dbv * ST1[c];"),
+    ("projection backward: Sigma3D gradient not symmetrised",
+     "acc += (dSig3[3 * r + k] + dSig3[3 * k + r]) * M[3 * k + l];", "acc += dSig3[3 * r + k] * M[3 * k + l];"),
+    ("projection backward: exp of the log-scale not chained", "g_log_scales[l * n + i] = ds * s[l];",
+     "g_log_scales[l * n + i] = ds;"),
+    ("projection backward: quaternion normalisation not projected",
+     "g_quats[k * n + i] = (dqh[k] - qh[k] * dot) / qn;", "g_quats[k * n + i] = dqh[k] / qn;"),
+    ("projection backward: sign in the clamped Jacobian branch", "dt[2] += dJ[2] * (fx * rx / (tz * tz));",
+     "dt[2] += dJ[2] * (-fx * rx / (tz * tz));"),
+    ("projection backward: LC sigma gradient without the depth", "gsig[j] = dw * v_i * d / (P->sigma * P->sigma);",
+     "gsig[j] = dw * v_i / (P->sigma * P->sigma);"),
+    ("projection backward: view-direction normalisation not projected",
+     "dp[c] = (ddir[c] - g->dir[c] * proj) / g->dist;", "dp[c] = ddir[c] / g->dist;"),
 ]
 
 
