@@ -226,6 +226,15 @@ def bench_train(args) -> None:
         "stages_ms": {"loss": round(loss_ms, 4), "adam": round(adam_ms, 4)},
         "final_loss": float(loss.item()),
     }
+    # the optimiser, the kernel the training step adds, against HBM: Adam reads
+    # p, g, m, v and writes p, m, v (28 B per parameter); the raster kernels are
+    # those of the render benchmark
+    n_params = sum(p_.numel() for p_, *_ in trainer._groups)
+    adam_gbs = 28.0 * n_params / (adam_ms * 1e-3) / 1e9
+    out["roofline"] = {"kernel": "adam_kernel (all parameter groups)", "bound": "hbm",
+                       "achieved": round(adam_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(adam_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                       "parameters": n_params, "launch_ms": round(adam_ms, 4)}
     print(json.dumps(out), flush=True)
 
 
