@@ -279,6 +279,11 @@ def bench_sorted(args) -> None:
 
     ms_wsr = timed(wsr_fwd, args.steps)
     wsr.check()
+    # the weighted-sum raster alone (the dominant kernel of its forward), for
+    # the roofline: in-support pairs counted once, untimed
+    _, _, cnt = wsr.render_fwd(g, count=True)
+    pairs = int(cnt.sum().item())
+    ms_raster = timed(lambda: wsr.render_fwd(g, out=(rgb, den)), args.steps)
     sd = WSRContext(n, cams, st.copy(weight_kind="dir"))
     sd.forward(dev, g)
     sd._alloc_pairs(int(sd.last_pairs * 1.1) + 1024)
@@ -311,6 +316,12 @@ def bench_sorted(args) -> None:
         "speedup_vs_sorted_exact": round(out["exact"] / ms_wsr, 3),
         "speedup_vs_sorted_3dgs": round(out["3dgs"] / ms_wsr, 3),
     }
+    achieved = pairs * FWD_FLOPS_PER_PAIR / (ms_raster * 1e-3) / 1e12
+    res["roofline"] = {"kernel": "raster_fwd (raster_fwd_kernel)", "bound": "alu", "achieved": round(achieved, 3),
+                       "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                       "flops_per_pair": FWD_FLOPS_PER_PAIR, "launch_ms": round(ms_raster, 4),
+                       "in_support_pairs": pairs}
     print(json.dumps(res), flush=True)
 
 
