@@ -146,7 +146,11 @@ typedef struct {
     float* globals;            /* [6], see WSR_GLOBALS */
 } wsr_grads;
 
+/* WSR_ABI_VERSION of the built library: a binding compares it with the
+ * header it was written against before making any other call. */
 int32_t wsr_abi_version(void);
+/* A static, NUL-terminated description of a wsr_status value (the caller
+ * does not free it); "unknown status" for any other value. */
 const char* wsr_status_string(int32_t status);
 
 /* Bytes of the workspace needed for n Gaussians over the given views and
@@ -187,8 +191,10 @@ int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params
                        int64_t capacity, float* out_rgb, float* out_den, int32_t* out_count,
                        void* stream);
 
-/* Steps a8-a9: gradient of a loss L given dL/dC (concatenated [H][W][3]),
- * the forward's colour and denominator.  Recomputes every pair's amplitude
+/* Steps a8-a9: Eq. 7 differentiated per pixel and pair, then chained
+ * through Eqs. 3-5 (EWA), Eq. 4 and Eq. 11 (SH colour and opacity) and
+ * Eqs. 8-10 (depth weights) to the scene: the gradient of a loss L given
+ * dL/dC (concatenated [H][W][3]), the forward's colour and denominator.  Recomputes every pair's amplitude
  * (nothing per pair is stored by the forward) and writes every field of
  * grads (they are overwritten, not accumulated).  out_grad2d (nullable,
  * DEVICE [n_views][n][9]) receives the per-(view, Gaussian) gradient with
