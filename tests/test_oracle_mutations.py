@@ -53,6 +53,11 @@ MUTATIONS = [
     ("early-out: cutoff without its factor 2", "const double c = 2.0 * log(o->u / P->alpha_cut);",
      "const double c = log(o->u / P->alpha_cut);"),
     ("sorted blending: transmittance not attenuated", "T *= 1.0 - a;", "T *= 1.0;"),
+    ("OIT: coverage product without the clamp", "cov[o] *= 1.0 - clampd(g->u * G, 0.0, 1.0);",
+     "cov[o] *= 1.0 - g->u * G;"),
+    ("OIT: background and average weights swapped", "Cimg[3 * o + c] = cov[o] * P->bg[c] + (1.0 - cov[o]) * avg;",
+     "Cimg[3 * o + c] = (1.0 - cov[o]) * P->bg[c] + cov[o] * avg;"),
+    ("sorted blending: early stop ignored", "if (T < t_min) break;", "if (T < 0.0) break;"),
     ("projection backward: factor 2 of d(T S T^T)/dT dropped", "dTm[c] = 2.0 * da * ST0[c] + dbv * ST1[c];",
      "dTm[c] = da * ST0[c] + dbv * ST1[c];"),
     ("projection backward: Sigma3D gradient not symmetrised",

@@ -12,7 +12,7 @@ from tests.oracle_helpers import dc_for_colour, scene_from
 from tests.test_oracle_grad import FD_H, _tiny
 
 
-def _brute(sc, cam, st):
+def _brute(sc, cam, st, clamp=True):
     p = oracle.project(sc, cam, st.copy(oit=False))
     H, W = cam["height"], cam["width"]
     ys, xs = np.mgrid[0:H, 0:W]
@@ -27,7 +27,7 @@ def _brute(sc, cam, st):
         a = p["u"][i] * p["w"][i] * G
         num += a[..., None] * p["rgb"][i]
         den += a
-        cov *= 1.0 - np.clip(p["u"][i] * G, 0.0, 1.0)
+        cov *= 1.0 - (np.clip(p["u"][i] * G, 0.0, 1.0) if clamp else p["u"][i] * G)
     avg = np.where(den[..., None] != 0, num / np.where(den == 0, 1, den)[..., None], 0.0)
     return cov[..., None] * np.array(st.bg) + (1 - cov[..., None]) * avg
 
@@ -41,6 +41,29 @@ def test_oit_matches_a_brute_force_evaluation(kind, mode):
     assert np.abs(got - _brute(sc, cam, st)).max() < 1e-12
     # it differs from Eq. 7
     assert np.abs(got - oracle.render(sc, cam, st.copy(oit=False))["C"]).max() > 1e-3
+
+
+def test_opacities_outside_the_unit_interval_are_clamped_in_the_coverage():
+    """With the unclamped SH opacity of Sec. 4.3, u can leave [0, 1]; Eq. 2's
+    layer opacity alpha = u exp(-q/2) is clamped to [0, 1] in the coverage
+    product (the weighted average keeps the raw amplitude)."""
+    sc, _, st = ws.make_scene("c2", n=80)
+    sc = {k: v.astype(np.float64) for k, v in sc.items()}
+    rng = np.random.default_rng(17)
+    u_target = np.where(rng.random(80) < 0.6, rng.uniform(1.2, 1.8, 80), rng.uniform(0.2, 0.9, 80))
+    u_target[rng.random(80) < 0.1] = -0.2
+    sc["sh"][0, :, 3] = dc_for_colour(u_target)     # same basis and offset as the colour
+    sc["sh"][1:, :, 3] = 0.0
+    cam = ws.look_at_camera((0.0, 0.0, -4.0), 30, 26)
+    st = st.copy(weight_kind="lc", opacity_mode="sh", tau=1e4, oit=True)
+    u = oracle.project(sc, cam, st)["u"]
+    assert (u > 1.0).sum() > 20 and (u < 0.0).any()
+    got = oracle.render(sc, cam, st)["C"]
+    assert np.abs(got - _brute(sc, cam, st)).max() < 1e-12
+    # the box-restricted mode takes the same decisions
+    assert np.abs(oracle.render(sc, cam, st, mode="aabb")["C"] - got).max() < 1e-12
+    # the clamp matters here: without it the image differs
+    assert np.abs(got - _brute(sc, cam, st, clamp=False)).max() > 1e-3
 
 
 def test_single_layer_is_alpha_blending():
