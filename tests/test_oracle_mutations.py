@@ -58,6 +58,9 @@ MUTATIONS = [
     ("OIT: background and average weights swapped", "Cimg[3 * o + c] = cov[o] * P->bg[c] + (1.0 - cov[o]) * avg;",
      "Cimg[3 * o + c] = (1.0 - cov[o]) * P->bg[c] + cov[o] * avg;"),
     ("sorted blending: early stop ignored", "if (T < t_min) break;", "if (T < 0.0) break;"),
+    ("box-restricted mode: red sum takes the green channel", "num[3 * o] += a * g->rgb[0];",
+     "num[3 * o] += a * g->rgb[1];"),
+    ("box-restricted mode: magnitude sum drops the absolute value", "aden[o] += fabs(a);", "aden[o] += a;"),
     ("projection backward: factor 2 of d(T S T^T)/dT dropped", "dTm[c] = 2.0 * da * ST0[c] + dbv * ST1[c];",
      "dTm[c] = da * ST0[c] + dbv * ST1[c];"),
     ("projection backward: Sigma3D gradient not symmetrised",

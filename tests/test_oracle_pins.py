@@ -330,6 +330,34 @@ def test_strict_and_aabb_modes_agree(c1):
     b = oracle.render(sc2, cams2[0], st2, crop=crop, mode="aabb")
     np.testing.assert_allclose(a["C"], b["C"], atol=1e-12)
     assert np.array_equal(a["count"], b["count"])
+    for k in ("den", "abs_den"):
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=1e-12)
+
+
+def test_denominator_magnitude_counts_negative_amplitudes():
+    """abs_den = |w_B| + sum |a| (the conditioning report of Eq. 7's
+    denominator), against a brute-force sum, in both evaluation modes, on a
+    scene whose unclamped SH opacities (Sec. 4.3) make some amplitudes
+    negative."""
+    sc, _, st = ws.make_scene("c2", n=60)
+    sc = {k: v.astype(np.float64) for k, v in sc.items()}
+    rng = np.random.default_rng(23)
+    sc["sh"][0, :, 3] = dc_for_colour(np.where(rng.random(60) < 0.3, -0.4, 0.7))
+    sc["sh"][1:, :, 3] = 0.0
+    cam = ws.look_at_camera((0.0, 0.0, -4.0), 24, 20)
+    st = st.copy(tau=1e4)
+    p = oracle.project(sc, cam, st)
+    assert (p["u"][p["visible"]] < 0).sum() > 5
+    ys, xs = np.mgrid[0:cam["height"], 0:cam["width"]]
+    want = np.full((cam["height"], cam["width"]), abs(st.w_bg))
+    for i in np.nonzero(p["visible"])[0]:
+        A, B, Cc = p["conic"][i]
+        dx, dy = xs + 0.5 - p["mu"][i, 0], ys + 0.5 - p["mu"][i, 1]
+        q = A * dx * dx + 2 * B * dx * dy + Cc * dy * dy
+        want += np.where(q <= st.tau, np.abs(p["u"][i] * p["w"][i] * np.exp(-0.5 * q)), 0.0)
+    for mode in ("strict", "aabb"):
+        got = oracle.render(sc, cam, st, mode=mode)["abs_den"]
+        np.testing.assert_allclose(got, want, rtol=1e-12)
 
 
 def test_ambiguity_window_widens_only_the_report(c1):
