@@ -451,7 +451,12 @@ static double amb_pos_window(const proj_t *g, double dx, double dy, double pos_h
  *   out_den [h][w]    denominator including w_B
  *   out_amb [h][w]    sum of |a| over the pairs whose support decision a
  *                     float32 evaluation of q may flip:
- *                     |q - tau| <= eta * M + amb_pos_window(..., pos_h)
+ *                     |q - cut| <= eta * M + amb_pos_window(..., pos_h)
+ *                     (+ 10 eta (|cut| + 1) where the early-out lowers the
+ *                     cutoff below tau, for the float32 rounding of the
+ *                     cutoff itself; parity unpinned: no test fixes the size
+ *                     of this allowance, the GPU tests only bound how many
+ *                     pixels it reports)
  *                     with M = A dx^2 + 2|B dx dy| + C dy^2, the magnitude of
  *                     the terms q sums (rounding error scales with M, not q,
  *                     because the terms cancel for elongated splats); pos_h

@@ -61,6 +61,7 @@ MUTATIONS = [
     ("box-restricted mode: red sum takes the green channel", "num[3 * o] += a * g->rgb[0];",
      "num[3 * o] += a * g->rgb[1];"),
     ("box-restricted mode: magnitude sum drops the absolute value", "aden[o] += fabs(a);", "aden[o] += a;"),
+    ("ambiguity report: colour distance dropped", "sc += a * md;", "sc += a;"),
     ("projection backward: factor 2 of d(T S T^T)/dT dropped", "dTm[c] = 2.0 * da * ST0[c] + dbv * ST1[c];",
      "dTm[c] = da * ST0[c] + dbv * ST1[c];"),
     ("projection backward: Sigma3D gradient not symmetrised",

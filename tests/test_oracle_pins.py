@@ -334,6 +334,25 @@ def test_strict_and_aabb_modes_agree(c1):
         np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=1e-12)
 
 
+def test_ambiguity_report_weighs_each_pair_by_its_colour_distance():
+    """With one Gaussian, every reported pixel holds exactly that pair, so
+    amb_c / amb is the largest channel distance between its colour and the
+    rendered colour there (the most the pair's flip can move the pixel, per
+    unit of |a|)."""
+    cam = ws.look_at_camera((0.0, 0.0, -4.0), 40, 40)
+    sh = np.zeros((1, 1, 4))
+    sh[0, 0, :3] = dc_for_colour((0.9, 0.1, 0.6))
+    sc = scene_from([(0.03, -0.02, 0.0)], log_scales=np.full(1, -1.2), sh=sh, logit=np.array([1.2]))
+    st = ws.Settings(weight_kind="exp", opacity_mode="logit", bg=(0.2, 0.7, 0.4))
+    r = oracle.render(sc, cam, st, eta=0.05)
+    m = r["amb"] > 0
+    assert m.sum() > 10
+    rgb = oracle.project(sc, cam, st)["rgb"][0]
+    want = np.abs(rgb[None, :] - r["C"][m]).max(axis=-1)
+    np.testing.assert_allclose(r["amb_c"][m] / r["amb"][m], want, rtol=1e-12)
+    assert (r["amb_c"][~m] == 0).all()
+
+
 def test_denominator_magnitude_counts_negative_amplitudes():
     """abs_den = |w_B| + sum |a| (the conditioning report of Eq. 7's
     denominator), against a brute-force sum, in both evaluation modes, on a
