@@ -62,6 +62,11 @@ MUTATIONS = [
      "num[3 * o] += a * g->rgb[1];"),
     ("box-restricted mode: magnitude sum drops the absolute value", "aden[o] += fabs(a);", "aden[o] += a;"),
     ("ambiguity report: colour distance dropped", "sc += a * md;", "sc += a;"),
+    ("OIT strict mode: coverage without the clamp", "pc *= 1.0 - clampd(g->u * G, 0.0, 1.0);",
+     "pc *= 1.0 - g->u * G;"),
+    ("sorted blending: ambiguity report dropped",
+     "if (fabs(q - tau) <= eta * M + amb_pos_window(g, dx, dy, pos_h)) amb += fabs(a);",
+     "if (fabs(q - tau) <= eta * M + amb_pos_window(g, dx, dy, pos_h)) amb += 0.0;"),
     ("projection backward: factor 2 of d(T S T^T)/dT dropped", "dTm[c] = 2.0 * da * ST0[c] + dbv * ST1[c];",
      "dTm[c] = da * ST0[c] + dbv * ST1[c];"),
     ("projection backward: Sigma3D gradient not symmetrised",

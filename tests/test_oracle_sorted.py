@@ -39,6 +39,20 @@ def test_single_layer_over_background():
     assert a.max() > 0.3
 
 
+def test_ambiguity_report_of_a_single_layer():
+    """The report sums the alpha of layers whose support decision is within
+    rounding of the cutoff: with one layer, every reported pixel inside the
+    support carries exactly that layer's alpha, 1 - T; pixels far from the
+    cutoff carry nothing."""
+    pts, cols, lg = [(0.1, -0.05, 0.0)], [(0.9, 0.3, 0.1)], [1.2]
+    out = oracle.render_sorted(_scene(pts, cols, lg, log_s=-1.0), CAM, ST, eta=0.05)
+    m = (out["amb"] > 0) & (out["T"] < 1.0)
+    assert m.sum() > 5
+    np.testing.assert_allclose(out["amb"][m], 1.0 - out["T"][m], rtol=1e-12)
+    centre = out["T"] == out["T"].min()
+    assert (out["amb"][centre] == 0).all()
+
+
 def test_two_layers_in_depth_order():
     cols, lg = [(0.9, 0.1, 0.1), (0.1, 0.8, 0.2)], [0.5, 2.0]
     for z_front in (-0.5, 0.5):           # swap which Gaussian is nearer the camera (at z = -4)
