@@ -144,11 +144,14 @@ def results(tmp_path_factory):
     jobs = [("renderer", i, m) for i, m in enumerate(RENDERER_CASES)] + \
            [("training", i, m) for i, m in enumerate(TRAINING_CASES)]
 
+    # the temporary directories are made here, in one thread (pytest's
+    # temporary-directory factory is not safe to call from several threads)
+    dirs = {(kind, i): tmp_path_factory.mktemp(f"{kind}{i}") for kind, i, _ in jobs}
+
     def run(job):
         kind, i, (_, old, new) = job
-        tmp = tmp_path_factory.mktemp(f"{kind}{i}")
         fn = _run_renderer_copy if kind == "renderer" else _run_training_copy
-        return (kind, i), fn(tmp / "copy", old, new)
+        return (kind, i), fn(dirs[(kind, i)] / "copy", old, new)
 
     with concurrent.futures.ThreadPoolExecutor(max_workers=4) as pool:
         return dict(pool.map(run, jobs))
