@@ -62,6 +62,9 @@ MUTATIONS = [
      "num[3 * o] += a * g->rgb[1];"),
     ("box-restricted mode: magnitude sum drops the absolute value", "aden[o] += fabs(a);", "aden[o] += a;"),
     ("ambiguity report: colour distance dropped", "sc += a * md;", "sc += a;"),
+    ("ambiguity report: centre-rounding window a quarter too narrow",
+     "return ldexp(gx * (fabs(dx) + pos_h) + gy * (fabs(dy) + pos_h), -24);",
+     "return ldexp(gx * (fabs(dx) + pos_h) + gy * (fabs(dy) + pos_h), -26);"),
     ("OIT strict mode: coverage without the clamp", "pc *= 1.0 - clampd(g->u * G, 0.0, 1.0);",
      "pc *= 1.0 - g->u * G;"),
     ("sorted blending: ambiguity report dropped",

@@ -353,6 +353,53 @@ def test_ambiguity_report_weighs_each_pair_by_its_colour_distance():
     assert (r["amb_c"][~m] == 0).all()
 
 
+def test_a_support_flip_from_the_float32_centre_is_reported():
+    """The renderer forms a splat's centre relative to its tile's centre in
+    float32 (the integer part exact, the fraction rounded once).  A pair is
+    built whose exact q lies just above tau while q from that rounded centre
+    lies below it (the rest of the arithmetic exact): the report's centre
+    term (pos_h = half a tile) must flag the pixel, and without it (pos_h = 0,
+    eta = 0) nothing is flagged.  The shift is two thirds of the reported
+    window here, so a window a quarter as wide would miss it."""
+    T, px, py, x = 16, 50, 31, -0.56
+    cam = ws.look_at_camera((0.0, 0.0, -4.0), 64, 64)
+    st = ws.Settings(weight_kind="exp", opacity_mode="logit", bg=(0.2, 0.7, 0.4), tau=9.0)
+    f32 = np.float32
+
+    def scene(ls):
+        return scene_from([(x, 0.013, 0.0)], log_scales=np.full(1, ls), logit=np.array([1.0]))
+
+    def q_exact_and_rounded(ls):
+        p = oracle.project(scene(ls), cam, st)
+        (A, B, C), (mux, muy) = p["conic"][0], p["mu"][0]
+
+        def offset(mu, pix):                      # pixel centre minus the float32 centre
+            o, tc = np.floor(mu), (pix // T) * T + T / 2
+            return (pix + 0.5 - tc) - float(f32(f32(o - tc) + f32(mu - o)))
+
+        q = lambda dx, dy: A * dx * dx + 2 * B * dx * dy + C * dy * dy  # noqa: E731
+        return q(px + 0.5 - mux, py + 0.5 - muy), q(offset(mux, px), offset(muy, py))
+
+    # bisect the log-scale so that the exact q sits halfway across the shift
+    a, b = -3.0, 0.5
+    g = lambda ls: sum(q_exact_and_rounded(ls)) / 2 - st.tau  # noqa: E731
+    ga = g(a)
+    for _ in range(80):
+        m = 0.5 * (a + b)
+        if (g(m) > 0) == (ga > 0):
+            a, ga = m, g(m)
+        else:
+            b = m
+    ls = 0.5 * (a + b)
+    q, qr = q_exact_and_rounded(ls)
+    assert (q <= st.tau) != (qr <= st.tau)            # the rounded centre flips the decision
+    assert abs(qr - q) > 5e-7
+    with_term = oracle.render(scene(ls), cam, st, eta=0.0, pos_h=T / 2)
+    without = oracle.render(scene(ls), cam, st, eta=0.0, pos_h=0.0)
+    assert with_term["amb"][py, px] > 0
+    assert without["amb"][py, px] == 0
+
+
 def test_denominator_magnitude_counts_negative_amplitudes():
     """abs_den = |w_B| + sum |a| (the conditioning report of Eq. 7's
     denominator), against a brute-force sum, in both evaluation modes, on a
