@@ -172,7 +172,9 @@ int32_t wsr_project(const wsr_scene* scene, const wsr_camera* cams, int32_t n_vi
 int64_t wsr_pair_bytes(void);
 
 /* Step a6 (Sec. 4.1): build per-tile lists of Gaussian ids for every view,
- * with no depth key (Eq. 7 is a commutative sum, so order is irrelevant).
+ * with no depth key (Eq. 7 is a commutative sum, so no order is needed).
+ * Each list holds its ids in increasing order, so the lists, and with them
+ * every float sum of the later steps, are the same from run to run.
  * `pairs` is a DEVICE buffer of capacity * wsr_pair_bytes() bytes, aligned
  * to 256 bytes, that holds one entry per (tile, Gaussian) pair: the id lists
  * and the per-pair scratch of the backward.  It is owned by the caller and
@@ -200,8 +202,8 @@ int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params
  * DEVICE [n_views][n][9]) receives the per-(view, Gaussian) gradient with
  * respect to (mu_x, mu_y, A, B, C, r, g, b, a) where (A, B, C) is the conic
  * (q = A dx^2 + 2B dx dy + C dy^2) and a = u w the amplitude.  No atomics:
- * every sum is formed in a fixed order, so for given inputs (dL_drgb, rgb,
- * den and the binning) the result does not vary from run to run. */
+ * every sum is formed in a fixed order, so for given inputs the result does
+ * not vary from run to run (nor does that of the forward or the binning). */
 int32_t wsr_render_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views,
                        const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
                        void* pairs, int64_t capacity, const float* dL_drgb, const float* rgb,
@@ -244,7 +246,7 @@ int32_t wsr_check(const void* ws, int64_t ws_bytes, void* stream);
  * skipping layers with alpha_i < alpha_min and stopping a pixel once its
  * transmittance falls below t_min (0 and 0 give Eq. 6 exactly; 1/255 and
  * 1e-4 are the usual 3D Gaussian Splatting settings).  Forward only. */
-#define WSR_SORT_MAX 8192
+#define WSR_SORT_MAX 16384
 
 typedef struct {
     float alpha_max;   /* opacity clamp, (0, 1] */

@@ -46,7 +46,7 @@ class WsrParams(C.Structure):
 FLAG_UNNORMALISED = 1
 FLAG_OIT = 2
 WSR_ERR_TILE_LIST = 5
-SORT_MAX = 8192
+SORT_MAX = 16384
 
 
 class WsrBlend(C.Structure):

@@ -158,8 +158,7 @@ int32_t wsr_bin(const wsr_camera* cams, int32_t n_views, const wsr_params* param
   Layout L;
   if (!make_layout(n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
   if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
-  return to_status(launch_bin(L, ws, pairs, capacity, (params->flags & WSR_FLAG_OIT) != 0,
-                              static_cast<hipStream_t>(stream)));
+  return to_status(launch_bin(L, ws, pairs, capacity, static_cast<hipStream_t>(stream)));
 }
 
 int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,

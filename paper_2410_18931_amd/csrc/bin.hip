@@ -11,12 +11,14 @@
 //      over the blocks, and the tile's total; tile_scan_single scans the
 //      totals into the start of every tile's list (tile_start).
 //   3. bin_pass<scatter>: the same blocks re-expand their pairs and place ids
-//      at tile_start[t] + M[v][b][t] + an LDS-atomic cursor.
+//      at tile_start[t] + M[v][b][t] + the pair's stable rank in the block.
 // Pairs are expanded load-balanced: per round of 256 Gaussians a block-wide
 // scan of the pair counts lets every thread take every 256th pair, so one
-// huge splat does not serialise on one thread.  The order of ids inside a
-// tile is irrelevant to the sums (and the sums are order-insensitive up to
-// float rounding).
+// huge splat does not serialise on one thread.  The scatter is stable: every
+// tile's list holds its Gaussian ids in increasing order, whatever the
+// timing of the run.  Eq. 7 does not need an order, but the float sums of
+// the raster stages follow the list order, so a fixed order makes the whole
+// path reproducible bit for bit.
 //
 // The same step also lays out the backward's per-pair scratch: every
 // (view, Gaussian) gets a contiguous range of "Gaussian-major" slots, one per
@@ -90,6 +92,9 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
   const int64_t g0 = static_cast<int64_t>(b) * kBinChunk;
   const int64_t g1 = min(g0 + kBinChunk, a.n);
   const uint2* rect = a.rect + static_cast<int64_t>(v) * a.n;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  // bits of a chunk-local tile index
+  const int tbits = chunk_tiles > 1 ? 32 - __clz(static_cast<uint32_t>(chunk_tiles - 1)) : 1;
   for (int64_t base = g0; base < g1; base += kBinThreads) {
     const int64_t i = base + threadIdx.x;
     uint32_t cnt = 0, x0 = 0, w = 0, y0 = 0;
@@ -112,23 +117,55 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
     s_w[threadIdx.x] = w;
     s_y0[threadIdx.x] = y0;
     __syncthreads();
-    for (uint32_t p = threadIdx.x; p < total; p += kBinThreads) {
-      // largest g with s_off[g] <= p (it has a non-zero count)
-      int lo = 0, hi = kBinThreads - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= p) lo = mid; else hi = mid - 1;
+    // pairs p0 .. p0 + 255 of the round, in Gaussian-major order (a
+    // Gaussian's tiles row-major), one per thread
+    for (uint32_t p0 = 0; p0 < total; p0 += kBinThreads) {
+      const uint32_t p = p0 + threadIdx.x;
+      const bool valid = p < total;
+      uint32_t t = 0;
+      int lo = 0;
+      if (valid) {
+        // largest g with s_off[g] <= p (it has a non-zero count)
+        int hi = kBinThreads - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t local = p - s_off[lo];
+        const uint32_t ww = s_w[lo];
+        const uint32_t ty = s_y0[lo] + local / ww;
+        const uint32_t tx = s_x0[lo] + local % ww;
+        t = (ty - ry0) * tiles_x + tx;
       }
-      const uint32_t local = p - s_off[lo];
-      const uint32_t ww = s_w[lo];
-      const uint32_t ty = s_y0[lo] + local / ww;
-      const uint32_t tx = s_x0[lo] + local % ww;
-      const uint32_t t = (ty - ry0) * tiles_x + tx;
       if (!SCATTER) {
-        atomicAdd(&lds[t], 1u);
-      } else {
-        const uint32_t pos = atomicAdd(&lds[t], 1u);
-        if (pos < a.capacity) a.ids[pos] = static_cast<uint32_t>(base + lo);
+        if (valid) atomicAdd(&lds[t], 1u);
+        continue;
+      }
+      // Stable rank: the lanes of this wave holding the same tile are those
+      // that agree with this lane on every bit of the tile index (one ballot
+      // per bit); among them, lower lanes hold earlier pairs.
+      const uint64_t vmask = __ballot(valid);
+      uint64_t peers = vmask;
+      for (int k = 0; k < tbits; ++k) {
+        const bool bit = ((t >> k) & 1u) != 0u;
+        const uint64_t bm = __ballot(valid && bit);
+        if (bm != 0ull && bm != vmask) peers &= bit ? bm : ~bm;
+      }
+      const uint32_t rank = static_cast<uint32_t>(__popcll(peers & ((1ull << lane) - 1ull)));
+      const uint32_t grp = static_cast<uint32_t>(__popcll(peers));
+      const bool last = (peers >> lane) == 1ull;  // highest lane of its group
+      // The waves place their pairs in turn (wave order is pair order): each
+      // reads its tiles' cursors, and the last lane of a group advances its
+      // tile's cursor past the group.
+#pragma unroll
+      for (int turn = 0; turn < kBinThreads / kWave; ++turn) {
+        if (wv == turn && valid) {
+          const uint32_t start = lds[t];
+          const uint32_t pos = start + rank;
+          if (pos < a.capacity) a.ids[pos] = static_cast<uint32_t>(base + lo);
+          if (last) lds[t] = start + grp;
+        }
+        __syncthreads();
       }
     }
     __syncthreads();
@@ -365,7 +402,7 @@ __global__ __launch_bounds__(1024) void scan_parts(uint32_t* parts, int64_t npar
 
 }  // namespace
 
-hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, bool oit, hipStream_t st) {
+hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, hipStream_t st) {
   DevFlags* flags = at<DevFlags>(ws, L.off_flags);
   uint32_t* hist = at<uint32_t>(ws, L.off_hist);
   uint32_t* parts = at<uint32_t>(ws, L.off_scan);
@@ -394,11 +431,7 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
   const size_t lds = static_cast<size_t>(a.rows_per_chunk) * L.max_tiles_x * sizeof(uint32_t);
   const dim3 grid(static_cast<unsigned>(L.nblk), static_cast<unsigned>(nchunks), static_cast<unsigned>(L.nv));
 
-  // split-tile accumulators of the forward raster start at zero
-  hipError_t e = launch_fill_zero(at<float>(ws, L.off_acc), sizeof(float) * 4 * L.total_pixels, st);
-  if (e != hipSuccess) return e;
-  if (oit && (e = launch_fill_zero(at<float>(ws, L.off_acclog), sizeof(float) * L.total_pixels, st)) != hipSuccess)
-    return e;
+  hipError_t e;
   bin_pass<false><<<grid, kBinThreads, lds, st>>>(a);
   column_scan_wide<<<static_cast<unsigned>((L.total_tiles + 1 + kWave - 1) / kWave), kColWaves * kWave, 0, st>>>(
       a.cams, L.nv, L.nblk, L.total_tiles, hist, tstart);

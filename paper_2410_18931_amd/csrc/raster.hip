@@ -163,10 +163,16 @@ struct RasterArgs {
   const float* den;
   float3* part;           // per-pair partial 2D gradients, 3 float3 per slot
   float* tilepart;
-  // work items (see tile_scan_single) and the split-tile accumulator
+  // work items (see tile_scan_single); the split-tile partial sums of the
+  // forward: item 0 of a split tile in the per-pixel accumulator, item k > 0
+  // of the tile with first item i0 at slot i0 - tile + k - 1 of split4 (and
+  // splitlog for Eq. 2's coverage), [split_slots][T * T]
   const uint32_t* items;
   int64_t total_tiles;
   float* acc;
+  float4* split4;
+  float* splitlog;
+  int64_t split_slots;
   // OIT (Eq. 2): per pixel (weighted average, coverage P) from the forward,
   // the split-tile accumulator of ln P and the per-pair partial dL/du
   float4* oit;
@@ -397,14 +403,22 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
   if (COUNT) atomicAdd(a.out_count + pix, cntp);
   if (c.nk > 1) {
-    // split tile: partial sums, normalised by raster_fwd_finalize (the
-    // coverage products of the parts multiply, so their logarithms add)
-    float* ac = a.acc + 4 * pix;
-    unsafeAtomicAdd(ac, nr);
-    unsafeAtomicAdd(ac + 1, ng);
-    unsafeAtomicAdd(ac + 2, nb);
-    unsafeAtomicAdd(ac + 3, dd);
-    if (OIT) unsafeAtomicAdd(a.acclog + pix, __logf(cov));
+    // split tile: this item's partial sums, added in item order by
+    // raster_fwd_finalize (the coverage products of the parts multiply, so
+    // their logarithms add).  Item 0 stores into the per-pixel accumulator,
+    // item k > 0 into its own slot of the split-tile partials.
+    const float4 sums = make_float4(nr, ng, nb, dd);
+    if (c.k == 0) {
+      reinterpret_cast<float4*>(a.acc)[pix] = sums;
+      if (OIT) a.acclog[pix] = __logf(cov);
+    } else {
+      const int64_t e = static_cast<int64_t>(a.items[c.tile]) - c.tile + c.k - 1;
+      if (e < a.split_slots) {
+        const int64_t q = e * (T * T) + (c.py - c.ty * T) * T + (c.px - c.tx * T);
+        a.split4[q] = sums;
+        if (OIT) a.splitlog[q] = __logf(cov);
+      }
+    }
     return;
   }
   if (OIT)
@@ -414,30 +428,40 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
 }
 
 // Normalisation of the tiles whose list was split over several work items:
-// their partial sums were accumulated in `acc`, which is cleared again here.
+// the items' partial sums are added in item order (item 0's from the
+// per-pixel accumulator, the others' from their slots), so the image does
+// not depend on the order in which the items ran.
 template <int T, bool OIT>
 __global__ __launch_bounds__(256) void raster_fwd_finalize(RasterArgs a) {
   const int64_t t = blockIdx.x;
-  if (a.items[t + 1] - a.items[t] <= 1) return;
+  const uint32_t i0 = a.items[t], nk = a.items[t + 1] - i0;
+  if (nk <= 1) return;
   const int tile = static_cast<int>(t);
   const int v = find_view(a.cams, a.nv, tile);
   const DevCamera& cam = a.cams[v];
   const int local = tile - cam.tile_base;
   const int tx = local % cam.tiles_x, ty = local / cam.tiles_x;
+  const int64_t e0 = static_cast<int64_t>(i0) - t;  // slot of the tile's item 1
   for (int q = threadIdx.x; q < T * T; q += 256) {
     const int px = tx * T + q % T, py = ty * T + q / T;
     if (px >= cam.width || py >= cam.height) continue;
     const int64_t pix = cam.pix_base + static_cast<int64_t>(py) * cam.width + px;
-    float4* ac = reinterpret_cast<float4*>(a.acc) + pix;
-    const float4 s = *ac;
-    *ac = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (OIT) {
-      const float lg = a.acclog[pix];
-      a.acclog[pix] = 0.f;
-      write_pixel_oit(a, pix, s.x, s.y, s.z, s.w, __expf(lg));
-    } else {
-      write_pixel(a, pix, s.x, s.y, s.z, s.w);
+    float4 s = reinterpret_cast<const float4*>(a.acc)[pix];
+    float lg = OIT ? a.acclog[pix] : 0.f;
+    for (uint32_t k = 1; k < nk; ++k) {
+      const int64_t e = e0 + k - 1;
+      if (e >= a.split_slots) break;
+      const float4 x = a.split4[e * (T * T) + q];
+      s.x += x.x;
+      s.y += x.y;
+      s.z += x.z;
+      s.w += x.w;
+      if (OIT) lg += a.splitlog[e * (T * T) + q];
     }
+    if (OIT)
+      write_pixel_oit(a, pix, s.x, s.y, s.z, s.w, __expf(lg));
+    else
+      write_pixel(a, pix, s.x, s.y, s.z, s.w);
   }
 }
 
@@ -1083,6 +1107,14 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   a.items = at<uint32_t>(ws, L.off_items);
   a.total_tiles = L.total_tiles;
   a.acc = at<float>(ws, L.off_acc);
+  // The forward's split-tile slots live in the pair buffer's partial-gradient
+  // region, which the raster backward fills only later.  A tile of l pairs
+  // has ceil(l / kItemSplats) - 1 items beyond its first, so at most
+  // (capacity - 1) / kItemSplats slots exist; their T^2 x 20 bytes each fit
+  // in the region's 36 bytes per pair for every tile size (T <= 32).
+  a.split_slots = capacity > 0 ? (capacity - 1) / kItemSplats : 0;
+  a.split4 = reinterpret_cast<float4*>(pv.part);
+  a.splitlog = reinterpret_cast<float*>(a.split4 + a.split_slots * L.tile * L.tile);
   a.oit = at<float4>(ws, L.off_oit);
   a.acclog = at<float>(ws, L.off_acclog);
   a.du = pv.du;

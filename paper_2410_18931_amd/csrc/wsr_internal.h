@@ -84,8 +84,8 @@ struct DevFlags {
 };
 
 // Longest tile list the per-tile depth sort of the sorted-blending baseline
-// holds in LDS (64-bit keys, 64 KB).
-constexpr int kSortMax = 8192;
+// holds in LDS (64-bit keys, 128 KB of the 160 KB a gfx950 workgroup may use).
+constexpr int kSortMax = 16384;
 
 struct Layout {
   int64_t n = 0;
@@ -161,7 +161,7 @@ hipError_t launch_project(const wsr_scene* sc, const wsr_params* P, const float*
                           const Layout& L, void* ws, float* out_proj, hipStream_t st);
 hipError_t launch_upload_cameras(const DevCamera* dc, int32_t nv, void* ws, const Layout& L,
                                  hipStream_t st);
-hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, bool oit, hipStream_t st);
+hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, hipStream_t st);
 hipError_t launch_raster_fwd(const Layout& L, void* ws, const void* pairs, int64_t capacity,
                              const wsr_params* P, const float* globals, float* out_rgb,
                              float* out_den, int32_t* out_count, hipStream_t st);

@@ -98,6 +98,13 @@ def unambiguous(ref) -> np.ndarray:
     return (ref["amb_c"] == 0)[..., None].astype(np.float32)
 
 
+def seeded_normal_like(t: torch.Tensor, seed: int) -> torch.Tensor:
+    """Standard normal values of ``t``'s shape from a seeded numpy generator
+    (the same numbers on every run, whatever ran before), on ``t``'s device."""
+    r = np.random.default_rng([int(seed), 4321]).standard_normal(tuple(t.shape)).astype(np.float32)
+    return torch.from_numpy(r).to(t.device)
+
+
 def grads_to_numpy(g: dict) -> dict:
     return {k: v.detach().cpu().numpy() for k, v in g.items()}
 

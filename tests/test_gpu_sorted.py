@@ -94,11 +94,39 @@ def test_sorted_multi_view_uneven_sizes():
         _compare(to_views(ctx, rgb)[v], to_views(ctx, T)[v], ref, f"view {v}")
 
 
+def test_c3_sorted_densest_crop_or_limit_reported():
+    """The densest configuration (1.2 M Gaussians in 32 blobs, 1080p): every
+    tile list either fits the per-tile sort, and the densest crop matches the
+    reference, or the limit is reported by wsr_check (never a silently
+    unsorted image)."""
+    sc, cams, st = ws.make_scene("c3")
+    st = st.copy(weight_kind="dir")
+    log("case: c3 sorted densest crop")
+    ctx0 = WSRContext(sc["means"].shape[1], cams, st)
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    _, _, cnt = ctx0.forward(dev, g, count=True)
+    x0, y0, x1, y1 = densest_crop(to_views(ctx0, cnt)[0])
+    del ctx0
+    ctx = WSRContext(sc["means"].shape[1], cams, st)
+    ctx.project(dev, g)
+    ctx.bin(grow=True)
+    rgb, T = ctx.render_sorted(g)
+    try:
+        ctx.check()
+    except _lib.WsrError as e:
+        assert e.status == _lib.WSR_ERR_TILE_LIST
+        log(f"c3: a tile list is longer than {_lib.SORT_MAX}: reported")
+        return
+    ref = oracle.render_sorted(sc, cams[0], st, crop=(x0, y0, x1, y1), **amb_kw(st))
+    _compare(to_views(ctx, rgb)[0][y0:y1, x0:x1], to_views(ctx, T)[0][y0:y1, x0:x1], ref, "c3 crop")
+
+
 def test_tile_list_longer_than_the_sort_limit_is_reported():
-    """9,000 small splats at one point all land in the same tiles: longer than
-    the per-tile sort takes, which wsr_check reports."""
+    """More small splats than the per-tile sort takes, all at one point, land
+    in the same tiles: wsr_check reports the limit."""
     rng = np.random.default_rng(5)
-    n = 9000
+    n = _lib.SORT_MAX + 800
     sc, cams, st = ws.make_scene("c1", n=n)
     sc["means"] = (rng.normal(0, 1e-3, (3, n))).astype(sc["means"].dtype)
     sc["log_scales"] = np.full((3, n), -4.0, dtype=sc["log_scales"].dtype)
