@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define WSR_ABI_VERSION 3
+#define WSR_ABI_VERSION 4
 #define WSR_MAX_VIEWS 256
 
 typedef enum {
@@ -55,7 +55,8 @@ typedef enum {
     WSR_ERR_WORKSPACE = 2,   /* workspace smaller than wsr_workspace_bytes */
     WSR_ERR_CAPACITY = 3,    /* per-tile list overflow (device flag) */
     WSR_ERR_HIP = 4,         /* a HIP runtime call failed */
-    WSR_ERR_TILE_LIST = 5    /* a tile list longer than wsr_sort_tiles takes (device flag) */
+    WSR_ERR_TILE_LIST = 5,   /* a tile list longer than wsr_sort_tiles takes (device flag) */
+    WSR_ERR_STATIC = 6       /* larger than an allocation-free entry point's static workspace */
 } wsr_status;
 
 /* Depth weight w(d) of Sec. 4.2: Eq. 8 (DIR, w = 1), Eq. 9 (EXP,
@@ -294,6 +295,27 @@ int64_t wsr_loss_workspace_bytes(const wsr_camera* cams, int32_t n_views);
  * WSR_ERR_WORKSPACE if ws_bytes is too small. */
 int32_t wsr_loss(const wsr_camera* cams, int32_t n_views, const float* img, const float* target, float lambda,
                  void* ws, int64_t ws_bytes, float* loss, float* dL_dimg, void* stream);
+
+/* Size in bytes of the static workspace of wsr_loss_noalloc, per device:
+ * 72 MiB, enough for one 1920 x 1080 view (wsr_loss_workspace_bytes of
+ * such a camera is 74,845,440 bytes). */
+#define WSR_LOSS_STATIC_BYTES (72ll << 20)
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc: wsr_loss without a workspace argument.  Same arguments,
+ * results and errors as wsr_loss (the same kernels), but the workspace is a
+ * static device array of WSR_LOSS_STATIC_BYTES bytes that the library holds
+ * on every device it runs on until the process ends.  Calls on the current
+ * device (`stream` must belong to it); nothing is allocated or freed.
+ * Returns WSR_ERR_STATIC, before anything is enqueued, when
+ * wsr_loss_workspace_bytes(cams, n_views) exceeds WSR_LOSS_STATIC_BYTES
+ * (about 2.09 M pixels in all).  Every call on a device shares that
+ * device's array, which keeps the last call's contents (each call writes
+ * every byte it reads first, so nothing needs clearing): calls that overlap
+ * on one device, on any streams, race and must be ordered by the caller. */
+int32_t wsr_loss_noalloc(const wsr_camera* cams, int32_t n_views, const float* img, const float* target,
+                         float lambda, float* loss, float* dL_dimg, void* stream);
 
 /* One Adam update (Kingma and Ba 2015, with bias correction) of n DEVICE
  * floats in place: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,

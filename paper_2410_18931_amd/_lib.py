@@ -17,11 +17,11 @@ WEIGHT_KINDS = {"dir": 0, "exp": 1, "lc": 2}
 OPACITY_MODES = {"logit": 0, "sh": 1}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 MAX_VIEWS = 256
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 EXPORTED = ("wsr_abi_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_pair_bytes", "wsr_project", "wsr_bin",
             "wsr_render_fwd", "wsr_render_bwd", "wsr_raster_bwd", "wsr_project_bwd", "wsr_pair_count",
-            "wsr_check", "wsr_loss_workspace_bytes", "wsr_loss", "wsr_adam", "wsr_sort_tiles",
+            "wsr_check", "wsr_loss_workspace_bytes", "wsr_loss", "wsr_loss_noalloc", "wsr_adam", "wsr_sort_tiles",
             "wsr_render_sorted")
 
 
@@ -46,6 +46,8 @@ class WsrParams(C.Structure):
 FLAG_UNNORMALISED = 1
 FLAG_OIT = 2
 WSR_ERR_TILE_LIST = 5
+WSR_ERR_STATIC = 6
+LOSS_STATIC_BYTES = 72 << 20
 SORT_MAX = 16384
 
 
@@ -105,6 +107,8 @@ def load():
     lib.wsr_loss_workspace_bytes.argtypes = [P, I32]
     lib.wsr_loss.restype = I32
     lib.wsr_loss.argtypes = [P, I32, P, P, F, P, I64, P, P, P]
+    lib.wsr_loss_noalloc.restype = I32
+    lib.wsr_loss_noalloc.argtypes = [P, I32, P, P, F, P, P, P]
     lib.wsr_adam.restype = I32
     lib.wsr_adam.argtypes = [P, P, P, P, I64, I32, F, F, F, F, P]
     lib.wsr_sort_tiles.restype = I32

@@ -122,6 +122,7 @@ const char* wsr_status_string(int32_t status) {
     case WSR_ERR_CAPACITY: return "per-tile id list overflow";
     case WSR_ERR_HIP: return "HIP runtime error";
     case WSR_ERR_TILE_LIST: return "tile list longer than the per-tile sort takes";
+    case WSR_ERR_STATIC: return "request larger than the static workspace of an allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -298,6 +299,18 @@ int32_t wsr_loss(const wsr_camera* cams, int32_t n_views, const float* img, cons
   if (!(lambda >= 0.f && lambda <= 1.f)) return WSR_ERR_INVALID;
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return WSR_ERR_INVALID;
   if (ws_bytes < loss_workspace_bytes(cams, n_views)) return WSR_ERR_WORKSPACE;
+  const hipError_t e = launch_loss(cams, n_views, img, target, lambda, ws, loss, dL_dimg,
+                                   static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? WSR_OK : WSR_ERR_HIP;
+}
+
+int32_t wsr_loss_noalloc(const wsr_camera* cams, int32_t n_views, const float* img, const float* target,
+                         float lambda, float* loss, float* dL_dimg, void* stream) {
+  if (!loss_cams_ok(cams, n_views) || !img || !target || !loss || !dL_dimg) return WSR_ERR_INVALID;
+  if (!(lambda >= 0.f && lambda <= 1.f)) return WSR_ERR_INVALID;
+  if (loss_workspace_bytes(cams, n_views) > static_cast<int64_t>(WSR_LOSS_STATIC_BYTES)) return WSR_ERR_STATIC;
+  void* ws = nullptr;
+  if (loss_static_workspace(&ws) != hipSuccess) return WSR_ERR_HIP;
   const hipError_t e = launch_loss(cams, n_views, img, target, lambda, ws, loss, dL_dimg,
                                    static_cast<hipStream_t>(stream));
   return e == hipSuccess ? WSR_OK : WSR_ERR_HIP;

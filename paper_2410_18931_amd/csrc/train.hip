@@ -19,8 +19,17 @@
 //   loss_pass2: the three derivative maps filtered again -> dL/dx.
 // The tile shares are summed in FP64 in a fixed order (loss_finalize).
 #include <cmath>
+#include <mutex>
 
 #include "wsr_internal.h"
+
+// Workspace of the allocation-free loss entry point: the derivative maps and
+// per-tile shares of wsr_loss, in a device array of fixed size.  Every device
+// the library runs on holds its own copy until the process ends.  In host
+// code this name stands for a host-side shadow, not a device address: host
+// code uses only the address hipGetSymbolAddress returns for the current
+// device (loss_static_workspace).
+static __device__ __align__(256) unsigned char scratch[WSR_LOSS_STATIC_BYTES];
 
 namespace wsr {
 namespace {
@@ -318,6 +327,31 @@ hipError_t launch_loss(const wsr_camera* cams, int32_t nv, const float* img, con
   }
   loss_finalize<<<1, 256, 0, st>>>(a.part, static_cast<int64_t>(tile0) * 3, loss);
   return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t loss_static_workspace(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0) return hipErrorInvalidValue;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int32_t step, float lr, float b1,

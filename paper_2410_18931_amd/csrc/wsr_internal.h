@@ -181,6 +181,9 @@ hipError_t launch_loss(const wsr_camera* cams, int32_t nv, const float* img, con
                        void* ws, float* loss, float* dL, hipStream_t st);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int32_t step, float lr, float b1,
                        float b2, float eps, hipStream_t st);
+// Address of the allocation-free loss's static workspace on the current
+// device (WSR_LOSS_STATIC_BYTES bytes, 256-byte aligned).
+hipError_t loss_static_workspace(void** out);
 // Upper bound of the raster work items for an id list of `capacity` entries.
 inline int64_t max_raster_items(const Layout& L, int64_t capacity) {
   return L.total_tiles + (capacity + kItemSplats - 1) / kItemSplats;

@@ -55,6 +55,17 @@ class Loss:
         return self.value, dL
 
 
+def loss_noalloc(cams_c, n_views: int, img: torch.Tensor, target: torch.Tensor, lam: float, loss: torch.Tensor,
+                 dL: torch.Tensor) -> None:
+    """wsr_loss_noalloc: the loss and its gradient into the caller's ``loss``
+    [1] and ``dL`` [P][3], with the library's static workspace (nothing is
+    allocated)."""
+    lib = _lib.load()
+    st = lib.wsr_loss_noalloc(cams_c, int(n_views), _ptr(img), _ptr(target), C.c_float(lam), _ptr(loss), _ptr(dL),
+                              _stream())
+    _lib.check("wsr_loss_noalloc", st)
+
+
 def adam_(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
           beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15) -> None:
     """In-place Adam update of a contiguous float32 device tensor."""

@@ -114,6 +114,17 @@ def test_loss_and_adam_reject_bad_arguments_before_launch():
     assert lib.wsr_loss(cc, 1, dummy, dummy, F(1.5), dummy, need, dummy, dummy, None) == INV
     assert lib.wsr_loss(cc, 1, None, dummy, F(0.2), dummy, need, dummy, dummy, None) == INV
     assert lib.wsr_loss(cc, 1, dummy, dummy, F(0.2), C.c_void_p(0x1004), need, dummy, dummy, None) == INV
+    # the allocation-free variant: the same checks, and a request beyond its
+    # static workspace refused before any device call
+    assert lib.wsr_loss_noalloc(cc, 1, None, dummy, F(0.2), dummy, dummy, None) == INV
+    assert lib.wsr_loss_noalloc(cc, 1, dummy, dummy, F(-0.1), dummy, dummy, None) == INV
+    assert lib.wsr_loss_noalloc(cc, 0, dummy, dummy, F(0.2), dummy, dummy, None) == INV
+    big = _lib.make_cameras([ws.look_at_camera((0.0, 0.0, -4.0), 1920, 1090)])
+    assert lib.wsr_loss_workspace_bytes(big, 1) > _lib.LOSS_STATIC_BYTES
+    assert lib.wsr_loss_noalloc(big, 1, dummy, dummy, F(0.2), dummy, dummy, None) == _lib.WSR_ERR_STATIC
+    hd = _lib.make_cameras([ws.look_at_camera((0.0, 0.0, -4.0), 1920, 1080)])
+    assert lib.wsr_loss_workspace_bytes(hd, 1) <= _lib.LOSS_STATIC_BYTES
+    assert "static" in _lib.status_string(_lib.WSR_ERR_STATIC)
     assert lib.wsr_adam(dummy, dummy, dummy, dummy, 10, 0, F(0.1), F(0.9), F(0.999), F(1e-15), None) == INV
     assert lib.wsr_adam(dummy, dummy, dummy, dummy, 10, 1, F(0.1), F(1.0), F(0.999), F(1e-15), None) == INV
     assert lib.wsr_adam(None, dummy, dummy, dummy, 10, 1, F(0.1), F(0.9), F(0.999), F(1e-15), None) == INV
