@@ -91,6 +91,7 @@ typedef struct {
     double rgb[3];
     double u, w, depth;
     double cut;       /* pairs with q <= cut contribute (tau, or less with the early-out) */
+    double u_mag;     /* magnitude of the terms of u: |offset| + sum_k |H_k Y_k| (SH opacity), or u */
     double Y[ORA_MAX_K];
 } proj_t;
 
@@ -273,9 +274,11 @@ static void project_one(const ora_scene *S, const ora_camera *cam, const ora_par
             o->rgb[c] = o->raw[c] > 0.0 ? o->raw[c] : 0.0;
         } else if (S->opacity_mode == 1) {
             o->u = acc + P->opacity_offset; /* view-dependent opacity, not clamped */
+            o->u_mag = fabs(P->opacity_offset);
+            for (int k = 0; k < K; ++k) o->u_mag += fabs(S->sh[(k * n + i) * 4 + c] * o->Y[k]);
         }
     }
-    if (S->opacity_mode == 0) o->u = 1.0 / (1.0 + exp(-S->opacity_logit[i]));
+    if (S->opacity_mode == 0) o->u = o->u_mag = 1.0 / (1.0 + exp(-S->opacity_logit[i]));
 
     if (P->weight_kind == 0) {
         o->w = 1.0;
@@ -452,11 +455,8 @@ static double amb_pos_window(const proj_t *g, double dx, double dy, double pos_h
  *   out_amb [h][w]    sum of |a| over the pairs whose support decision a
  *                     float32 evaluation of q may flip:
  *                     |q - cut| <= eta * M + amb_pos_window(..., pos_h)
- *                     (+ 10 eta (|cut| + 1) where the early-out lowers the
- *                     cutoff below tau, for the float32 rounding of the
- *                     cutoff itself; parity unpinned: no test fixes the size
- *                     of this allowance, the GPU tests only bound how many
- *                     pixels it reports)
+ *                     (+ cut_window(g) where the early-out lowers the
+ *                     cutoff below tau, see there)
  *                     with M = A dx^2 + 2|B dx dy| + C dy^2, the magnitude of
  *                     the terms q sums (rounding error scales with M, not q,
  *                     because the terms cancel for elongated splats); pos_h
@@ -468,6 +468,19 @@ static double amb_pos_window(const proj_t *g, double dx, double dy, double pos_h
  *   out_cnt [h][w]    number of pairs with q <= tau
  * Any output pointer may be NULL.
  */
+/* Where the early-out lowers a Gaussian's cutoff below tau, the renderer
+ * evaluates u and 2 ln(u / alpha_cut) in double precision, then rounds the
+ * cutoff to float32 once and multiplies it by a float32 constant (the scale
+ * its q carries too): each rounding moves it by at most 2^-24 of its size,
+ * so the cutoff it compares with lies within 2^-23 |cut| of the exact one.
+ * The second term bounds the difference of two double-precision
+ * evaluations of u (2^-38 of the magnitude of its terms, relative to u,
+ * orders of magnitude above double rounding). */
+static double cut_window(const proj_t *g)
+{
+    return 0x1p-23 * fabs(g->cut) + 0x1p-38 * (1.0 + g->u_mag / fabs(g->u));
+}
+
 void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                 int64_t x0, int64_t y0, int64_t x1, int64_t y1, int32_t mode, double eta, double pos_h,
                 double *out_C, double *out_num, double *out_den, double *out_amb,
@@ -547,7 +560,11 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
     for (int64_t o = 0; o < w * h; ++o) {
         if (P->oit) {
             /* Eq. 2 with c_0 = c_B: coverage-weighted blend of the weighted
-             * average over the background (no w_B term) */
+             * average over the background (no w_B term).  The average takes
+             * Eq. 7's amplitudes u w G with the unclamped opacity of Sec. 4.3
+             * (num, den); the coverage takes alpha = u G clamped to [0, 1]
+             * (cov), so that it stays a transmittance.  Eq. 2 has one alpha
+             * in both places; the two coincide for opacities in [0, 1]. */
             const double D = den[o];
             for (int c = 0; c < 3; ++c) {
                 const double avg = (D != 0.0) ? num[3 * o + c] / D : 0.0;
@@ -589,7 +606,7 @@ void ora_render(const ora_scene *S, const ora_camera *cam, const ora_params *P,
                     const double M = g->conic[0] * dx * dx + 2.0 * fabs(g->conic[1] * dx * dy) +
                                      g->conic[2] * dy * dy;
                     const double win = eta * M + amb_pos_window(g, dx, dy, pos_h) +
-                                       (g->cut < tau ? 10.0 * eta * (fabs(g->cut) + 1.0) : 0.0);
+                                       (g->cut < tau ? cut_window(g) : 0.0);
                     if (fabs(q - g->cut) <= win) {
                         const double a = fabs(g->u * g->w * exp(-0.5 * q));
                         double md = 0.0;

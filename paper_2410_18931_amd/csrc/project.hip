@@ -111,11 +111,25 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
 
       // ---- opacity early-out (App. D; off with alpha_cut = 0): a pair
       // contributes only while u exp(-q/2) >= alpha_cut, i.e. while
-      // q <= 2 ln(u / alpha_cut); a Gaussian with u <= alpha_cut never does
+      // q <= 2 ln(u / alpha_cut); a Gaussian with u <= alpha_cut never does.
+      // The cutoff is a support decision, so u is evaluated again in double
+      // precision for it (the float32 u above carries the SH sum's rounding,
+      // which would move the cutoff by far more than the float rounding of
+      // q); the only float32 step left is the rounding of the cutoff itself.
       double cut = a.tau;
       if (a.alpha_cut > 0.f) {
-        alive = u > a.alpha_cut;
-        if (alive) cut = fmin(cut, 2.0 * log(static_cast<double>(u) / static_cast<double>(a.alpha_cut)));
+        double u64;
+        if (a.opa_mode == WSR_OPACITY_SH) {
+          double Y64[K];
+          sh_eval_f64<DEG>(dir[0], dir[1], dir[2], Y64);
+          u64 = a.opacity_offset;
+#pragma unroll
+          for (int k = 0; k < K; ++k) u64 = fma(static_cast<double>(coef[k].w), Y64[k], u64);
+        } else {
+          u64 = 1.0 / (1.0 + exp(-static_cast<double>(logit)));
+        }
+        alive = u64 > a.alpha_cut;
+        if (alive) cut = fmin(cut, 2.0 * log(u64 / static_cast<double>(a.alpha_cut)));
       }
       // ---- support box of q <= cut, widened so float rounding of q never
       // reaches a pixel outside it ----

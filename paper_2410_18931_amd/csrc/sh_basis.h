@@ -49,6 +49,40 @@ __device__ inline void sh_eval(float x, float y, float z, float* Y) {
   }
 }
 
+// The same basis in double precision, for the opacity early-out's cutoff
+// (a support decision, where a float32 opacity would move the cutoff by
+// more than float rounding of q).
+template <int DEG>
+__device__ inline void sh_eval_f64(double x, double y, double z, double* Y) {
+  Y[0] = 0.28209479177387814;
+  if constexpr (DEG >= 1) {
+    const double c1 = 0.48860251190291992;
+    Y[1] = c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = c1 * x;
+  }
+  if constexpr (DEG >= 2) {
+    const double x2 = x * x, y2 = y * y, z2 = z * z;
+    const double a = 1.0925484305920792, b = 0.31539156525252005, c = 0.54627421529603959;
+    Y[4] = a * x * y;
+    Y[5] = a * y * z;
+    Y[6] = b * (2.0 * z2 - x2 - y2);
+    Y[7] = a * x * z;
+    Y[8] = c * (x2 - y2);
+    if constexpr (DEG >= 3) {
+      const double e = 0.59004358992664352, f = 2.8906114426405538, g = 0.45704579946446572,
+                   h = 0.37317633259011540, k = 1.4453057213202769;
+      Y[9] = e * y * (3.0 * x2 - y2);
+      Y[10] = f * x * y * z;
+      Y[11] = g * y * (4.0 * z2 - x2 - y2);
+      Y[12] = h * z * (2.0 * z2 - 3.0 * x2 - 3.0 * y2);
+      Y[13] = g * x * (4.0 * z2 - x2 - y2);
+      Y[14] = k * z * (x2 - y2);
+      Y[15] = e * x * (x2 - 3.0 * y2);
+    }
+  }
+}
+
 // G[k] = (dY_k/dx, dY_k/dy, dY_k/dz) of the polynomials above.
 template <int DEG>
 __device__ inline void sh_eval_grad(float x, float y, float z, float3* G) {

@@ -7,6 +7,7 @@ import numpy as np
 
 import oracle
 import wsr_synth as ws
+from tests.oracle_helpers import scene_from
 
 CUT = 0.08
 
@@ -90,3 +91,66 @@ def test_early_out_backward_matches_central_differences():
             assert abs(fd - g[name].reshape(-1)[j]) <= 1e-6 * max(1.0, abs(fd)), (name, j)
             checked += abs(fd) > 1e-4
     assert checked > 10
+
+
+def test_a_support_flip_from_the_float32_early_out_cutoff_is_reported():
+    """The renderer evaluates an early-out cutoff 2 ln(u / alpha_cut) in double
+    precision, rounds it to float32 once and multiplies it by a float32
+    constant (the scale q carries too).  A Gaussian is chosen (over float32
+    logits) whose two roundings move the cutoff by more than half of the
+    report's window 2^-23 |cut|; a pixel whose exact q lies between the exact
+    and the rounded cutoff, whose decision therefore flips, must be reported
+    (with eta = 0 and no centre term, only the cutoff term covers it), and a
+    pixel at 1.5 windows from the cutoff must not be.  So the window is
+    neither a quarter as wide nor ten times as wide."""
+    f32 = np.float32
+    k32 = f32(0.72134752044448170)                # log2(e) / 2 as the renderer holds it
+    alpha = float(f32(0.05))
+    st = ws.Settings(weight_kind="dir", opacity_mode="logit", tau=9.0, alpha_cut=alpha)
+    cam = ws.look_at_camera((0.0, 0.0, -4.0), 32, 32)
+    px, py = 19, 16
+
+    def cutoffs(logit):
+        u = 1.0 / (1.0 + np.exp(-float(logit)))
+        cut = 2.0 * np.log(u / alpha)
+        eff = float(f32(f32(cut) * k32)) / float(k32)   # what the renderer compares q with
+        return cut, eff
+
+    chosen = None
+    for logit in f32(np.linspace(-1.5, 3.0, 40001)):
+        cut, eff = cutoffs(logit)
+        if 0.5 < cut < st.tau and abs(eff - cut) > 0.55 * 2.0 ** -23 * cut:
+            chosen = logit
+            break
+    assert chosen is not None
+    cut, eff = cutoffs(chosen)
+    win = 2.0 ** -23 * cut
+
+    def scene(ls):
+        return scene_from([(0.0, 0.0, 0.0)], log_scales=np.full(1, ls), logit=np.array([chosen]))
+
+    def q_at(ls):
+        p = oracle.project(scene(ls), cam, st)
+        assert abs(p["cut"][0] - cut) <= 1e-12 * cut
+        (A, B, C), (mux, muy) = p["conic"][0], p["mu"][0]
+        dx, dy = px + 0.5 - mux, py + 0.5 - muy
+        return A * dx * dx + 2 * B * dx * dy + C * dy * dy
+
+    def log_scale_for(target):
+        a, b = -4.0, 0.5                          # q falls as the splat grows
+        for _ in range(200):
+            m = 0.5 * (a + b)
+            if q_at(m) > target:
+                a = m
+            else:
+                b = m
+        return 0.5 * (a + b)
+
+    flip = log_scale_for(0.5 * (cut + eff))
+    q = q_at(flip)
+    assert (q <= cut) != (q <= eff)               # the rounded cutoff flips the decision
+    assert abs(q - cut) <= win
+    far = log_scale_for(cut + 1.5 * win * np.sign(eff - cut))
+    assert abs(q_at(far) - cut) > win
+    assert oracle.render(scene(flip), cam, st, eta=0.0, pos_h=0.0)["amb"][py, px] > 0
+    assert oracle.render(scene(far), cam, st, eta=0.0, pos_h=0.0)["amb"][py, px] == 0

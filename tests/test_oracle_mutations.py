@@ -65,6 +65,10 @@ MUTATIONS = [
     ("ambiguity report: centre-rounding window a quarter too narrow",
      "return ldexp(gx * (fabs(dx) + pos_h) + gy * (fabs(dy) + pos_h), -24);",
      "return ldexp(gx * (fabs(dx) + pos_h) + gy * (fabs(dy) + pos_h), -26);"),
+    ("early-out report: cutoff-rounding window a quarter as wide",
+     "return 0x1p-23 * fabs(g->cut)", "return 0x1p-25 * fabs(g->cut)"),
+    ("early-out report: cutoff-rounding window ten times as wide",
+     "return 0x1p-23 * fabs(g->cut)", "return 10.0 * 0x1p-23 * fabs(g->cut)"),
     ("OIT strict mode: coverage without the clamp", "pc *= 1.0 - clampd(g->u * G, 0.0, 1.0);",
      "pc *= 1.0 - g->u * G;"),
     ("sorted blending: ambiguity report dropped",
