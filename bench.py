@@ -8,6 +8,7 @@ one 1920x1080 camera.  Inputs are resident in HBM before timing starts.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--tile 16]
                     [--storage f32|f16|bf16] [--no-cpu-baseline]
+                    [--config c4 --graph --autotune --per-view --errors]
 
 Prints one JSON line.  Per-kernel durations come from HIP events recorded on
 the stream the kernels run on.
@@ -105,6 +106,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU baseline sample")
     ap.add_argument("--graph", action="store_true", help="time replays of the whole step captured as one HIP graph")
+    ap.add_argument("--batch", type=int, default=0, help="raster records staged per LDS batch (0: default)")
+    ap.add_argument("--persistent", action="store_true", help="raster stages as persistent grids")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick tile, batch and launch form with the autotuner first (overrides --tile/--batch)")
+    ap.add_argument("--per-view", action="store_true",
+                    help="also time the plain FP32 path view by view (one fwd+bwd step per view, eager)")
+    ap.add_argument("--errors", action="store_true",
+                    help="also report image and gradient errors against the FP64 checker on the densest "
+                         "64x64 crops of two views (and against the FP32 source with 16-bit storage)")
     ap.add_argument("--oit", action="store_true", help="weighted-blended OIT (Eq. 2) instead of Eq. 7")
     ap.add_argument("--alpha-cut", type=float, default=0.0,
                     help="opacity early-out threshold (0: off); the line then also reports the image error "
@@ -160,6 +170,111 @@ def cpu_baseline(scene, cams, settings, seconds: float) -> dict:
             "sample": f"FP64 C checker (strict all-pairs mode), forward+backward on {done} full-width strips of "
                       f"{h} rows ({done * h} of {H} rows, seeded random positions) of the same frame, "
                       f"{dt:.1f} s; frames/s = sampled fraction / time"}
+
+
+def per_view_fp32(scene, cams, settings, args) -> dict:
+    """The plain path the batched line is compared with: FP32 attribute
+    storage, tile 16, default batch, one fwd+bwd step per view (each view its
+    own projection, binning, raster and backward), eager launches; the time
+    of one pass over all views."""
+    import torch
+
+    from paper_2410_18931_amd import WSRContext, globals_tensor, scene_to_device
+    st = settings.copy(tile=16, batch=0, persistent=False)
+    n = scene["means"].shape[1]
+    dev = scene_to_device(scene, storage="f32")
+    g = globals_tensor(st)
+    steps = []
+    for cam in cams:
+        ctx = WSRContext(n, [cam], st)
+        ctx.forward(dev, g)
+        ctx._alloc_pairs(int(ctx.last_pairs * 1.1) + 1024)
+        rgb = torch.empty((ctx.total_pixels, 3), device="cuda")
+        den = torch.empty((ctx.total_pixels,), device="cuda")
+        dL = torch.randn((ctx.total_pixels, 3), generator=torch.Generator(device="cuda").manual_seed(1),
+                         device="cuda")
+        grads = ctx.alloc_grads(dev)
+        steps.append((ctx, rgb, den, dL, grads))
+
+    def one_pass():
+        for ctx, rgb, den, dL, grads in steps:
+            ctx.project(dev, g)
+            ctx.bin(grow=False)
+            ctx.render_fwd(g, out=(rgb, den))
+            ctx.render_bwd(dev, g, dL, rgb, den, grads=grads)
+
+    for _ in range(max(1, args.warmup)):
+        one_pass()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(1, args.steps // 4)
+    e0.record()
+    for _ in range(reps):
+        one_pass()
+    e1.record()
+    torch.cuda.synchronize()
+    for ctx, *_ in steps:
+        ctx.check()
+    ms = e0.elapsed_time(e1) / reps
+    return {"ms_per_pass": round(ms, 4), "views": len(cams), "views_per_s": round(len(cams) * 1e3 / ms, 2),
+            "what": "FP32 storage, tile 16, one eager fwd+bwd step per view"}
+
+
+def checker_errors(scene, cams, settings, storage: str, ctx, dev, g) -> dict:
+    """Image and gradient errors of this line's configuration against the FP64
+    checker, on the densest 64x64 crop of two views: images (max-abs over the
+    pixels whose support decisions are not within float32 rounding of a
+    cutoff, and the count of those), gradients through both crops (max |err|
+    relative to the tensor's max |ref|).  With 16-bit storage, against the
+    checker on the dequantised inputs (the kernels' arithmetic) and on the
+    FP32 source (the storage rounding included)."""
+    import torch
+
+    import oracle
+    import wsr_synth as ws
+    rgb, den, cnt = ctx.forward(dev, g, count=True)
+    views = [0, len(cams) // 2] if len(cams) > 1 else [0]
+    imgs, counts = ctx.views(rgb), ctx.views(cnt)
+    src = {"dequantised": ws.quantise(scene, storage)["f32"], "fp32_source": scene} if storage != "f32" else \
+        {"fp32_source": scene}
+    crops, dLs = {}, []
+    rng = np.random.default_rng(17)
+    for v, cam in enumerate(cams):
+        r = np.zeros((cam["height"], cam["width"], 3), np.float32)
+        if v in views:
+            c = counts[v].cpu().numpy()
+            H, W = c.shape
+            s = 64
+            cs = np.cumsum(np.cumsum(np.pad(c.astype(np.int64), ((1, 0), (1, 0))), 0), 1)
+            tot = cs[s:, s:] - cs[:-s, s:] - cs[s:, :-s] + cs[:-s, :-s]
+            y, x = np.unravel_index(np.argmax(tot), tot.shape)
+            crops[v] = (int(x), int(y), int(x) + s, int(y) + s)
+            amb = oracle.render(src.get("dequantised", scene), cam, settings, crop=crops[v], eta=1e-6,
+                                pos_h=settings.tile / 2)["amb_c"] > 0
+            r[y:y + s, x:x + s] = rng.standard_normal((s, s, 3)) * (~amb)[..., None]
+        dLs.append(r)
+    dL = torch.cat([torch.from_numpy(r.reshape(-1, 3)) for r in dLs]).cuda()
+    gg = {k: v.detach().cpu().numpy() for k, v in ctx.render_bwd(dev, g, dL, rgb, den).items()}
+    keys = ["means", "log_scales", "quats", "sh"] + (["lc_v"] if settings.weight_kind == "lc" else []) + \
+        (["opacity_logit"] if settings.opacity_mode == "logit" else [])
+    out = {"crops": {str(v): crops[v] for v in views}}
+    for name, sc in src.items():
+        print(f"# checker errors: {name}", file=sys.stderr, flush=True)
+        img_err, amb_px = 0.0, 0
+        for v in views:
+            x0, y0, x1, y1 = crops[v]
+            ref = oracle.render(sc, cams[v], settings, crop=crops[v], eta=1e-6, pos_h=settings.tile / 2)
+            e = np.abs(imgs[v][y0:y1, x0:x1].cpu().numpy().astype(np.float64) - ref["C"]).max(axis=-1)
+            clean = ref["amb_c"] == 0
+            img_err = max(img_err, float(e[clean].max()))
+            amb_px += int((~clean).sum())
+        gref = oracle.render_bwd_views(sc, [cams[v] for v in views], settings,
+                                       [dLs[v][crops[v][1]:crops[v][3], crops[v][0]:crops[v][2]] for v in views],
+                                       [crops[v] for v in views])
+        rel = {k: float(np.abs(gg[k] - gref[k]).max() / max(np.abs(gref[k]).max(), 1e-30)) for k in keys}
+        out[name] = {"image_max_abs": img_err, "ambiguous_px": amb_px, "grad_rel_to_max": rel,
+                     "grad_rel_to_max_worst": max(rel.values())}
+    return out
 
 
 def bench_train(args) -> None:
@@ -350,10 +465,20 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     scene, cams, st = ws.make_scene(args.config)
-    st = st.copy(tile=args.tile, alpha_cut=args.alpha_cut, oit=args.oit)
+    st = st.copy(tile=args.tile, alpha_cut=args.alpha_cut, oit=args.oit, batch=args.batch,
+                 persistent=args.persistent)
     n = scene["means"].shape[1]
     dev = scene_to_device(scene, storage=args.storage)
     g = globals_tensor(st)
+    tuned = None
+    if args.autotune:
+        import tempfile
+        from paper_2410_18931_amd.autotune import autotune
+        with tempfile.TemporaryDirectory() as tmp:
+            tuned = autotune(dev, cams, st, g, reps=5, cache=os.path.join(tmp, "tune.json"))
+        st = st.copy(tile=tuned["tile"], batch=tuned["batch"], persistent=tuned["persistent"])
+        args.tile = tuned["tile"]
+        print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
     ctx = WSRContext(n, cams, st)
     P = ctx.total_pixels
     rgb = torch.empty((P, 3), dtype=torch.float32, device="cuda")
@@ -453,12 +578,14 @@ def main():
         "config": {"workload": f"{args.config}: {n:,} Gaussians, " + (
                        f"one {cams[0]['width']}x{cams[0]['height']} view" if ctx.nv == 1 else
                        f"{ctx.nv} views of uneven size, {P:,} px in total") +
-                       f", tile {args.tile}, {args.storage} attribute storage" +
+                       f", tile {args.tile}" + (f", batch {st.batch}" if st.batch else "") +
+                       (", persistent raster grids" if st.persistent else "") +
+                       f", {args.storage} attribute storage" +
                        (f", opacity early-out at {args.alpha_cut:g}" if args.alpha_cut > 0 else "") +
                        (", weighted-blended OIT (Eq. 2)" if args.oit else "") +
                        (", whole step replayed as one HIP graph" if args.graph else ""),
                    "gaussians": n, "views": ctx.nv, "pixels": P, "tile": args.tile, "storage": args.storage,
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "batch": st.batch, "persistent": bool(st.persistent)},
         "equivalent_1080p_frames_per_s": round(P / (ms * 1e-3) / 2073600.0, 3),
         "eager_ms_per_step": round(eager_ms, 4),
         "gaussian_pixel_evals_per_s": pairs / (ms * 1e-3),
@@ -473,6 +600,14 @@ def main():
                      "launch_ms": round(stage_ms[dominant], 4), "algorithmic_bytes": ab[dominant]},
         "stage_hbm_gbs": {k: round(ab[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in names},
     }
+    if tuned is not None:
+        out["autotune"] = {"tile": tuned["tile"], "batch": tuned["batch"], "persistent": tuned["persistent"],
+                           "ms": tuned["ms"]}
+    if args.per_view:
+        out["per_view_fp32"] = per_view_fp32(scene, cams, st, args)
+        out["per_view_fp32"]["speedup_of_this_line"] = round(out["per_view_fp32"]["ms_per_pass"] / ms, 3)
+    if args.errors:
+        out["errors_vs_checker"] = checker_errors(scene, cams, st, args.storage, ctx, dev, g)
     if args.alpha_cut > 0:
         exact = WSRContext(n, cams, st.copy(alpha_cut=0.0))
         rgb_exact, _ = exact.forward(dev, g)

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define WSR_ABI_VERSION 4
+#define WSR_ABI_VERSION 5
 #define WSR_MAX_VIEWS 256
 
 typedef enum {
@@ -103,7 +103,11 @@ typedef struct {
  * alpha_cut > 0 enables the opacity early-out that App. D proposes: a pair
  * also needs u exp(-q/2) >= alpha_cut (so q <= 2 ln(u / alpha_cut)), and a
  * Gaussian with u <= alpha_cut is culled.  It changes the image (opt-in);
- * 0 turns it off.  The sorted-blending entry points require 0. */
+ * 0 turns it off.  The sorted-blending entry points require 0.
+ * batch is the number of splat records the raster stages in LDS per batch
+ * (a tuning choice; the sums are the same): 0 for the default (64 for tile
+ * 8, 256 otherwise), or 64 (tiles 8 and 16), 128 or 256 (tiles 16 and 32);
+ * other values are WSR_ERR_INVALID. */
 typedef struct {
     int32_t weight_kind;       /* wsr_weight_kind */
     int32_t tile;              /* 8 | 16 | 32 */
@@ -113,6 +117,7 @@ typedef struct {
     float opacity_offset;      /* 0.5; SH opacity mode only */
     int32_t flags;             /* WSR_FLAG_* */
     float alpha_cut;           /* opacity early-out threshold, >= 0; 0 = off */
+    int32_t batch;             /* raster records staged per LDS batch; 0 = default */
 } wsr_params;
 
 /* wsr_render_fwd writes the raw sums instead of the image: out_rgb receives
@@ -131,6 +136,12 @@ typedef struct {
  * receives sum_i a_i.  Not combinable with WSR_FLAG_UNNORMALISED or
  * alpha_cut > 0, nor with the sorted-blending entry points. */
 #define WSR_FLAG_OIT 2
+
+/* Launch the raster stages as persistent grids: as many workgroups as the
+ * device holds at once, each looping over the (view, tile) work items of all
+ * views, instead of one workgroup per work item.  A scheduling choice: the
+ * results are the same bit for bit. */
+#define WSR_FLAG_PERSISTENT 4
 
 /* Learnable global parameters, a DEVICE array of 6 floats:
  * [0] sigma, [1] beta (EXP only), [2] w_B, [3..5] c_B (RGB). */

@@ -17,7 +17,7 @@ WEIGHT_KINDS = {"dir": 0, "exp": 1, "lc": 2}
 OPACITY_MODES = {"logit": 0, "sh": 1}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 MAX_VIEWS = 256
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 EXPORTED = ("wsr_abi_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_pair_bytes", "wsr_project", "wsr_bin",
             "wsr_render_fwd", "wsr_render_bwd", "wsr_raster_bwd", "wsr_project_bwd", "wsr_pair_count",
@@ -40,11 +40,12 @@ class WsrCamera(C.Structure):
 class WsrParams(C.Structure):
     _fields_ = [("weight_kind", C.c_int32), ("tile", C.c_int32), ("tau", C.c_float),
                 ("dilation", C.c_float), ("near_z", C.c_float), ("opacity_offset", C.c_float),
-                ("flags", C.c_int32), ("alpha_cut", C.c_float)]
+                ("flags", C.c_int32), ("alpha_cut", C.c_float), ("batch", C.c_int32)]
 
 
 FLAG_UNNORMALISED = 1
 FLAG_OIT = 2
+FLAG_PERSISTENT = 4
 WSR_ERR_TILE_LIST = 5
 WSR_ERR_STATIC = 6
 LOSS_STATIC_BYTES = 72 << 20
@@ -144,6 +145,8 @@ def make_cameras(cams) -> "C.Array":
 def make_params(settings, flags: int = 0) -> WsrParams:
     if getattr(settings, "oit", False):
         flags |= FLAG_OIT
+    if getattr(settings, "persistent", False):
+        flags |= FLAG_PERSISTENT
     return WsrParams(WEIGHT_KINDS[settings.weight_kind], int(settings.tile), float(settings.tau),
                      float(settings.dilation), float(settings.near), float(settings.opacity_offset), int(flags),
-                     float(getattr(settings, "alpha_cut", 0.0)))
+                     float(getattr(settings, "alpha_cut", 0.0)), int(getattr(settings, "batch", 0)))

@@ -1,11 +1,15 @@
-"""Tile-size autotuner for the WSR path.
+"""Launch autotuner for the WSR path.
 
 For a scene and a camera set it captures one forward + backward step per
-candidate tile size (8, 16, 32) as a HIP graph, times replays with HIP events
-and keeps the fastest.  Results are cached in a JSON file keyed by the
-problem's shape class: Gaussian count (rounded to 2 significant digits),
-number of views, total pixels (rounded likewise), attribute storage type, SH
-degree, weight and opacity modes.
+candidate launch configuration as a HIP graph, times replays with HIP events
+and keeps the fastest.  The candidates are every tile size (8, 16, 32), every
+raster batch the tile size is built for (splat records staged in LDS per
+batch: 64 for tile 8; 64, 128, 256 for tile 16; 128, 256 for tile 32) and both
+raster launch forms (one workgroup per work item, or a persistent grid).
+Results are cached in a JSON file keyed by the problem's shape class:
+Gaussian count (rounded to 2 significant digits), number of views, total
+pixels (rounded likewise), attribute storage type, SH degree, weight and
+opacity modes.
 """
 from __future__ import annotations
 
@@ -20,6 +24,16 @@ from .render import WSRContext
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "wsr_autotune.json")
 TILES = (8, 16, 32)
+BATCHES = {8: (64,), 16: (64, 128, 256), 32: (128, 256)}
+
+
+def candidates(tiles=TILES, persistent=(False, True)) -> list:
+    """(tile, batch, persistent) launch configurations to time."""
+    return [(t, b, p) for t in tiles for b in BATCHES[t] for p in persistent]
+
+
+def config_name(tile: int, batch: int, persistent: bool) -> str:
+    return f"{tile}/{batch}/{'persistent' if persistent else 'grid'}"
 
 
 def _round2(x: int) -> int:
@@ -47,8 +61,10 @@ def _load(path):
 
 
 def autotune(scene: dict, cams: list, settings, globals_: torch.Tensor, dL: torch.Tensor | None = None,
-             tiles=TILES, reps: int = 10, cache: str | None = DEFAULT_CACHE, force: bool = False) -> dict:
-    """Return {"tile": best, "ms": {tile: ms per fwd+bwd step}, "key": ...}.
+             tiles=TILES, persistent=(False, True), reps: int = 10, cache: str | None = DEFAULT_CACHE,
+             force: bool = False) -> dict:
+    """Return {"tile", "batch", "persistent": the fastest configuration,
+    "ms": {"tile/batch/grid|persistent": ms per fwd+bwd step}, "key": ...}.
     ``scene`` holds device tensors (see ``render.scene_to_device``)."""
     key = shape_key(scene, cams, settings)
     if cache and not force:
@@ -57,8 +73,8 @@ def autotune(scene: dict, cams: list, settings, globals_: torch.Tensor, dL: torc
             return dict(hit, key=key, cached=True)
     n = scene["means"].shape[1]
     times = {}
-    for t in tiles:
-        st = settings.copy(tile=t)
+    for t, b, p in candidates(tiles, persistent):
+        st = settings.copy(tile=t, batch=b, persistent=p)
         ctx = WSRContext(n, cams, st)
         step = GraphStep(ctx, scene, globals_, dL)
         step.replay()
@@ -70,10 +86,11 @@ def autotune(scene: dict, cams: list, settings, globals_: torch.Tensor, dL: torc
         e1.record()
         torch.cuda.synchronize()
         step.check()
-        times[t] = e0.elapsed_time(e1) / reps
+        times[(t, b, p)] = e0.elapsed_time(e1) / reps
         del step, ctx
-    best = min(times, key=times.get)
-    res = {"tile": int(best), "ms": {str(k): round(v, 4) for k, v in times.items()}}
+    t, b, p = min(times, key=times.get)
+    res = {"tile": int(t), "batch": int(b), "persistent": bool(p),
+           "ms": {config_name(*k): round(v, 4) for k, v in times.items()}}
     if cache:
         os.makedirs(os.path.dirname(cache), exist_ok=True)
         data = _load(cache)

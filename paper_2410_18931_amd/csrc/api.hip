@@ -65,6 +65,7 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   size_t off = 0;
   L->off_cams = off;     off = align256(off + sizeof(DevCamera) * WSR_MAX_VIEWS);
   L->off_flags = off;    off = align256(off + sizeof(DevFlags));
+  L->off_queue = off;    off = align256(off + sizeof(uint32_t) * 2);
   L->off_rec = off;      off = align256(off + sizeof(DevSplat) * slots);
   L->off_rect = off;     off = align256(off + sizeof(uint2) * slots);
   L->off_hist = off;     off = align256(off + sizeof(uint32_t) * (hist + 1));
@@ -100,12 +101,22 @@ bool scene_ok(const wsr_scene* s, int32_t weight_kind) {
   return true;
 }
 
+// Raster batch sizes each tile size is built for (0 picks the default).
+bool batch_ok(int32_t tile, int32_t batch) {
+  if (batch == 0) return true;
+  if (tile == 8) return batch == 64;
+  if (tile == 16) return batch == 64 || batch == 128 || batch == 256;
+  return batch == 128 || batch == 256;
+}
+
 bool params_ok(const wsr_params* p) {
   return p && p->weight_kind >= WSR_WEIGHT_DIR && p->weight_kind <= WSR_WEIGHT_LC &&
          (p->tile == 8 || p->tile == 16 || p->tile == 32) && std::isfinite(p->tau) && p->tau >= 0.f &&
          std::isfinite(p->dilation) && std::isfinite(p->near_z) && std::isfinite(p->alpha_cut) &&
-         p->alpha_cut >= 0.f && (p->flags & ~(WSR_FLAG_UNNORMALISED | WSR_FLAG_OIT)) == 0 &&
-         (!(p->flags & WSR_FLAG_OIT) || ((p->flags & WSR_FLAG_UNNORMALISED) == 0 && p->alpha_cut == 0.f));
+         p->alpha_cut >= 0.f &&
+         (p->flags & ~(WSR_FLAG_UNNORMALISED | WSR_FLAG_OIT | WSR_FLAG_PERSISTENT)) == 0 &&
+         (!(p->flags & WSR_FLAG_OIT) || ((p->flags & WSR_FLAG_UNNORMALISED) == 0 && p->alpha_cut == 0.f)) &&
+         batch_ok(p->tile, p->batch);
 }
 
 }  // namespace

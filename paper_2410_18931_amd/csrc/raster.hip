@@ -16,7 +16,10 @@
 // walks the block.  The sums are commutative, so the list order does not
 // matter, and no per-pair data is stored between forward and backward: the
 // backward recomputes every pair.
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "wsr_internal.h"
 
@@ -178,7 +181,21 @@ struct RasterArgs {
   float4* oit;
   float* acclog;
   float* du;
+  // persistent launches: the counter the workgroups take work items from
+  // (zeroed before the launch); null for one workgroup per work item
+  uint32_t* queue;
 };
+
+// The first work item of this workgroup (first = true) or the one after
+// `item`: with a queue the next unclaimed item, taken by thread 0 and shared
+// through LDS; otherwise blockIdx.x, then none (the grid covers every item).
+__device__ __forceinline__ uint32_t next_item(const RasterArgs& a, uint32_t* s_item, bool first, uint32_t n_items) {
+  if (!a.queue) return first ? blockIdx.x : n_items;
+  __syncthreads();  // every thread has read the previous item
+  if (threadIdx.x == 0) *s_item = atomicAdd(a.queue, 1u);
+  __syncthreads();
+  return *s_item;
+}
 
 __device__ __forceinline__ int find_view(const DevCamera* cams, int nv, int tile) {
   int v = 0;
@@ -188,7 +205,7 @@ __device__ __forceinline__ int find_view(const DevCamera* cams, int nv, int tile
 
 // Common set-up of one work item: its tile (view, tile coordinates), the
 // sub-range [start, end) of the tile's id list it covers, and this lane's
-// pixels.  Returns false for blocks beyond the last item.
+// pixels.
 template <int T>
 struct TileCtx {
   int v, tx, ty;
@@ -203,10 +220,8 @@ struct TileCtx {
 };
 
 template <int T>
-__device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, const DevCamera*& cam) {
+__device__ __forceinline__ void tile_setup(const RasterArgs& a, uint32_t item, TileCtx<T>& c, const DevCamera*& cam) {
   using G = TileGeom<T>;
-  const uint32_t item = blockIdx.x;
-  if (item >= a.items[a.total_tiles]) return false;
   // largest tile t with items[t] <= item (items is strictly increasing)
   int64_t lo = 0, hi = a.total_tiles - 1;
   while (lo < hi) {
@@ -240,7 +255,6 @@ __device__ __forceinline__ bool tile_setup(const RasterArgs& a, TileCtx<T>& c, c
   c.fy0 = c.ty * T + T / 2;
   c.px = c.bx0 + (c.lane & 7);
   c.py = c.by0 + (c.lane >> 3);
-  return true;
 }
 
 // Stage one batch of records into LDS (as StagedRec) and build this wave's
@@ -350,17 +364,11 @@ __device__ __forceinline__ const StagedRec& rec_at(const StagedRec* base, uint32
   return *reinterpret_cast<const StagedRec*>(reinterpret_cast<const char*>(base) + off);
 }
 
-// Forward.  Lists hold LDS byte offsets of the staged records.
-template <int T, bool COUNT, bool CUT, bool OIT>
-__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
-  using G = TileGeom<T>;
+// The forward of one work item (tile_setup's c), S records staged per batch.
+template <int T, int S, bool COUNT, bool CUT, bool OIT>
+__device__ __forceinline__ void raster_fwd_item(const RasterArgs& a, const TileCtx<T>& c, const DevCamera* cam,
+                                                StagedRec* s_rec, uint32_t* s_list) {
   using LT = uint32_t;
-  __shared__ StagedRec s_rec[G::kBatch];
-  __shared__ __align__(16) LT s_list[G::kWaves * G::kBatch];
-  TileCtx<T> c;
-  const DevCamera* cam;
-  if (!tile_setup<T>(a, c, cam)) return;
-
   float nr = 0.f, ng = 0.f, nb = 0.f, dd = 0.f;
   float cov = 1.f;  // OIT: prod (1 - alpha)
   int cntp = 0;
@@ -368,9 +376,9 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   const float pcx = static_cast<float>(c.px - c.fx0) + 0.5f;
   const float pcy = static_cast<float>(c.py - c.fy0) + 0.5f;
   const float tau = a.tau;
-  for (uint32_t b = c.start; b < c.end; b += G::kBatch) {
-    const int m = stage_and_cull<T, G::kBatch, false, CUT, OIT, true, LT>(a, c, b, s_rec, nullptr, s_list, nullptr);
-    const LT* list = s_list + c.wave * G::kBatch;
+  for (uint32_t b = c.start; b < c.end; b += S) {
+    const int m = stage_and_cull<T, S, false, CUT, OIT, true, LT>(a, c, b, s_rec, nullptr, s_list, nullptr);
+    const LT* list = s_list + c.wave * S;
     // four splats per step: one read fetches their list entries and all four
     // records are requested before any arithmetic, so LDS latency is paid
     // once per four splats.  The staged colour carries the amplitude.
@@ -425,6 +433,27 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
     write_pixel_oit(a, pix, nr, ng, nb, dd, cov);
   else
     write_pixel(a, pix, nr, ng, nb, dd);
+}
+
+// Forward.  Lists hold LDS byte offsets of the staged records.  S records
+// are staged per batch.  A workgroup renders the work item blockIdx.x (the
+// grid covers them all), or, persistent, claims items from a counter until
+// none is left.
+template <int T, int S, bool COUNT, bool CUT, bool OIT>
+__global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
+  using G = TileGeom<T>;
+  using LT = uint32_t;
+  __shared__ StagedRec s_rec[S];
+  __shared__ __align__(16) LT s_list[G::kWaves * S];
+  __shared__ uint32_t s_item;
+  const uint32_t n_items = a.items[a.total_tiles];
+  for (uint32_t item = next_item(a, &s_item, true, n_items); item < n_items;
+       item = next_item(a, &s_item, false, n_items)) {
+    TileCtx<T> c;
+    const DevCamera* cam;
+    tile_setup<T>(a, item, c, cam);
+    raster_fwd_item<T, S, COUNT, CUT, OIT>(a, c, cam, s_rec, s_list);
+  }
 }
 
 // Normalisation of the tiles whose list was split over several work items:
@@ -853,11 +882,13 @@ constexpr int bwd_min_blocks() {
 // tile lists the summation order is fixed, so the result does not vary from
 // run to run (the order in which a record's per-wave sums are added follows
 // the rounds that reach them, i.e. the list positions).
-template <int T, bool CUT, bool OIT>
+template <int T, int S, bool CUT, bool OIT>
 __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) void raster_bwd_kernel(
     RasterArgs a) {
   using G = TileGeom<T>;
-  constexpr int kB = G::kBatch;
+  constexpr int kB = S;  // records staged per batch (thread k < kB owns record k)
+  static_assert(kB <= G::kThreads, "every staged record needs an owner thread");
+  static_assert(kB <= 256, "the culled lists hold 8-bit record indices");
   constexpr int NV = OIT ? 10 : 9;  // sums per (tile, splat) pair
   __shared__ StagedRec s_rec[kB];
   __shared__ uint32_t s_slot[kB];
@@ -868,96 +899,102 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
   __shared__ float4 s_pd[G::kThreads];            // per-pixel factors, thread order
   __shared__ float s_pk[OIT ? G::kThreads : 1];   // OIT: per-pixel coverage factors
   __shared__ float s_bg[G::kWaves][4];
-  TileCtx<T> c;
-  const DevCamera* cam;
-  if (!tile_setup<T>(a, c, cam)) return;
+  __shared__ uint32_t s_item;
+  const uint32_t n_items = a.items[a.total_tiles];
+  for (uint32_t item = next_item(a, &s_item, true, n_items); item < n_items;
+       item = next_item(a, &s_item, false, n_items)) {
+    __syncthreads();  // the previous item is done with the shared arrays
+    TileCtx<T> c;
+    const DevCamera* cam;
+    tile_setup<T>(a, item, c, cam);
 
-  // every thread's per-pixel factors into LDS, where the chunks read them at
-  // wave-uniform (broadcast) or per-lane addresses; the tile's first work
-  // item also stores the tile's background-gradient partial sums
-  {
-    float4 pd;
-    float kcov, bacc[4];
-    pixel_factors<OIT>(a, *cam, c.px, c.py, &pd, &kcov, bacc);
-    s_pd[threadIdx.x] = pd;
-    if (OIT) s_pk[threadIdx.x] = kcov;
-    if (c.k == 0) {
+    // every thread's per-pixel factors into LDS, where the chunks read them at
+    // wave-uniform (broadcast) or per-lane addresses; the tile's first work
+    // item also stores the tile's background-gradient partial sums
+    {
+      float4 pd;
+      float kcov, bacc[4];
+      pixel_factors<OIT>(a, *cam, c.px, c.py, &pd, &kcov, bacc);
+      s_pd[threadIdx.x] = pd;
+      if (OIT) s_pk[threadIdx.x] = kcov;
+      if (c.k == 0) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float sj = wave_sum(bacc[j]);
-        if (c.lane == 0) s_bg[c.wave][j] = sj;
-      }
-      __syncthreads();
-      if (threadIdx.x < 4) {
-        float sj = 0.f;
+        for (int j = 0; j < 4; ++j) {
+          const float sj = wave_sum(bacc[j]);
+          if (c.lane == 0) s_bg[c.wave][j] = sj;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+          float sj = 0.f;
 #pragma unroll
-        for (int w = 0; w < G::kWaves; ++w) sj += s_bg[w][threadIdx.x];
-        a.tilepart[c.tile * 4 + threadIdx.x] = sj;
-      }
-    }
-  }
-  const float4* pd_wave = s_pd + c.wave * kWave;
-  const float* pk_wave = OIT ? s_pk + c.wave * kWave : nullptr;
-  const float tau = a.tau;
-  const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
-  for (uint32_t b = c.start; b < c.end; b += kB) {
-    const int m = stage_and_cull<T, kB, true, CUT, OIT, false, uint8_t>(a, c, b, s_rec, s_slot, s_list, s_pos);
-    const int cnt = static_cast<int>(min(static_cast<uint32_t>(kB), c.end - b));
-    if (c.lane == 0) s_m[c.wave] = m;
-    __syncthreads();
-    int rounds = 0;
-#pragma unroll
-    for (int w = 0; w < G::kWaves; ++w) rounds = max(rounds, (s_m[w] + kWave - 1) / kWave);
-    const uint8_t* list = s_list + c.wave * kB;
-    float acc[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = 0.f;
-    for (int r = 0; r < rounds; ++r) {
-      const int left = m - r * kWave;  // splats in this wave's chunk of the round
-      if (left > 0) {
-        const float4* pdl = pd_wave;
-        if (OIT) {
-          const float* pkl = pk_wave;
-          if (left > kWave / 2)
-            bwd_chunk_oit<T>(c, r * kWave, m, list, s_rec, pd_wave, pk_wave, s_part[c.wave], tau);
-          else if (left > kWave / 4)
-            bwd_chunk_oit_split<T, 2>(c, r * kWave, m, list, s_rec, pdl, pkl, s_part[c.wave], tau);
-          else if (left > kWave / 8)
-            bwd_chunk_oit_split<T, 4>(c, r * kWave, m, list, s_rec, pdl, pkl, s_part[c.wave], tau);
-          else
-            bwd_chunk_oit_split<T, 8>(c, r * kWave, m, list, s_rec, pdl, pkl, s_part[c.wave], tau);
-        } else {
-          if (left > kWave / 2)
-            bwd_chunk<T, CUT>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
-          else if (left > kWave / 4)
-            bwd_chunk_split<T, CUT, 2>(c, r * kWave, m, list, s_rec, pdl, s_part[c.wave], tau);
-          else if (left > kWave / 8)
-            bwd_chunk_split<T, CUT, 4>(c, r * kWave, m, list, s_rec, pdl, s_part[c.wave], tau);
-          else
-            bwd_chunk_split<T, CUT, 8>(c, r * kWave, m, list, s_rec, pdl, s_part[c.wave], tau);
+          for (int w = 0; w < G::kWaves; ++w) sj += s_bg[w][threadIdx.x];
+          a.tilepart[c.tile * 4 + threadIdx.x] = sj;
         }
       }
+    }
+    const float4* pd_wave = s_pd + c.wave * kWave;
+    const float* pk_wave = OIT ? s_pk + c.wave * kWave : nullptr;
+    const float tau = a.tau;
+    const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
+    for (uint32_t b = c.start; b < c.end; b += kB) {
+      const int m = stage_and_cull<T, kB, true, CUT, OIT, false, uint8_t>(a, c, b, s_rec, s_slot, s_list, s_pos);
+      const int cnt = static_cast<int>(min(static_cast<uint32_t>(kB), c.end - b));
+      if (c.lane == 0) s_m[c.wave] = m;
       __syncthreads();
-      if (own < cnt) {
+      int rounds = 0;
 #pragma unroll
-        for (int w = 0; w < G::kWaves; ++w) {
-          const int p = s_pos[w * kB + own];  // 0xffff: culled by wave w
-          if ((p >> 6) == r) {
+      for (int w = 0; w < G::kWaves; ++w) rounds = max(rounds, (s_m[w] + kWave - 1) / kWave);
+      const uint8_t* list = s_list + c.wave * kB;
+      float acc[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) acc[q] += s_part[w][q][p & (kWave - 1)];
+      for (int q = 0; q < NV; ++q) acc[q] = 0.f;
+      for (int r = 0; r < rounds; ++r) {
+        const int left = m - r * kWave;  // splats in this wave's chunk of the round
+        if (left > 0) {
+          const float4* pdl = pd_wave;
+          if (OIT) {
+            const float* pkl = pk_wave;
+            if (left > kWave / 2)
+              bwd_chunk_oit<T>(c, r * kWave, m, list, s_rec, pd_wave, pk_wave, s_part[c.wave], tau);
+            else if (left > kWave / 4)
+              bwd_chunk_oit_split<T, 2>(c, r * kWave, m, list, s_rec, pdl, pkl, s_part[c.wave], tau);
+            else if (left > kWave / 8)
+              bwd_chunk_oit_split<T, 4>(c, r * kWave, m, list, s_rec, pdl, pkl, s_part[c.wave], tau);
+            else
+              bwd_chunk_oit_split<T, 8>(c, r * kWave, m, list, s_rec, pdl, pkl, s_part[c.wave], tau);
+          } else {
+            if (left > kWave / 2)
+              bwd_chunk<T, CUT>(c, r * kWave, m, list, s_rec, pd_wave, s_part[c.wave], tau);
+            else if (left > kWave / 4)
+              bwd_chunk_split<T, CUT, 2>(c, r * kWave, m, list, s_rec, pdl, s_part[c.wave], tau);
+            else if (left > kWave / 8)
+              bwd_chunk_split<T, CUT, 4>(c, r * kWave, m, list, s_rec, pdl, s_part[c.wave], tau);
+            else
+              bwd_chunk_split<T, CUT, 8>(c, r * kWave, m, list, s_rec, pdl, s_part[c.wave], tau);
           }
         }
+        __syncthreads();
+        if (own < cnt) {
+#pragma unroll
+          for (int w = 0; w < G::kWaves; ++w) {
+            const int p = s_pos[w * kB + own];  // 0xffff: culled by wave w
+            if ((p >> 6) == r) {
+#pragma unroll
+              for (int q = 0; q < NV; ++q) acc[q] += s_part[w][q][p & (kWave - 1)];
+            }
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
-    }
-    if (own < cnt) {
-      const uint32_t sl = s_slot[own];
-      if (sl < a.capacity) {
-        float3* dst = a.part + 3 * static_cast<int64_t>(sl);
-        dst[0] = make_float3(acc[0], acc[1], acc[2]);
-        dst[1] = make_float3(acc[3], acc[4], acc[5]);
-        dst[2] = make_float3(acc[6], acc[7], acc[8]);
-        if (OIT) a.du[sl] = acc[NV - 1];
+      if (own < cnt) {
+        const uint32_t sl = s_slot[own];
+        if (sl < a.capacity) {
+          float3* dst = a.part + 3 * static_cast<int64_t>(sl);
+          dst[0] = make_float3(acc[0], acc[1], acc[2]);
+          dst[1] = make_float3(acc[3], acc[4], acc[5]);
+          dst[2] = make_float3(acc[6], acc[7], acc[8]);
+          if (OIT) a.du[sl] = acc[NV - 1];
+        }
       }
     }
   }
@@ -1121,23 +1158,93 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   return a;
 }
 
-template <int T, bool CUT, bool OIT>
-void fwd_k(const RasterArgs& a, const dim3& g, bool count, hipStream_t st) {
-  if (count)
-    raster_fwd_kernel<T, true, CUT, OIT><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
-  else
-    raster_fwd_kernel<T, false, CUT, OIT><<<g, TileGeom<T>::kThreads, 0, st>>>(a);
+// Workgroups of `kernel` (with `threads` threads) the current device holds
+// at once: its compute units times the workgroups one of them can host.
+// Looked up once per kernel and device; 0 if the runtime cannot tell.
+int64_t resident_workgroups(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int64_t> known;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(kernel, dev);
+  const auto it = known.find(key);
+  if (it != known.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const int64_t r = static_cast<int64_t>(per_cu) * cus;
+  known[key] = r;
+  return r;
 }
 
-template <int T>
-hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, bool count, bool cut, bool oit, hipStream_t st) {
-  const dim3 g(static_cast<unsigned>(grid));
+// Launch a raster kernel over the work items: one workgroup per item (the
+// grid covers the upper bound of the item count; workgroups beyond the
+// actual count exit at once), or, persistent, as many workgroups as the
+// device holds at once, claiming items from `queue` (cleared here first)
+// until none is left.
+hipError_t launch_items(void (*kernel)(RasterArgs), RasterArgs a, int64_t max_items, uint32_t* queue,
+                        int threads, hipStream_t st) {
+  int64_t grid = max_items;
+  a.queue = nullptr;
+  if (queue) {
+    const int64_t r = resident_workgroups(reinterpret_cast<const void*>(kernel), threads);
+    if (r > 0 && r < grid) {
+      grid = r;
+      a.queue = queue;
+      const hipError_t e = launch_fill_zero(queue, sizeof(uint32_t), st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(grid)), dim3(threads), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int T, int S>
+hipError_t fwd_ts(const RasterArgs& a, int64_t grid, bool count, bool cut, bool oit, uint32_t* queue,
+                  hipStream_t st) {
+  constexpr int kT = TileGeom<T>::kThreads;
   if (oit)
-    fwd_k<T, false, true>(a, g, count, st);
-  else if (cut)
-    fwd_k<T, true, false>(a, g, count, st);
-  else
-    fwd_k<T, false, false>(a, g, count, st);
+    return launch_items(count ? raster_fwd_kernel<T, S, true, false, true> : raster_fwd_kernel<T, S, false, false, true>,
+                        a, grid, queue, kT, st);
+  if (cut)
+    return launch_items(count ? raster_fwd_kernel<T, S, true, true, false> : raster_fwd_kernel<T, S, false, true, false>,
+                        a, grid, queue, kT, st);
+  return launch_items(count ? raster_fwd_kernel<T, S, true, false, false> : raster_fwd_kernel<T, S, false, false, false>,
+                      a, grid, queue, kT, st);
+}
+
+template <int T, int S>
+hipError_t bwd_ts(const RasterArgs& a, int64_t grid, bool cut, bool oit, uint32_t* queue, hipStream_t st) {
+  constexpr int kT = TileGeom<T>::kThreads;
+  if (oit) return launch_items(raster_bwd_kernel<T, S, false, true>, a, grid, queue, kT, st);
+  if (cut) return launch_items(raster_bwd_kernel<T, S, true, false>, a, grid, queue, kT, st);
+  return launch_items(raster_bwd_kernel<T, S, false, false>, a, grid, queue, kT, st);
+}
+
+// Records staged per batch: tile 8 (one wave, 64 threads) stages 64; tiles
+// 16 and 32 take 64 (tile 16 only), 128 or 256 (the default).
+template <int T>
+hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, int batch, bool count, bool cut, bool oit,
+                 uint32_t* queue, hipStream_t st) {
+  hipError_t e;
+  if constexpr (T == 8) {
+    e = fwd_ts<8, 64>(a, grid, count, cut, oit, queue, st);
+  } else {
+    if (batch == 128)
+      e = fwd_ts<T, 128>(a, grid, count, cut, oit, queue, st);
+    else if (T == 16 && batch == 64)
+      e = fwd_ts<16, 64>(a, grid, count, cut, oit, queue, st);
+    else
+      e = fwd_ts<T, 256>(a, grid, count, cut, oit, queue, st);
+  }
+  if (e != hipSuccess) return e;
   if (oit)
     raster_fwd_finalize<T, true><<<dim3(static_cast<unsigned>(tiles)), 256, 0, st>>>(a);
   else
@@ -1146,16 +1253,14 @@ hipError_t fwd_t(const RasterArgs& a, int64_t grid, int64_t tiles, bool count, b
 }
 
 template <int T>
-hipError_t bwd_t(const RasterArgs& a, int64_t grid, bool cut, bool oit, hipStream_t st) {
-  const dim3 gi(static_cast<unsigned>(grid));
-  constexpr int kT = TileGeom<T>::kThreads;
-  if (oit)
-    raster_bwd_kernel<T, false, true><<<gi, kT, 0, st>>>(a);
-  else if (cut)
-    raster_bwd_kernel<T, true, false><<<gi, kT, 0, st>>>(a);
-  else
-    raster_bwd_kernel<T, false, false><<<gi, kT, 0, st>>>(a);
-  return hipGetLastError();
+hipError_t bwd_t(const RasterArgs& a, int64_t grid, int batch, bool cut, bool oit, uint32_t* queue, hipStream_t st) {
+  if constexpr (T == 8) {
+    return bwd_ts<8, 64>(a, grid, cut, oit, queue, st);
+  } else {
+    if (batch == 128) return bwd_ts<T, 128>(a, grid, cut, oit, queue, st);
+    if (T == 16 && batch == 64) return bwd_ts<16, 64>(a, grid, cut, oit, queue, st);
+    return bwd_ts<T, 256>(a, grid, cut, oit, queue, st);
+  }
 }
 
 }  // namespace
@@ -1175,10 +1280,12 @@ hipError_t launch_raster_fwd(const Layout& L, void* ws, const void* pairs, int64
   }
   const int64_t grid = max_raster_items(L, capacity);
   const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
+  uint32_t* queue = (P->flags & WSR_FLAG_PERSISTENT) ? at<uint32_t>(ws, L.off_queue) : nullptr;
+  const bool cut = P->alpha_cut > 0.f;
   switch (L.tile) {
-    case 8: return fwd_t<8>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, oit, st);
-    case 32: return fwd_t<32>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, oit, st);
-    default: return fwd_t<16>(a, grid, L.total_tiles, cnt, P->alpha_cut > 0.f, oit, st);
+    case 8: return fwd_t<8>(a, grid, L.total_tiles, P->batch, cnt, cut, oit, queue, st);
+    case 32: return fwd_t<32>(a, grid, L.total_tiles, P->batch, cnt, cut, oit, queue, st);
+    default: return fwd_t<16>(a, grid, L.total_tiles, P->batch, cnt, cut, oit, queue, st);
   }
 }
 
@@ -1193,10 +1300,12 @@ hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t cap
   a.tilepart = at<float>(ws, L.off_tilepart);
   const int64_t grid = max_raster_items(L, capacity);
   const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
+  uint32_t* queue = (P->flags & WSR_FLAG_PERSISTENT) ? at<uint32_t>(ws, L.off_queue) + 1 : nullptr;
+  const bool cut = P->alpha_cut > 0.f;
   switch (L.tile) {
-    case 8: return bwd_t<8>(a, grid, P->alpha_cut > 0.f, oit, st);
-    case 32: return bwd_t<32>(a, grid, P->alpha_cut > 0.f, oit, st);
-    default: return bwd_t<16>(a, grid, P->alpha_cut > 0.f, oit, st);
+    case 8: return bwd_t<8>(a, grid, P->batch, cut, oit, queue, st);
+    case 32: return bwd_t<32>(a, grid, P->batch, cut, oit, queue, st);
+    default: return bwd_t<16>(a, grid, P->batch, cut, oit, queue, st);
   }
 }
 

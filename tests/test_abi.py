@@ -80,6 +80,12 @@ def test_entry_points_reject_bad_arguments_before_launch():
     g = _lib.WsrGrads(dummy, dummy, dummy, dummy, dummy, dummy, None)
     assert lib.wsr_render_bwd(C.byref(scene), cc, 1, C.byref(p), dummy, dummy, 1 << 30, dummy, 10, dummy,
                               dummy, dummy, C.byref(g), None, None) == INV
+    # raster batch sizes a tile size is not built for
+    for tile, batch in ((16, 100), (8, 128), (32, 64), (16, 512)):
+        bad_batch = _lib.make_params(st.copy(tile=tile, batch=batch))
+        assert lib.wsr_bin(cc, 1, C.byref(bad_batch), 8, dummy, 1 << 30, dummy, 10, None) == INV
+    assert lib.wsr_bin(cc, 1, C.byref(_lib.make_params(st.copy(tile=8, batch=64, persistent=True))), 8, dummy,
+                       16, dummy, 10, None) == WSP     # a valid batch and flag pass the checks
     out = C.c_int64(0)
     assert lib.wsr_pair_count(None, 0, C.byref(out), None) == INV
     assert lib.wsr_check(None, 0, None) == INV

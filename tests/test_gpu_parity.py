@@ -507,18 +507,59 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
 
 
-def test_autotune_picks_a_tile_and_caches(tmp_path):
-    from paper_2410_18931_amd.autotune import autotune
+def test_autotune_picks_a_launch_configuration_and_caches(tmp_path):
+    from paper_2410_18931_amd.autotune import BATCHES, autotune, candidates, config_name
     sc, cams, st = _small_multiview()
     log("case: autotune")
     dev = scene_to_device(sc)
     g = globals_tensor(st)
     cache = str(tmp_path / "tune.json")
     r1 = autotune(dev, cams, st, g, reps=3, cache=cache)
-    assert r1["tile"] in (8, 16, 32) and not r1["cached"]
-    assert set(r1["ms"]) == {"8", "16", "32"}
+    log(f"autotune: {r1}")
+    assert r1["tile"] in (8, 16, 32) and r1["batch"] in BATCHES[r1["tile"]] and not r1["cached"]
+    assert set(r1["ms"]) == {config_name(*c) for c in candidates()} and len(r1["ms"]) == 12
     r2 = autotune(dev, cams, st, g, reps=3, cache=cache)
-    assert r2["cached"] and r2["tile"] == r1["tile"]
+    assert r2["cached"] and (r2["tile"], r2["batch"], r2["persistent"]) == (r1["tile"], r1["batch"],
+                                                                             r1["persistent"])
+
+
+@pytest.mark.parametrize("tile,batch,persistent", [(16, 64, False), (16, 128, True), (16, 256, True),
+                                                   (32, 128, False), (8, 64, True)])
+def test_launch_configurations(tile, batch, persistent):
+    """The raster batch size and the persistent launch only change how the
+    work is scheduled (the uneven multi-view batch, every view's tiles in one
+    launch).  The forward sums every pixel over its tile list in list order
+    whatever the batch, and a work item computes the same sums whichever
+    workgroup runs it, so the image equals the default launch's bit for bit,
+    and so do the gradients when only the launch form changes.  Another batch
+    size regroups the backward's chunks (a splat's pixels may then be summed
+    by several lanes), so its gradients are held to the checker's at the
+    gradient bar."""
+    sc, cams, st = _small_multiview()
+    st = st.copy(tile=tile)
+    default_batch = 64 if tile == 8 else 256
+    log(f"case: launch tile {tile} batch {batch} persistent {persistent}")
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    rs = ws.upstream_grad(cams, seed=37)
+    dL = torch.cat([torch.from_numpy(r.reshape(-1, 3)) for r in rs]).cuda()
+    outs = []
+    for s in (st, st.copy(batch=batch, persistent=persistent)):
+        ctx = WSRContext(sc["means"].shape[1], cams, s)
+        rgb, den = ctx.forward(dev, g)
+        grads = ctx.render_bwd(dev, g, dL, rgb, den)
+        torch.cuda.synchronize()
+        ctx.check()
+        outs.append((rgb, den, grads))
+    (r1, d1, g1), (r2, d2, g2) = outs
+    assert torch.equal(r1, r2) and torch.equal(d1, d2)
+    if batch == default_batch:
+        for k in g1:
+            assert torch.equal(g1[k], g2[k]), k
+    else:
+        gref = oracle.render_bwd_views(sc, cams, st, rs)
+        compare_grads(grads_to_numpy(g2), gref, _grad_keys(st, 16), label=f"batch {batch}")
+        _check_globals(g2["globals"].cpu().numpy(), _oracle_globals(st, gref["globals"]), f"batch {batch}")
 
 
 # ---------------------------------------------------------------- sharding proxy and reduced precision

@@ -83,6 +83,8 @@ class Settings:
     tile: int = 16
     alpha_cut: float = 0.0            # opacity early-out threshold (0: off)
     oit: bool = False                 # weighted-blended OIT (Eq. 2) instead of Eq. 7
+    batch: int = 0                    # raster records staged per LDS batch (0: the renderer's default)
+    persistent: bool = False          # raster stages as persistent grids
 
     def copy(self, **kw) -> "Settings":
         d = dict(self.__dict__)
