@@ -186,11 +186,9 @@ struct RasterArgs {
   uint32_t* queue;
 };
 
-// The first work item of this workgroup (first = true) or the one after
-// `item`: with a queue the next unclaimed item, taken by thread 0 and shared
-// through LDS; otherwise blockIdx.x, then none (the grid covers every item).
-__device__ __forceinline__ uint32_t next_item(const RasterArgs& a, uint32_t* s_item, bool first, uint32_t n_items) {
-  if (!a.queue) return first ? blockIdx.x : n_items;
+// A persistent workgroup's next work item: the next unclaimed one, taken
+// from the counter by thread 0 and shared through LDS.
+__device__ __forceinline__ uint32_t claim_item(const RasterArgs& a, uint32_t* s_item) {
   __syncthreads();  // every thread has read the previous item
   if (threadIdx.x == 0) *s_item = atomicAdd(a.queue, 1u);
   __syncthreads();
@@ -437,9 +435,9 @@ __device__ __forceinline__ void raster_fwd_item(const RasterArgs& a, const TileC
 
 // Forward.  Lists hold LDS byte offsets of the staged records.  S records
 // are staged per batch.  A workgroup renders the work item blockIdx.x (the
-// grid covers them all), or, persistent, claims items from a counter until
-// none is left.
-template <int T, int S, bool COUNT, bool CUT, bool OIT>
+// grid covers them all), or, PERSIST, claims items from a counter until none
+// is left.
+template <int T, int S, bool COUNT, bool CUT, bool OIT, bool PERSIST>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
   using LT = uint32_t;
@@ -447,12 +445,14 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   __shared__ __align__(16) LT s_list[G::kWaves * S];
   __shared__ uint32_t s_item;
   const uint32_t n_items = a.items[a.total_tiles];
-  for (uint32_t item = next_item(a, &s_item, true, n_items); item < n_items;
-       item = next_item(a, &s_item, false, n_items)) {
+  uint32_t item = PERSIST ? claim_item(a, &s_item) : blockIdx.x;
+  while (item < n_items) {
     TileCtx<T> c;
     const DevCamera* cam;
     tile_setup<T>(a, item, c, cam);
     raster_fwd_item<T, S, COUNT, CUT, OIT>(a, c, cam, s_rec, s_list);
+    if (!PERSIST) break;
+    item = claim_item(a, &s_item);
   }
 }
 
@@ -882,7 +882,7 @@ constexpr int bwd_min_blocks() {
 // tile lists the summation order is fixed, so the result does not vary from
 // run to run (the order in which a record's per-wave sums are added follows
 // the rounds that reach them, i.e. the list positions).
-template <int T, int S, bool CUT, bool OIT>
+template <int T, int S, bool CUT, bool OIT, bool PERSIST>
 __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) void raster_bwd_kernel(
     RasterArgs a) {
   using G = TileGeom<T>;
@@ -901,9 +901,8 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
   __shared__ float s_bg[G::kWaves][4];
   __shared__ uint32_t s_item;
   const uint32_t n_items = a.items[a.total_tiles];
-  for (uint32_t item = next_item(a, &s_item, true, n_items); item < n_items;
-       item = next_item(a, &s_item, false, n_items)) {
-    __syncthreads();  // the previous item is done with the shared arrays
+  uint32_t item = PERSIST ? claim_item(a, &s_item) : blockIdx.x;
+  while (item < n_items) {
     TileCtx<T> c;
     const DevCamera* cam;
     tile_setup<T>(a, item, c, cam);
@@ -997,6 +996,8 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
         }
       }
     }
+    if (!PERSIST) break;
+    item = claim_item(a, &s_item);  // (its first barrier: the shared arrays are free again)
   }
 }
 
@@ -1186,46 +1187,51 @@ int64_t resident_workgroups(const void* kernel, int threads) {
 
 // Launch a raster kernel over the work items: one workgroup per item (the
 // grid covers the upper bound of the item count; workgroups beyond the
-// actual count exit at once), or, persistent, as many workgroups as the
-// device holds at once, claiming items from `queue` (cleared here first)
-// until none is left.
-hipError_t launch_items(void (*kernel)(RasterArgs), RasterArgs a, int64_t max_items, uint32_t* queue,
-                        int threads, hipStream_t st) {
-  int64_t grid = max_items;
-  a.queue = nullptr;
+// actual count exit at once), or, with a queue, the persistent kernel on as
+// many workgroups as the device holds at once, claiming items from the
+// queue (cleared here first) until none is left.
+hipError_t launch_items(void (*grid_kernel)(RasterArgs), void (*persistent_kernel)(RasterArgs), RasterArgs a,
+                        int64_t max_items, uint32_t* queue, int threads, hipStream_t st) {
   if (queue) {
-    const int64_t r = resident_workgroups(reinterpret_cast<const void*>(kernel), threads);
-    if (r > 0 && r < grid) {
-      grid = r;
+    const int64_t r = resident_workgroups(reinterpret_cast<const void*>(persistent_kernel), threads);
+    if (r > 0 && r < max_items) {
       a.queue = queue;
       const hipError_t e = launch_fill_zero(queue, sizeof(uint32_t), st);
       if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(persistent_kernel, dim3(static_cast<unsigned>(r)), dim3(threads), 0, st, a);
+      return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(grid)), dim3(threads), 0, st, a);
+  a.queue = nullptr;
+  hipLaunchKernelGGL(grid_kernel, dim3(static_cast<unsigned>(max_items)), dim3(threads), 0, st, a);
   return hipGetLastError();
+}
+
+template <int T, int S, bool COUNT, bool CUT, bool OIT>
+hipError_t fwd_k(const RasterArgs& a, int64_t grid, uint32_t* queue, hipStream_t st) {
+  return launch_items(raster_fwd_kernel<T, S, COUNT, CUT, OIT, false>, raster_fwd_kernel<T, S, COUNT, CUT, OIT, true>,
+                      a, grid, queue, TileGeom<T>::kThreads, st);
 }
 
 template <int T, int S>
 hipError_t fwd_ts(const RasterArgs& a, int64_t grid, bool count, bool cut, bool oit, uint32_t* queue,
                   hipStream_t st) {
-  constexpr int kT = TileGeom<T>::kThreads;
-  if (oit)
-    return launch_items(count ? raster_fwd_kernel<T, S, true, false, true> : raster_fwd_kernel<T, S, false, false, true>,
-                        a, grid, queue, kT, st);
-  if (cut)
-    return launch_items(count ? raster_fwd_kernel<T, S, true, true, false> : raster_fwd_kernel<T, S, false, true, false>,
-                        a, grid, queue, kT, st);
-  return launch_items(count ? raster_fwd_kernel<T, S, true, false, false> : raster_fwd_kernel<T, S, false, false, false>,
-                      a, grid, queue, kT, st);
+  if (oit) return count ? fwd_k<T, S, true, false, true>(a, grid, queue, st) : fwd_k<T, S, false, false, true>(a, grid, queue, st);
+  if (cut) return count ? fwd_k<T, S, true, true, false>(a, grid, queue, st) : fwd_k<T, S, false, true, false>(a, grid, queue, st);
+  return count ? fwd_k<T, S, true, false, false>(a, grid, queue, st) : fwd_k<T, S, false, false, false>(a, grid, queue, st);
+}
+
+template <int T, int S, bool CUT, bool OIT>
+hipError_t bwd_k(const RasterArgs& a, int64_t grid, uint32_t* queue, hipStream_t st) {
+  return launch_items(raster_bwd_kernel<T, S, CUT, OIT, false>, raster_bwd_kernel<T, S, CUT, OIT, true>, a, grid,
+                      queue, TileGeom<T>::kThreads, st);
 }
 
 template <int T, int S>
 hipError_t bwd_ts(const RasterArgs& a, int64_t grid, bool cut, bool oit, uint32_t* queue, hipStream_t st) {
-  constexpr int kT = TileGeom<T>::kThreads;
-  if (oit) return launch_items(raster_bwd_kernel<T, S, false, true>, a, grid, queue, kT, st);
-  if (cut) return launch_items(raster_bwd_kernel<T, S, true, false>, a, grid, queue, kT, st);
-  return launch_items(raster_bwd_kernel<T, S, false, false>, a, grid, queue, kT, st);
+  if (oit) return bwd_k<T, S, false, true>(a, grid, queue, st);
+  if (cut) return bwd_k<T, S, true, false>(a, grid, queue, st);
+  return bwd_k<T, S, false, false>(a, grid, queue, st);
 }
 
 // Records staged per batch: tile 8 (one wave, 64 threads) stages 64; tiles
