@@ -81,8 +81,18 @@ def compare_grads(g_gpu: dict, g_ref: dict, keys, tol=GRAD_TOL, label=""):
         b = np.asarray(g_ref[k], dtype=np.float64)
         assert a.shape == b.shape, (k, a.shape, b.shape)
         scale = np.abs(b).max()
-        err = np.abs(a - b).max()
-        log(f"[grad {label}] {k}: max|ref|={scale:.4g} max|err|={err:.4g} rel={err / max(scale, 1e-30):.3g}")
+        e = np.abs(a - b).ravel()
+        err = e.max() if e.size else 0.0
+        # per-element statistics: error of each element relative to the
+        # tensor's max |ref|, and relative to its own |ref| where that is at
+        # least 1e-2 of the max (smaller elements cancel)
+        rel = e / max(scale, 1e-30)
+        big = np.abs(b).ravel() >= 1e-2 * scale
+        own = e[big] / np.abs(b).ravel()[big] if big.any() else np.zeros(1)
+        log(f"[grad {label}] {k}: max|ref|={scale:.4g} max|err|={err:.4g} rel={err / max(scale, 1e-30):.3g} "
+            f"p50/p99 of err/max|ref| {np.percentile(rel, 50):.2g}/{np.percentile(rel, 99):.2g}, "
+            f"p50/p99/max of err/|ref| (|ref| >= 1e-2 max) {np.percentile(own, 50):.2g}/"
+            f"{np.percentile(own, 99):.2g}/{own.max():.2g}")
         if scale == 0.0:
             assert err <= 1e-6, (k, err)
         else:
