@@ -76,6 +76,7 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   L->off_tilepart = off; off = align256(off + sizeof(float) * 4 * tiles);
   L->off_gpart = off;    off = align256(off + sizeof(double) * 2 * L->gpart_blocks);
   L->off_items = off;    off = align256(off + sizeof(uint32_t) * (tiles + 1));
+  L->off_torder = off;   off = align256(off + sizeof(uint32_t) * (tiles > 0 ? tiles : 1));
   L->off_acc = off;      off = align256(off + sizeof(float) * 4 * pixels);
   L->off_oit = off;      off = align256(off + sizeof(float) * 4 * pixels);
   L->off_acclog = off;   off = align256(off + sizeof(float) * pixels);

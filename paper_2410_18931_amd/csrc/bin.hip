@@ -255,9 +255,22 @@ __device__ inline uint32_t block_scan_1024(uint32_t v, uint32_t* sh, uint32_t* t
 // scans for the tile-sized arrays.
 constexpr int kTileScanThreads = 1024;
 constexpr int kTileScanPer = 8;
+constexpr int kOrderBuckets = kItemSplats / 32 + 1;
+
+// Bucket of tile t in the dispatch order: longest last work item first.
+// tile_start already holds the exclusive scan (tile_start[total_tiles] is
+// the total).
+__device__ __forceinline__ int order_bucket(const uint32_t* tile_start, int64_t t, uint64_t cap) {
+  uint64_t a = tile_start[t], e = tile_start[t + 1];
+  a = a < cap ? a : cap;
+  e = e < cap ? e : cap;
+  const uint64_t l = e > a ? e - a : 0;
+  const uint64_t last = l == 0 ? 0 : l - ((l - 1) / kItemSplats) * kItemSplats;  // in [1, kItemSplats]
+  return kOrderBuckets - 1 - static_cast<int>(last / 32);
+}
 __global__ __launch_bounds__(kTileScanThreads) void tile_scan_single(uint32_t* tile_start, int64_t total_tiles,
-                                                                     uint32_t* items, DevFlags* flags,
-                                                                     int64_t capacity) {
+                                                                     uint32_t* items, uint32_t* tile_order,
+                                                                     DevFlags* flags, int64_t capacity) {
   __shared__ uint32_t sh[16];
   const int64_t len = total_tiles + 1;
   constexpr int64_t kChunk = static_cast<int64_t>(kTileScanThreads) * kTileScanPer;
@@ -316,6 +329,31 @@ __global__ __launch_bounds__(kTileScanThreads) void tile_scan_single(uint32_t* t
     }
     icarry += tot;
   }
+  // Dispatch order of the work items.  Items that hold a full kItemSplats
+  // splats run first (in tile order: dispatch slot i < F, F the number of such
+  // items, is tile t's full item i - (items[t] - t)); then every tile's last
+  // item, longest first: tile_order lists the tiles by the length of that
+  // item, counting-sorted in buckets of 32 splats.  Heavy items start early,
+  // so the launch ends on short ones instead of waiting for a late heavy one.
+  // Only the order of execution changes (within a bucket it varies from run
+  // to run): every item writes the same outputs.
+  __shared__ uint32_t bucket[kOrderBuckets];
+  for (int b = threadIdx.x; b < kOrderBuckets; b += kTileScanThreads) bucket[b] = 0u;
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < total_tiles; t += kTileScanThreads)
+    atomicAdd(&bucket[order_bucket(tile_start, t, cap)], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 0; b < kOrderBuckets; ++b) {
+      const uint32_t c = bucket[b];
+      bucket[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < total_tiles; t += kTileScanThreads)
+    tile_order[atomicAdd(&bucket[order_bucket(tile_start, t, cap)], 1u)] = static_cast<uint32_t>(t);
 }
 
 // Gaussian-major pair offsets: the exclusive scan of every (view, Gaussian)'s
@@ -437,7 +475,8 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
       a.cams, L.nv, L.nblk, L.total_tiles, hist, tstart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // tile starts, overflow flags and raster work items in one workgroup
-  tile_scan_single<<<1, kTileScanThreads, 0, st>>>(tstart, L.total_tiles, items, flags, capacity);
+  tile_scan_single<<<1, kTileScanThreads, 0, st>>>(tstart, L.total_tiles, items,
+                                                   at<uint32_t>(ws, L.off_torder), flags, capacity);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   bin_pass<true><<<grid, kBinThreads, lds, st>>>(a);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -6,7 +6,10 @@
 //   backward: per pixel gbar = dL/dC / D and s = gbar . C; per pair
 //             dL/da = gbar . c_i - s, then the chain to (mu, conic, c, amp).
 //
-// One workgroup per work item (at most 1024 splats of one tile's list).
+// One workgroup per work item (at most 1024 splats of one tile's list); the
+// items are dispatched longest first (the full ones, then the tiles' last
+// items by decreasing length; see tile_scan_single), so that the launch ends
+// on short items.
 // Each wave owns an 8x8 pixel block of the tile.  Per batch the group stages
 // splat records into LDS; each wave then keeps only the splats whose support
 // reaches its own block (support box, then the exact minimum of q over the
@@ -171,6 +174,7 @@ struct RasterArgs {
   // of the tile with first item i0 at slot i0 - tile + k - 1 of split4 (and
   // splitlog for Eq. 2's coverage), [split_slots][T * T]
   const uint32_t* items;
+  const uint32_t* tile_order;  // dispatch order of the tiles' last items
   int64_t total_tiles;
   float* acc;
   float4* split4;
@@ -220,14 +224,24 @@ struct TileCtx {
 template <int T>
 __device__ __forceinline__ void tile_setup(const RasterArgs& a, uint32_t item, TileCtx<T>& c, const DevCamera*& cam) {
   using G = TileGeom<T>;
-  // largest tile t with items[t] <= item (items is strictly increasing)
-  int64_t lo = 0, hi = a.total_tiles - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (a.items[mid] <= item) lo = mid; else hi = mid - 1;
+  // dispatch slot -> (tile, item within the tile), in the order the binning
+  // laid out: first the full items, tile by tile, then the tiles' last items
+  // in tile_order
+  const uint32_t nfull = a.items[a.total_tiles] - static_cast<uint32_t>(a.total_tiles);
+  int64_t lo = 0;
+  if (item < nfull) {
+    // largest tile t with items[t] - t <= item (nondecreasing in t)
+    int64_t hi = a.total_tiles - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (static_cast<int64_t>(a.items[mid]) - mid <= static_cast<int64_t>(item)) lo = mid; else hi = mid - 1;
+    }
+    c.k = item - (a.items[lo] - static_cast<uint32_t>(lo));
+  } else {
+    lo = a.tile_order[item - nfull];
+    c.k = a.items[lo + 1] - a.items[lo] - 1;
   }
   c.tile = lo;
-  c.k = item - a.items[lo];
   c.nk = a.items[lo + 1] - a.items[lo];
   const int tile = static_cast<int>(lo);
   c.v = find_view(a.cams, a.nv, tile);
@@ -434,9 +448,9 @@ __device__ __forceinline__ void raster_fwd_item(const RasterArgs& a, const TileC
 }
 
 // Forward.  Lists hold LDS byte offsets of the staged records.  S records
-// are staged per batch.  A workgroup renders the work item blockIdx.x (the
-// grid covers them all), or, PERSIST, claims items from a counter until none
-// is left.
+// are staged per batch.  A workgroup renders the work item of dispatch slot
+// blockIdx.x (the grid covers them all), or, PERSIST, claims slots from a
+// counter until none is left.
 template <int T, int S, bool COUNT, bool CUT, bool OIT, bool PERSIST>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
@@ -1008,23 +1022,30 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
 
 // One workgroup per tile: the tile's list, keyed by (depth bits, id), is
 // sorted in LDS by a bitonic network over the next power of two (padding
-// keys sort last) and written back in place.  Lists longer than kSortMax
-// raise a flag and stay unsorted.
+// keys sort last) and written back in place.  An instance holds CAP keys and
+// sorts the lists of length lo < l <= CAP; the largest instance raises a flag
+// for lists longer than kSortMax, which stay unsorted.  Three instances
+// (16, 64 and 128 KB of LDS): most lists are short, and the smaller
+// instances let more workgroups share a CU.
+constexpr int kSortSmall = 2048;
+constexpr int kSortMid = 8192;
+
+template <int CAP>
 __global__ __launch_bounds__(1024) void sort_tiles_kernel(const DevCamera* cams, int32_t nv, const DevSplat* rec,
                                                           int64_t n, const uint32_t* tile_start, uint32_t* ids,
-                                                          int64_t capacity, DevFlags* flags) {
-  __shared__ uint64_t keys[kSortMax];
+                                                          int64_t capacity, int lo, DevFlags* flags) {
+  __shared__ uint64_t keys[CAP];
   const int tile = static_cast<int>(blockIdx.x);
   const uint64_t cap = static_cast<uint64_t>(capacity);
   uint64_t s = tile_start[tile], e = tile_start[tile + 1];
   s = s < cap ? s : cap;
   e = e < cap ? e : cap;
-  if (e <= s + 1) return;
-  const int len = static_cast<int>(e - s);
-  if (e - s > static_cast<uint64_t>(kSortMax)) {
-    if (threadIdx.x == 0) flags->sort_overflow = 1u;
+  if (e <= s + 1 || e - s <= static_cast<uint64_t>(lo)) return;
+  if (e - s > static_cast<uint64_t>(CAP)) {
+    if (CAP == kSortMax && threadIdx.x == 0) flags->sort_overflow = 1u;
     return;
   }
+  const int len = static_cast<int>(e - s);
   const int v = find_view(cams, nv, tile);
   int npow = 2;
   while (npow < len) npow <<= 1;
@@ -1041,13 +1062,13 @@ __global__ __launch_bounds__(1024) void sort_tiles_kernel(const DevCamera* cams,
   for (int size = 2; size <= npow; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = threadIdx.x; i < (npow >> 1); i += 1024) {
-        const int lo = (i / stride) * 2 * stride + (i % stride);
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t x = keys[lo], y = keys[hi];
+        const int a = (i / stride) * 2 * stride + (i % stride);
+        const int b = a + stride;
+        const bool up = (a & size) == 0;
+        const uint64_t x = keys[a], y = keys[b];
         if ((x > y) == up) {
-          keys[lo] = y;
-          keys[hi] = x;
+          keys[a] = y;
+          keys[b] = x;
         }
       }
       __syncthreads();
@@ -1143,6 +1164,7 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   a.unnormalised = (P->flags & WSR_FLAG_UNNORMALISED) ? 1 : 0;
   a.globals = globals;
   a.items = at<uint32_t>(ws, L.off_items);
+  a.tile_order = at<uint32_t>(ws, L.off_torder);
   a.total_tiles = L.total_tiles;
   a.acc = at<float>(ws, L.off_acc);
   // The forward's split-tile slots live in the pair buffer's partial-gradient
@@ -1322,9 +1344,17 @@ namespace wsr {
 hipError_t launch_sort_tiles(const Layout& L, void* ws, void* pairs, int64_t capacity, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
   const PairView pv = pair_view(pairs, capacity);
-  sort_tiles_kernel<<<dim3(static_cast<unsigned>(L.total_tiles)), 1024, 0, st>>>(
-      at<DevCamera>(ws, L.off_cams), L.nv, at<DevSplat>(ws, L.off_rec), L.n, at<uint32_t>(ws, L.off_tstart),
-      pv.ids, capacity, at<DevFlags>(ws, L.off_flags));
+  const dim3 grid(static_cast<unsigned>(L.total_tiles));
+  // the three instances sort disjoint sets of tiles
+  sort_tiles_kernel<kSortSmall><<<grid, 1024, 0, st>>>(at<DevCamera>(ws, L.off_cams), L.nv, at<DevSplat>(ws, L.off_rec),
+                                                       L.n, at<uint32_t>(ws, L.off_tstart), pv.ids, capacity, 0,
+                                                       at<DevFlags>(ws, L.off_flags));
+  sort_tiles_kernel<kSortMid><<<grid, 1024, 0, st>>>(at<DevCamera>(ws, L.off_cams), L.nv, at<DevSplat>(ws, L.off_rec),
+                                                     L.n, at<uint32_t>(ws, L.off_tstart), pv.ids, capacity,
+                                                     kSortSmall, at<DevFlags>(ws, L.off_flags));
+  sort_tiles_kernel<kSortMax><<<grid, 1024, 0, st>>>(at<DevCamera>(ws, L.off_cams), L.nv, at<DevSplat>(ws, L.off_rec),
+                                                     L.n, at<uint32_t>(ws, L.off_tstart), pv.ids, capacity,
+                                                     kSortMid, at<DevFlags>(ws, L.off_flags));
   return hipGetLastError();
 }
 

@@ -99,7 +99,7 @@ struct Layout {
   int64_t hist_len = 0;      // entries of the count matrix (without the trailing total)
   int64_t scan_parts = 0;
   size_t off_cams = 0, off_flags = 0, off_rec = 0, off_rect = 0, off_hist = 0, off_scan = 0,
-         off_goff = 0, off_grad2d = 0, off_tstart = 0, off_tilepart = 0, off_gpart = 0, off_items = 0, off_acc = 0,
+         off_goff = 0, off_grad2d = 0, off_tstart = 0, off_tilepart = 0, off_gpart = 0, off_items = 0, off_torder = 0, off_acc = 0,
          off_oit = 0, off_acclog = 0, off_du2d = 0,
          off_queue = 0;  // work-item counters of the persistent raster launches (forward, backward)
   int64_t gpart_blocks = 0;
