@@ -514,14 +514,64 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
+// Moments about the wave block's centre.  A lane sums, per pixel of its
+// splat's walk, e = G dL/da against the pixel centre's offset xc from the
+// block centre (a compile-time constant per column: no per-pixel dx or dx^2
+// for the moments) and folds each row with dy = pixel y - splat y:
+//   X1 = sum e xc, X2 = sum e xc^2, XY = sum e xc dy, My = sum e dy,
+//   Myy = sum e dy^2, S = sum e.
+// With dx = xc - m (m the splat centre's offset from the block centre) the
+// moments about the splat centre follow once per splat:
+//   Mx = X1 - m S,  Mxx = X2 - 2 m X1 + m^2 S,  Mxy = XY - m My,
+// whose rounding is bounded like that of summing e dx directly (|xc| + |m|
+// bounds |dx| over the block).
+struct BlockMoments {
+  float X1 = 0.f, X2 = 0.f, XY = 0.f, My = 0.f, Myy = 0.f, S = 0.f;
+};
+
+__device__ __forceinline__ void fold_row(BlockMoments& M, float dy, float S0, float S1, float S2) {
+  M.S += S0;
+  M.X1 += S1;
+  M.X2 += S2;
+  M.My = fmaf(dy, S0, M.My);
+  M.XY = fmaf(dy, S1, M.XY);
+  M.Myy = fmaf(dy * dy, S0, M.Myy);
+}
+
+__device__ __forceinline__ BlockMoments shfl_sum(BlockMoments M, int d) {
+  M.X1 += __shfl_xor(M.X1, d, kWave);
+  M.X2 += __shfl_xor(M.X2, d, kWave);
+  M.XY += __shfl_xor(M.XY, d, kWave);
+  M.My += __shfl_xor(M.My, d, kWave);
+  M.Myy += __shfl_xor(M.Myy, d, kWave);
+  M.S += __shfl_xor(M.S, d, kWave);
+  return M;
+}
+
+// The five 2D-gradient sums from the block moments: the dq factors of the
+// mean and conic gradients (dq = -a e / 2 per pixel, with a = amp G; the
+// staged conic is scaled by log2(e) / 2, undone here).  `amp` multiplies the
+// sums once (1 where the moments already carry the amplitude).
+__device__ __forceinline__ void geom_sums(const BlockMoments& M, float m, float amp, float A, float B2, float Cc,
+                                          float* o) {
+  const float Mx = fmaf(-m, M.S, M.X1);
+  const float Mxx = fmaf(m, fmaf(m, M.S, -2.f * M.X1), M.X2);
+  const float Mxy = fmaf(-m, M.My, M.XY);
+  const float ampc = amp * kTwoLn2;
+  o[0] = ampc * (A * Mx + 0.5f * B2 * M.My);
+  o[1] = ampc * (0.5f * B2 * Mx + Cc * M.My);
+  o[2] = -0.5f * amp * Mxx;
+  o[3] = -amp * Mxy;
+  o[4] = -0.5f * amp * M.Myy;
+}
+
 // One chunk of the backward for one wave: up to 64 splats of the wave's
 // culled list, one per lane, each walked over the wave's 8x8 pixel block.
-// Per splat the lane sums over the pixels, with G = exp(-q/2) and
-// e = G dL/da: per row S0 = sum e, S1 = sum e dx and S2 = sum e dx^2 (three
-// FMAs a pixel), folded with dy once per row into the moments Mx = sum e dx,
-// My = sum e dy, Mxx = sum e dx^2, Mxy = sum e dx dy, Myy = sum e dy^2; and
-// sum G gbar.  The splat's amplitude multiplies them once at the end.  The
-// lane's nine partial 2D gradient sums are written to out[j][lane].
+// Per splat the lane sums, with G = exp(-q/2) and e = G dL/da, the block
+// moments of e (three FMAs a pixel, see BlockMoments) and sum G gbar.  The
+// splat's amplitude multiplies them once at the end.  The lane's nine
+// partial 2D gradient sums are written to out[j][lane].  A lane past the
+// end of the list gets a negative cutoff, so no pixel passes.
 //
 // All lanes walk the same pixel at the same time, so the per-pixel factors
 // (gbar, s) are read from LDS at a wave-uniform address (a broadcast).
@@ -534,10 +584,10 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
   const int kr = valid ? list[j] : 0;
   const StagedRec r = s_rec[kr];
   const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
-  float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
-  float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
+  BlockMoments M;
+  float g_r = 0.f, g_g = 0.f, g_b = 0.f;
   const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
-  const float cut = CUT ? r.r2.y : tau;
+  const float cut = valid ? (CUT ? r.r2.y : tau) : -1.f;
   // first pixel centre of the block relative to the tile's centre (exact),
   // so dx = (ex0 + col) - mx matches the forward's
   const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
@@ -549,42 +599,32 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
     float S0 = 0.f, S1 = 0.f, S2 = 0.f;
 #pragma unroll
     for (int col = 0; col < 8; ++col) {
+      const float xc = static_cast<float>(col) - 3.5f;
       const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
       const float q = quad_form(A, B2dy, Cdy2, dx);
       const float4 pd = pd_wave[row * 8 + col];  // wave-uniform LDS address: a broadcast read
-      const float Gq = (valid && q <= cut) ? falloff(q) : 0.f;
+      const float Gq = q <= cut ? falloff(q) : 0.f;
       const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
       const float e = Gq * dLda;
       S0 += e;
-      S1 = fmaf(e, dx, S1);
-      S2 = fmaf(e, dx * dx, S2);
+      S1 = fmaf(e, xc, S1);
+      S2 = fmaf(e, xc * xc, S2);
       g_r = fmaf(Gq, pd.x, g_r);
       g_g = fmaf(Gq, pd.y, g_g);
       g_b = fmaf(Gq, pd.z, g_b);
     }
-    g_amp += S0;
-    Mx += S1;
-    My = fmaf(dy, S0, My);
-    Mxx += S2;
-    Mxy = fmaf(dy, S1, Mxy);
-    Myy = fmaf(dy * dy, S0, Myy);
+    fold_row(M, dy, S0, S1, S2);
   }
-  // the sums above leave out the splat's constant amplitude (a = amp G):
-  // dq = -amp e / 2, and with q = A dx^2 + B2 dx dy + C dy^2, dx = px - mu_x,
-  // dL/dmu_x = -sum dq (2A dx + B2 dy) = amp (A Mx + (B2/2) My), and so on
-  // (the staged conic is scaled by log2(e) / 2, undone here);
   // dL/dc = amp sum G gbar, dL/damp = sum G dL/da
   const int l = c.lane;
-  const float ampc = amp * kTwoLn2;
-  out[0][l] = ampc * (A * Mx + 0.5f * B2 * My);
-  out[1][l] = ampc * (0.5f * B2 * Mx + Cc * My);
-  out[2][l] = -0.5f * amp * Mxx;
-  out[3][l] = -amp * Mxy;
-  out[4][l] = -0.5f * amp * Myy;
+  float o[5];
+  geom_sums(M, r.r0.x - (ex0 + 3.5f), amp, A, B2, Cc, o);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) out[q][l] = o[q];
   out[5][l] = amp * g_r;
   out[6][l] = amp * g_g;
   out[7][l] = amp * g_b;
-  out[8][l] = g_amp;
+  out[8][l] = M.S;
 }
 
 // A short chunk (at most 64 / K splats, K = 2, 4 or 8), which would leave
@@ -592,7 +632,7 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
 // rows [g 8/K, (g+1) 8/K) of the block, and the groups' sums are added with
 // cross-lane shuffles in a fixed order.  The groups visit different pixels
 // at the same time, so the per-pixel factors come from this wave's copy in
-// LDS (s_pd, 64 entries) instead of scalar loads.  The arithmetic per pixel
+// LDS (s_pd, 64 entries) at per-group addresses.  The arithmetic per pixel
 // is that of bwd_chunk.
 template <int T, bool CUT, int K>
 __device__ __forceinline__ void bwd_chunk_split(const TileCtx<T>& c, int c0, int m, const uint8_t* list,
@@ -607,10 +647,10 @@ __device__ __forceinline__ void bwd_chunk_split(const TileCtx<T>& c, int c0, int
   const int kr = valid ? list[j] : 0;
   const StagedRec r = s_rec[kr];
   const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
-  float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
-  float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f;
+  BlockMoments M;
+  float g_r = 0.f, g_g = 0.f, g_b = 0.f;
   const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
-  const float cut = CUT ? r.r2.y : tau;
+  const float cut = valid ? (CUT ? r.r2.y : tau) : -1.f;
   const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
   const float ey0 = static_cast<float>(c.by0 - c.fy0 + g * R) + 0.5f;  // first row of this group
   const float4* pd_rows = s_pd + g * R * 8;
@@ -621,49 +661,38 @@ __device__ __forceinline__ void bwd_chunk_split(const TileCtx<T>& c, int c0, int
     float S0 = 0.f, S1 = 0.f, S2 = 0.f;
 #pragma unroll
     for (int col = 0; col < 8; ++col) {
+      const float xc = static_cast<float>(col) - 3.5f;
       const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
       const float q = quad_form(A, B2dy, Cdy2, dx);
       const float4 pd = pd_rows[row * 8 + col];
-      const float Gq = (valid && q <= cut) ? falloff(q) : 0.f;
+      const float Gq = q <= cut ? falloff(q) : 0.f;
       const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
       const float e = Gq * dLda;
       S0 += e;
-      S1 = fmaf(e, dx, S1);
-      S2 = fmaf(e, dx * dx, S2);
+      S1 = fmaf(e, xc, S1);
+      S2 = fmaf(e, xc * xc, S2);
       g_r = fmaf(Gq, pd.x, g_r);
       g_g = fmaf(Gq, pd.y, g_g);
       g_b = fmaf(Gq, pd.z, g_b);
     }
-    g_amp += S0;
-    Mx += S1;
-    My = fmaf(dy, S0, My);
-    Mxx += S2;
-    Mxy = fmaf(dy, S1, Mxy);
-    Myy = fmaf(dy * dy, S0, Myy);
+    fold_row(M, dy, S0, S1, S2);
   }
 #pragma unroll
   for (int d = S; d < kWave; d <<= 1) {
-    Mx += __shfl_xor(Mx, d, kWave);
-    My += __shfl_xor(My, d, kWave);
-    Mxx += __shfl_xor(Mxx, d, kWave);
-    Mxy += __shfl_xor(Mxy, d, kWave);
-    Myy += __shfl_xor(Myy, d, kWave);
+    M = shfl_sum(M, d);
     g_r += __shfl_xor(g_r, d, kWave);
     g_g += __shfl_xor(g_g, d, kWave);
     g_b += __shfl_xor(g_b, d, kWave);
-    g_amp += __shfl_xor(g_amp, d, kWave);
   }
   if (g == 0) {
-    const float ampc = amp * kTwoLn2;
-    out[0][slot] = ampc * (A * Mx + 0.5f * B2 * My);
-    out[1][slot] = ampc * (0.5f * B2 * Mx + Cc * My);
-    out[2][slot] = -0.5f * amp * Mxx;
-    out[3][slot] = -amp * Mxy;
-    out[4][slot] = -0.5f * amp * Myy;
+    float o[5];
+    geom_sums(M, r.r0.x - (ex0 + 3.5f), amp, A, B2, Cc, o);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q][slot] = o[q];
     out[5][slot] = amp * g_r;
     out[6][slot] = amp * g_g;
     out[7][slot] = amp * g_b;
-    out[8][slot] = g_amp;
+    out[8][slot] = M.S;
   }
 }
 
@@ -683,9 +712,10 @@ __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m
   const StagedRec r = s_rec[kr];
   const float u = r.r2.z;
   const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
-  float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+  BlockMoments M;
   float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f, g_u = 0.f;
   const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
+  const float cut = valid ? tau : -1.f;
   const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
   const float ey0 = static_cast<float>(c.by0 - c.fy0) + 0.5f;
 #pragma unroll 1
@@ -695,37 +725,33 @@ __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m
     float S0 = 0.f, S1 = 0.f, S2 = 0.f;
 #pragma unroll
     for (int col = 0; col < 8; ++col) {
+      const float xc = static_cast<float>(col) - 3.5f;
       const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
       const float q = quad_form(A, B2dy, Cdy2, dx);
       const float4 pd = pd_wave[row * 8 + col];  // wave-uniform LDS address: a broadcast read
       const float k = pk_wave[row * 8 + col];
-      const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
+      const float Gq = q <= cut ? falloff(q) : 0.f;
       const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
       const float al = u * Gq;
       // hardware reciprocal (within 1 ulp) instead of an IEEE division
       const float dLdal = (al > 0.f && al < 1.f) ? -k * __builtin_amdgcn_rcpf(1.f - al) : 0.f;
       const float e = Gq * fmaf(amp, dLda, u * dLdal);
       S0 += e;
-      S1 = fmaf(e, dx, S1);
-      S2 = fmaf(e, dx * dx, S2);
+      S1 = fmaf(e, xc, S1);
+      S2 = fmaf(e, xc * xc, S2);
       g_r = fmaf(Gq, pd.x, g_r);
       g_g = fmaf(Gq, pd.y, g_g);
       g_b = fmaf(Gq, pd.z, g_b);
       g_amp = fmaf(Gq, dLda, g_amp);
       g_u = fmaf(Gq, dLdal, g_u);
     }
-    Mx += S1;
-    My = fmaf(dy, S0, My);
-    Mxx += S2;
-    Mxy = fmaf(dy, S1, Mxy);
-    Myy = fmaf(dy * dy, S0, Myy);
+    fold_row(M, dy, S0, S1, S2);
   }
   const int l = c.lane;
-  out[0][l] = kTwoLn2 * (A * Mx + 0.5f * B2 * My);  // staged conic scaled by log2(e) / 2
-  out[1][l] = kTwoLn2 * (0.5f * B2 * Mx + Cc * My);
-  out[2][l] = -0.5f * Mxx;
-  out[3][l] = -Mxy;
-  out[4][l] = -0.5f * Myy;
+  float o[5];
+  geom_sums(M, r.r0.x - (ex0 + 3.5f), 1.f, A, B2, Cc, o);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) out[q][l] = o[q];
   out[5][l] = amp * g_r;
   out[6][l] = amp * g_g;
   out[7][l] = amp * g_b;
@@ -749,9 +775,10 @@ __device__ __forceinline__ void bwd_chunk_oit_split(const TileCtx<T>& c, int c0,
   const StagedRec r = s_rec[kr];
   const float u = r.r2.z;
   const float amp = r.r1.y, cr = r.r1.z, cg = r.r1.w, cb = r.r2.x;
-  float Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+  BlockMoments M;
   float g_r = 0.f, g_g = 0.f, g_b = 0.f, g_amp = 0.f, g_u = 0.f;
   const float A = r.r0.z, B2 = r.r0.w, Cc = r.r1.x;
+  const float cut = valid ? tau : -1.f;
   const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
   const float ey0 = static_cast<float>(c.by0 - c.fy0 + g * R) + 0.5f;  // first row of this group
   const float4* pd_rows = s_pd + g * R * 8;
@@ -763,37 +790,30 @@ __device__ __forceinline__ void bwd_chunk_oit_split(const TileCtx<T>& c, int c0,
     float S0 = 0.f, S1 = 0.f, S2 = 0.f;
 #pragma unroll
     for (int col = 0; col < 8; ++col) {
+      const float xc = static_cast<float>(col) - 3.5f;
       const float dx = (ex0 + static_cast<float>(col)) - r.r0.x;
       const float q = quad_form(A, B2dy, Cdy2, dx);
       const float4 pd = pd_rows[row * 8 + col];
       const float k = pk_rows[row * 8 + col];
-      const float Gq = (valid && q <= tau) ? falloff(q) : 0.f;
+      const float Gq = q <= cut ? falloff(q) : 0.f;
       const float dLda = fmaf(pd.x, cr, fmaf(pd.y, cg, fmaf(pd.z, cb, -pd.w)));
       const float al = u * Gq;
       const float dLdal = (al > 0.f && al < 1.f) ? -k * __builtin_amdgcn_rcpf(1.f - al) : 0.f;
       const float e = Gq * fmaf(amp, dLda, u * dLdal);
       S0 += e;
-      S1 = fmaf(e, dx, S1);
-      S2 = fmaf(e, dx * dx, S2);
+      S1 = fmaf(e, xc, S1);
+      S2 = fmaf(e, xc * xc, S2);
       g_r = fmaf(Gq, pd.x, g_r);
       g_g = fmaf(Gq, pd.y, g_g);
       g_b = fmaf(Gq, pd.z, g_b);
       g_amp = fmaf(Gq, dLda, g_amp);
       g_u = fmaf(Gq, dLdal, g_u);
     }
-    Mx += S1;
-    My = fmaf(dy, S0, My);
-    Mxx += S2;
-    Mxy = fmaf(dy, S1, Mxy);
-    Myy = fmaf(dy * dy, S0, Myy);
+    fold_row(M, dy, S0, S1, S2);
   }
 #pragma unroll
   for (int d = S; d < kWave; d <<= 1) {
-    Mx += __shfl_xor(Mx, d, kWave);
-    My += __shfl_xor(My, d, kWave);
-    Mxx += __shfl_xor(Mxx, d, kWave);
-    Mxy += __shfl_xor(Mxy, d, kWave);
-    Myy += __shfl_xor(Myy, d, kWave);
+    M = shfl_sum(M, d);
     g_r += __shfl_xor(g_r, d, kWave);
     g_g += __shfl_xor(g_g, d, kWave);
     g_b += __shfl_xor(g_b, d, kWave);
@@ -801,11 +821,10 @@ __device__ __forceinline__ void bwd_chunk_oit_split(const TileCtx<T>& c, int c0,
     g_u += __shfl_xor(g_u, d, kWave);
   }
   if (g == 0) {
-    out[0][slot] = kTwoLn2 * (A * Mx + 0.5f * B2 * My);  // staged conic scaled by log2(e) / 2
-    out[1][slot] = kTwoLn2 * (0.5f * B2 * Mx + Cc * My);
-    out[2][slot] = -0.5f * Mxx;
-    out[3][slot] = -Mxy;
-    out[4][slot] = -0.5f * Myy;
+    float o[5];
+    geom_sums(M, r.r0.x - (ex0 + 3.5f), 1.f, A, B2, Cc, o);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q][slot] = o[q];
     out[5][slot] = amp * g_r;
     out[6][slot] = amp * g_g;
     out[7][slot] = amp * g_b;
