@@ -592,9 +592,10 @@ __device__ __forceinline__ void bwd_chunk(const TileCtx<T>& c, int c0, int m, co
   // so dx = (ex0 + col) - mx matches the forward's
   const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
   const float ey0 = static_cast<float>(c.by0 - c.fy0) + 0.5f;
+  float yrow = ey0;  // this row's pixel centre (exact: ey0 + row)
 #pragma unroll 1
-  for (int row = 0; row < 8; ++row) {
-    const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
+  for (int row = 0; row < 8; ++row, yrow += 1.f) {
+    const float dy = yrow - r.r0.y;
     const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
     float S0 = 0.f, S1 = 0.f, S2 = 0.f;
 #pragma unroll
@@ -718,9 +719,10 @@ __device__ __forceinline__ void bwd_chunk_oit(const TileCtx<T>& c, int c0, int m
   const float cut = valid ? tau : -1.f;
   const float ex0 = static_cast<float>(c.bx0 - c.fx0) + 0.5f;
   const float ey0 = static_cast<float>(c.by0 - c.fy0) + 0.5f;
+  float yrow = ey0;  // this row's pixel centre (exact: ey0 + row)
 #pragma unroll 1
-  for (int row = 0; row < 8; ++row) {
-    const float dy = (ey0 + static_cast<float>(row)) - r.r0.y;
+  for (int row = 0; row < 8; ++row, yrow += 1.f) {
+    const float dy = yrow - r.r0.y;
     const float B2dy = B2 * dy, Cdy2 = (Cc * dy) * dy;
     float S0 = 0.f, S1 = 0.f, S2 = 0.f;
 #pragma unroll
