@@ -269,8 +269,10 @@ typedef struct {
 
 /* Sorts every tile's id list (as left by wsr_bin on the same workspace and
  * pair buffer) by (camera depth, Gaussian id), in place, one workgroup per
- * tile in LDS.  A list longer than WSR_SORT_MAX is left unsorted and raises
- * a flag that wsr_check reports as WSR_ERR_TILE_LIST.  Asynchronous. */
+ * tile in LDS.  The lists stay valid input for wsr_render_fwd and the
+ * backward (Eq. 7 does not depend on their order).  A list longer than
+ * WSR_SORT_MAX is left unsorted and raises a flag that wsr_check reports as
+ * WSR_ERR_TILE_LIST.  Asynchronous. */
 int32_t wsr_sort_tiles(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
                        void* ws, int64_t ws_bytes, void* pairs, int64_t capacity, void* stream);
 

@@ -56,10 +56,7 @@ bool make_layout(int64_t n, const wsr_camera* cams, int32_t nv, int32_t tile, La
   L->total_tiles = tiles;
   L->total_pixels = pixels;
   L->hist_len = hist;
-  {
-    const int64_t longest = tiles + 1 > n * nv + 1 ? tiles + 1 : n * nv + 1;
-    L->scan_parts = (longest + kScanItems - 1) / kScanItems;
-  }
+  L->scan_parts = static_cast<int64_t>(nv) * L->nblk;  // one rectangle sum per (view, binning block)
   L->gpart_blocks = project_bwd_blocks(n);
   const int64_t slots = n * nv;
   size_t off = 0;

@@ -22,8 +22,12 @@
 //
 // The same step also lays out the backward's per-pair scratch: every
 // (view, Gaussian) gets a contiguous range of "Gaussian-major" slots, one per
-// tile of its rectangle in row-major order (goff_reduce / goff_apply), and
-// the raster work items that split long tile lists (tile_scan_single).
+// tile of its rectangle in row-major order.  Its first slot, goff, is the
+// exclusive scan of the rectangle sizes in (view, Gaussian) order, formed by
+// the same passes: the counting pass's first band also sums each block's
+// rectangle sizes, scan_parts scans those block sums, and the scatter pass's
+// first band writes goff.  The raster work items that split long tile lists
+// come from tile_scan_single.
 #include "wsr_internal.h"
 
 namespace wsr {
@@ -61,10 +65,13 @@ struct BinArgs {
   const uint2* rect;
   uint32_t* hist;              // block-major count matrix, then its column prefixes
   const uint32_t* tile_start;  // start of every tile's list (scatter pass)
-  uint32_t* ids;
+  uint2* ent;                  // list entries (id, Gaussian-major slot)
   int64_t n;
   int64_t capacity;
   int32_t rows_per_chunk;
+  int32_t nblk;                // blocks per view
+  uint32_t* parts;             // per (view, block): sum of the rectangle sizes, then its exclusive scan
+  uint32_t* goff;              // Gaussian-major first slot of every (view, Gaussian)
 };
 
 template <bool SCATTER>
@@ -72,6 +79,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t s_off[kBinThreads];
   __shared__ uint32_t s_x0[kBinThreads], s_w[kBinThreads], s_y0[kBinThreads];
+  __shared__ uint32_t s_gadj[kBinThreads];  // scatter: goff - (y0 w + x0), mod 2^32
   __shared__ uint32_t s_scan[4];
 
   const int b = blockIdx.x, z = blockIdx.y, v = blockIdx.z;
@@ -95,6 +103,10 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   // bits of a chunk-local tile index
   const int tbits = chunk_tiles > 1 ? 32 - __clz(static_cast<uint32_t>(chunk_tiles - 1)) : 1;
+  const int64_t part = static_cast<int64_t>(v) * a.nblk + b;
+  // running Gaussian-major offset of this block (counting pass: from 0, for
+  // the block's sum; scatter pass: from the block's scanned offset)
+  uint32_t gcarry = SCATTER ? a.parts[part] : 0u;
   for (int64_t base = g0; base < g1; base += kBinThreads) {
     const int64_t i = base + threadIdx.x;
     uint32_t cnt = 0, x0 = 0, w = 0, y0 = 0;
@@ -110,6 +122,25 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
         y0 = static_cast<uint32_t>(yl);
       }
     }
+    if (SCATTER || z == 0) {
+      // this (view, Gaussian)'s whole rectangle: its run of Gaussian-major
+      // slots (counting pass, first band: the block's sum; scatter pass:
+      // goff, stored by the first band, and each pair's slot)
+      uint32_t full = 0, gadj = 0;
+      if (i < g1) {
+        const uint2 r = rect[i];
+        const uint32_t rx0 = r.x & 0xffffu, rx1 = r.x >> 16, ry0r = r.y & 0xffffu, ry1r = r.y >> 16;
+        full = (rx1 > rx0 && ry1r > ry0r) ? (rx1 - rx0) * (ry1r - ry0r) : 0u;
+        gadj = 0u - (ry0r * (rx1 - rx0) + rx0);
+      }
+      uint32_t ftot;
+      const uint32_t fex = block_scan_256(full, s_scan, &ftot);
+      if (SCATTER) {
+        s_gadj[threadIdx.x] = gcarry + fex + gadj;  // slot of tile (tx, ty): this + ty w + tx
+        if (z == 0 && i < g1) a.goff[static_cast<int64_t>(v) * a.n + i] = gcarry + fex;
+      }
+      gcarry += ftot;
+    }
     uint32_t total;
     const uint32_t off = block_scan_256(cnt, s_scan, &total);
     s_off[threadIdx.x] = off;
@@ -122,7 +153,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
     for (uint32_t p0 = 0; p0 < total; p0 += kBinThreads) {
       const uint32_t p = p0 + threadIdx.x;
       const bool valid = p < total;
-      uint32_t t = 0;
+      uint32_t t = 0, pslot = 0;
       int lo = 0;
       if (valid) {
         // largest g with s_off[g] <= p (it has a non-zero count)
@@ -136,6 +167,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
         const uint32_t ty = s_y0[lo] + local / ww;
         const uint32_t tx = s_x0[lo] + local % ww;
         t = (ty - ry0) * tiles_x + tx;
+        if (SCATTER) pslot = s_gadj[lo] + ty * ww + tx;  // the pair's Gaussian-major slot
       }
       if (!SCATTER) {
         if (valid) atomicAdd(&lds[t], 1u);
@@ -162,7 +194,8 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
         if (wv == turn && valid) {
           const uint32_t start = lds[t];
           const uint32_t pos = start + rank;
-          if (pos < a.capacity) a.ids[pos] = static_cast<uint32_t>(base + lo);
+          if (pos < a.capacity)
+            a.ent[pos] = make_uint2(static_cast<uint32_t>(base + lo), pslot);
           if (last) lds[t] = start + grp;
         }
         __syncthreads();
@@ -172,6 +205,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_pass(BinArgs a) {
   }
   if (!SCATTER) {
     for (int t = threadIdx.x; t < chunk_tiles; t += kBinThreads) row[t] = lds[t];
+    if (z == 0 && threadIdx.x == 0) a.parts[part] = gcarry;
   }
 }
 
@@ -356,56 +390,10 @@ __global__ __launch_bounds__(kTileScanThreads) void tile_scan_single(uint32_t* t
     tile_order[atomicAdd(&bucket[order_bucket(tile_start, t, cap)], 1u)] = static_cast<uint32_t>(t);
 }
 
-// Gaussian-major pair offsets: the exclusive scan of every (view, Gaussian)'s
-// rectangle size, computed from the rectangles on the fly; the apply phase
-// also stores each offset in the Gaussian's record (where the raster backward
-// reads it).  Three kernels for what took five.
-__device__ __forceinline__ uint32_t rect_count(const uint2* rect, int64_t k, int64_t slots) {
-  if (k >= slots) return 0u;
-  const uint2 r = rect[k];
-  const uint32_t x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
-  return (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
-}
-
-__global__ __launch_bounds__(256) void goff_reduce(const uint2* rect, int64_t slots, uint32_t* parts) {
-  __shared__ uint32_t sh[4];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanItems + threadIdx.x * 16;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) s += rect_count(rect, base + k, slots);
-  uint32_t total;
-  block_scan_256(s, sh, &total);
-  if (threadIdx.x == 0) parts[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(256) void goff_apply(const uint2* rect, int64_t slots, const uint32_t* parts,
-                                                  uint32_t* goff, DevSplat* rec) {
-  __shared__ uint32_t sh[4];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanItems + threadIdx.x * 16;
-  uint32_t vals[16];
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    vals[k] = rect_count(rect, base + k, slots);
-    s += vals[k];
-  }
-  uint32_t total;
-  uint32_t run = block_scan_256(s, sh, &total) + parts[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int64_t i = base + k;
-    if (i <= slots) goff[i] = run;
-    if (i < slots) rec[i].slot.x = run;
-    run += vals[k];
-  }
-}
-
-// ---- device-wide exclusive scan of uint32 (in place), 3 phases ----
-
-// Scans the per-block partial sums; with `flags`, also records the grand
-// total and whether it exceeds `capacity` or 32 bits.
-__global__ __launch_bounds__(1024) void scan_parts(uint32_t* parts, int64_t nparts, DevFlags* flags,
-                                                   int64_t capacity) {
+// Exclusive scan (in place) of the per-(view, block) rectangle sums, in
+// (view, block) order, i.e. (view, Gaussian) order; the grand total goes to
+// *total (goff's closing entry).
+__global__ __launch_bounds__(1024) void scan_parts(uint32_t* parts, int64_t nparts, uint32_t* total) {
   __shared__ uint32_t sh[16];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
@@ -430,12 +418,7 @@ __global__ __launch_bounds__(1024) void scan_parts(uint32_t* parts, int64_t npar
     carry += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0 && flags) {
-    flags->total_pairs = carry;
-    flags->wrapped = carry > 0xffffffffull ? 1u : 0u;
-    flags->overflow = (carry > static_cast<uint64_t>(capacity) || carry > 0xffffffffull) ? 1u : 0u;
-    flags->sort_overflow = 0u;
-  }
+  if (threadIdx.x == 0) *total = static_cast<uint32_t>(carry);
 }
 
 }  // namespace
@@ -454,9 +437,12 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
   a.rect = at<uint2>(ws, L.off_rect);
   a.hist = hist;
   a.tile_start = tstart;
-  a.ids = pv.ids;
+  a.ent = pv.ent;
   a.n = L.n;
   a.capacity = capacity;
+  a.nblk = L.nblk;
+  a.parts = parts;
+  a.goff = goff;
   // whole tile rows per LDS chunk, at most kTileChunk tiles, and at least
   // kBinBands chunks of rows: each block then expands only the pairs of its
   // band, and the four times more blocks keep more of the chip busy (binning
@@ -478,16 +464,10 @@ hipError_t launch_bin(const Layout& L, void* ws, void* pairs, int64_t capacity, 
   tile_scan_single<<<1, kTileScanThreads, 0, st>>>(tstart, L.total_tiles, items,
                                                    at<uint32_t>(ws, L.off_torder), flags, capacity);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // Gaussian-major offsets of the blocks (the counting pass summed each
+  // block's rectangle sizes); the scatter pass writes goff
+  scan_parts<<<1, 1024, 0, st>>>(parts, static_cast<int64_t>(L.nv) * L.nblk, goff + L.n * L.nv);
   bin_pass<true><<<grid, kBinThreads, lds, st>>>(a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-
-  // Gaussian-major pair offsets (exclusive scan of the rectangle sizes),
-  // also stored in the records
-  const int64_t slots = L.n * L.nv;
-  const unsigned np = static_cast<unsigned>((slots + 1 + kScanItems - 1) / kScanItems);
-  goff_reduce<<<np, 256, 0, st>>>(a.rect, slots, parts);
-  scan_parts<<<1, 1024, 0, st>>>(parts, np, nullptr, 0);
-  goff_apply<<<np, 256, 0, st>>>(a.rect, slots, parts, goff, at<DevSplat>(ws, L.off_rec));
   return hipGetLastError();
 }
 

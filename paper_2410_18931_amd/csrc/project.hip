@@ -158,9 +158,10 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
       r.r2 = make_float4(rgb[0], rgb[1], rgb[2], a.alpha_cut > 0.f ? static_cast<float>(cut) : __uint_as_float(ext));
       DevSplat ds;
       ds.s = r;
-      // first pair slot filled in by binning; the camera depth orders the
-      // splats for the sorted-blending baseline, the opacity enters Eq. 2's
-      // coverage term in OIT mode
+      // the tile rectangle locates a pair's Gaussian-major slot; the camera
+      // depth orders the splats for the sorted-blending baseline, the
+      // opacity enters Eq. 2's coverage term in OIT mode (the first word is
+      // unused)
       ds.slot = make_uint4(0u, rect.x, rect.y, __float_as_uint(a.oit ? u : static_cast<float>(g.tz)));
       a.rec[slot] = ds;
     }

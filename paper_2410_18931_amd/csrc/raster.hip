@@ -152,7 +152,7 @@ struct RasterArgs {
   const DevCamera* cams;
   const DevSplat* rec;
   const uint32_t* tile_start;  // start of every tile's id list
-  const uint32_t* ids;
+  const uint2* ent;       // list entries (Gaussian id, Gaussian-major slot)
   int64_t n;
   int64_t capacity;
   int32_t nv;
@@ -289,7 +289,8 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
   for (int q = threadIdx.x; q < BATCH; q += G::kThreads) {
     const uint32_t j = b + q;
     if (j < c.end) {
-      const DevSplat* d = a.rec + static_cast<int64_t>(c.v) * c.n + a.ids[j];
+      const uint2 en = a.ent[j];  // (Gaussian id, the pair's Gaussian-major slot)
+      const DevSplat* d = a.rec + static_cast<int64_t>(c.v) * c.n + en.x;
       const SplatRec s = d->s;  // (fx, fy, A, B2) (C, ox, oy, amp) (c0, c1, c2, ext | cut)
       const float amp = s.r1.w;
       float c0 = s.r2.x, c1 = s.r2.y, c2 = s.r2.z;
@@ -305,11 +306,7 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
       // OIT: the opacity u rides in the record's third word
       r.r2 = make_float4(c2, CUT ? s.r2.w * kHalfLog2e : s.r2.w, OIT ? __uint_as_float(d->slot.w) : 0.f, 0.f);
       s_rec[q] = r;
-      if (SLOTS) {
-        const uint4 sl = d->slot;
-        const uint32_t rx0 = sl.y & 0xffffu, rw = (sl.y >> 16) - rx0, ry0 = sl.z & 0xffffu;
-        s_slot[q] = sl.x + (static_cast<uint32_t>(c.ty) - ry0) * rw + (static_cast<uint32_t>(c.tx) - rx0);
-      }
+      if (SLOTS) s_slot[q] = en.y;
     }
   }
   __syncthreads();
@@ -1041,20 +1038,24 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
 // DIR weight, so a record's amplitude is the opacity u), ordered per tile by
 // camera depth and composited front to back.
 
-// One workgroup per tile: the tile's list, keyed by (depth bits, id), is
-// sorted in LDS by a bitonic network over the next power of two (padding
-// keys sort last) and written back in place.  An instance holds CAP keys and
-// sorts the lists of length lo < l <= CAP; the largest instance raises a flag
-// for lists longer than kSortMax, which stay unsorted.  Three instances
-// (16, 64 and 128 KB of LDS): most lists are short, and the smaller
-// instances let more workgroups share a CU.
+// One workgroup per tile: the tile's list, keyed by (depth bits, list
+// position), is sorted in LDS by a bitonic network over the next power of two
+// (padding keys sort last), and the entries (id and Gaussian-major slot) are
+// then moved to their sorted positions: every thread first reads the entries
+// its positions receive, then, after a barrier, writes them.  Binning leaves
+// every list in increasing id order, so ties in depth stay in id order.  An
+// instance holds CAP keys and sorts the lists of length lo < l <= CAP; the
+// largest instance raises a flag for lists longer than kSortMax, which stay
+// unsorted.  Three instances (16, 64 and 128 KB of LDS): most lists are
+// short, and the smaller instances let more workgroups share a CU.
 constexpr int kSortSmall = 2048;
 constexpr int kSortMid = 8192;
 
 template <int CAP>
 __global__ __launch_bounds__(1024) void sort_tiles_kernel(const DevCamera* cams, int32_t nv, const DevSplat* rec,
-                                                          int64_t n, const uint32_t* tile_start, uint32_t* ids,
+                                                          int64_t n, const uint32_t* tile_start, uint2* ent,
                                                           int64_t capacity, int lo, DevFlags* flags) {
+  constexpr int R = CAP / 1024;  // list positions per thread
   __shared__ uint64_t keys[CAP];
   const int tile = static_cast<int>(blockIdx.x);
   const uint64_t cap = static_cast<uint64_t>(capacity);
@@ -1073,9 +1074,9 @@ __global__ __launch_bounds__(1024) void sort_tiles_kernel(const DevCamera* cams,
   for (int k = threadIdx.x; k < npow; k += 1024) {
     uint64_t key = ~0ull;
     if (k < len) {
-      const uint32_t id = ids[s + k];
+      const uint32_t id = ent[s + k].x;
       const uint32_t depth = rec[static_cast<int64_t>(v) * n + id].slot.w;
-      key = (static_cast<uint64_t>(depth) << 32) | id;
+      key = (static_cast<uint64_t>(depth) << 32) | static_cast<uint32_t>(k);
     }
     keys[k] = key;
   }
@@ -1095,7 +1096,18 @@ __global__ __launch_bounds__(1024) void sort_tiles_kernel(const DevCamera* cams,
       __syncthreads();
     }
   }
-  for (int k = threadIdx.x; k < len; k += 1024) ids[s + k] = static_cast<uint32_t>(keys[k]);
+  uint2 moved[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = threadIdx.x + r * 1024;
+    if (k < len) moved[r] = ent[s + static_cast<uint32_t>(keys[k])];
+  }
+  __syncthreads();  // every old entry has been read
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = threadIdx.x + r * 1024;
+    if (k < len) ent[s + k] = moved[r];
+  }
 }
 
 // One workgroup per tile (no splitting: the composition is sequential), the
@@ -1176,7 +1188,7 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   a.cams = at<DevCamera>(ws, L.off_cams);
   a.rec = at<DevSplat>(ws, L.off_rec);
   a.tile_start = at<uint32_t>(ws, L.off_tstart);
-  a.ids = pv.ids;
+  a.ent = pv.ent;
   a.part = pv.part;
   a.n = L.n;
   a.capacity = capacity;
@@ -1367,15 +1379,13 @@ hipError_t launch_sort_tiles(const Layout& L, void* ws, void* pairs, int64_t cap
   const PairView pv = pair_view(pairs, capacity);
   const dim3 grid(static_cast<unsigned>(L.total_tiles));
   // the three instances sort disjoint sets of tiles
-  sort_tiles_kernel<kSortSmall><<<grid, 1024, 0, st>>>(at<DevCamera>(ws, L.off_cams), L.nv, at<DevSplat>(ws, L.off_rec),
-                                                       L.n, at<uint32_t>(ws, L.off_tstart), pv.ids, capacity, 0,
-                                                       at<DevFlags>(ws, L.off_flags));
-  sort_tiles_kernel<kSortMid><<<grid, 1024, 0, st>>>(at<DevCamera>(ws, L.off_cams), L.nv, at<DevSplat>(ws, L.off_rec),
-                                                     L.n, at<uint32_t>(ws, L.off_tstart), pv.ids, capacity,
-                                                     kSortSmall, at<DevFlags>(ws, L.off_flags));
-  sort_tiles_kernel<kSortMax><<<grid, 1024, 0, st>>>(at<DevCamera>(ws, L.off_cams), L.nv, at<DevSplat>(ws, L.off_rec),
-                                                     L.n, at<uint32_t>(ws, L.off_tstart), pv.ids, capacity,
-                                                     kSortMid, at<DevFlags>(ws, L.off_flags));
+  const DevCamera* cams = at<DevCamera>(ws, L.off_cams);
+  const DevSplat* rec = at<DevSplat>(ws, L.off_rec);
+  const uint32_t* tstart = at<uint32_t>(ws, L.off_tstart);
+  DevFlags* flags = at<DevFlags>(ws, L.off_flags);
+  sort_tiles_kernel<kSortSmall><<<grid, 1024, 0, st>>>(cams, L.nv, rec, L.n, tstart, pv.ent, capacity, 0, flags);
+  sort_tiles_kernel<kSortMid><<<grid, 1024, 0, st>>>(cams, L.nv, rec, L.n, tstart, pv.ent, capacity, kSortSmall, flags);
+  sort_tiles_kernel<kSortMax><<<grid, 1024, 0, st>>>(cams, L.nv, rec, L.n, tstart, pv.ent, capacity, kSortMid, flags);
   return hipGetLastError();
 }
 

@@ -12,7 +12,6 @@ namespace wsr {
 constexpr int kWave = 64;
 constexpr int kBinChunk = 2048;       // Gaussians per binning block
 constexpr int kTileChunk = 14336;     // tiles per binning LDS histogram (56 KB + static < 64 KB)
-constexpr int kScanItems = 4096;      // elements per scan block (256 threads x 16)
 constexpr int kRasterBatch = 256;     // splats staged in LDS per batch
 constexpr int kItemSplats = 1024;     // a tile's list is split into raster work items of at most this many
 constexpr int kProjBlock = 256;
@@ -40,9 +39,9 @@ struct __align__(16) SplatRec {
 };
 
 // The record as stored in HBM: 64 bytes, so that no record straddles a cache
-// line, with the pair-slot data the raster backward needs appended:
-//   slot = (goff, rect.x, rect.y, depth): the Gaussian's first Gaussian-major
-//   pair slot (written by binning), its tile rectangle (x0 | x1 << 16,
+// line, with the pair-slot data the raster backward needs appended (the
+// Gaussian's first Gaussian-major slot itself is in the dense goff array):
+//   slot = (0, rect.x, rect.y, depth): its tile rectangle (x0 | x1 << 16,
 //   y0 | y1 << 16) and its camera depth t_z as float bits (the sort key of
 //   the sorted-blending baseline; positive, so the bits order like the
 //   values) -- in OIT mode the opacity u instead, which Eq. 2's coverage
@@ -55,22 +54,23 @@ struct __align__(64) DevSplat {
 // The caller's pair buffer (capacity entries of kPairBytes bytes): per
 // (tile, Gaussian) pair a 36-byte partial 2D gradient, written by the raster
 // backward at the pair's Gaussian-major slot (the Gaussian's pair offset plus
-// the tile's row-major index inside the Gaussian's tile rectangle), the
-// Gaussian id at each position of the per-tile lists, and in OIT mode the
-// pair's partial dL/du through the coverage term (Gaussian-major, like the
-// 2D gradient).
-constexpr int64_t kPairBytes = 44;
+// the tile's row-major index inside the Gaussian's tile rectangle), in OIT
+// mode the pair's partial dL/du through the coverage term (Gaussian-major,
+// like the 2D gradient), and the per-tile lists: at each list position the
+// Gaussian id and that pair's Gaussian-major slot, which the binning knows
+// when it places the id, so the backward reads it with the id.
+constexpr int64_t kPairBytes = 48;
 struct PairView {
   float3* part;        // [capacity][3] float3: (mu_x, mu_y, A) (B, C, r) (g, b, a)
-  uint32_t* ids;       // [capacity]
   float* du;           // [capacity]
+  uint2* ent;          // [capacity] list entries: (Gaussian id, Gaussian-major slot)
 };
 __host__ __device__ inline PairView pair_view(const void* pairs, int64_t capacity) {
   char* b = static_cast<char*>(const_cast<void*>(pairs));
   PairView v;
   v.part = reinterpret_cast<float3*>(b);
-  v.ids = reinterpret_cast<uint32_t*>(b + 36 * capacity);
-  v.du = reinterpret_cast<float*>(b + 40 * capacity);
+  v.du = reinterpret_cast<float*>(b + 36 * capacity);
+  v.ent = reinterpret_cast<uint2*>(b + 40 * capacity);  // 8-byte aligned for any capacity
   return v;
 }
 

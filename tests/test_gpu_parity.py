@@ -178,10 +178,10 @@ def test_every_pair_slot_is_written_by_the_backward(c1, oit):
     g = globals_tensor(st)
     ctx.project(dev, g)
     ctx.bin(grow=True)
-    # pair buffer layout: [capacity][36 B] partials, [capacity] ids, [capacity] dL/du
-    assert ctx.pair_bytes == 44
+    # pair buffer layout: [capacity][36 B] partials, [capacity] dL/du, [capacity] (id, slot) list entries
+    assert ctx.pair_bytes == 48
     ctx.pairs[: 36 * ctx.capacity].fill_(0xFF)                     # every partial slot NaN
-    ctx.pairs[40 * ctx.capacity: 44 * ctx.capacity].fill_(0xFF)    # and every dL/du slot
+    ctx.pairs[36 * ctx.capacity: 40 * ctx.capacity].fill_(0xFF)    # and every dL/du slot
     ctx.bin(grow=False)
     rgb, den = ctx.render_fwd(g)
     r = ws.upstream_grad(cams, seed=3)
@@ -586,7 +586,8 @@ def test_full_step_is_bit_reproducible(config, oit):
         gr = ctx.render_bwd(dev, g, dL, rgb, den, grad2d=grad2d)
         torch.cuda.synchronize()
         ctx.check()
-        ids = ctx.pairs[36 * ctx.capacity: 36 * ctx.capacity + 4 * ctx.last_pairs].clone()
+        # the list entries: (Gaussian id, Gaussian-major slot) per position
+        ids = ctx.pairs[40 * ctx.capacity: 40 * ctx.capacity + 8 * ctx.last_pairs].clone()
         outs.append((ids, rgb, den, grad2d, gr))
         del ctx
     (i1, r1, d1, q1, g1), (i2, r2, d2, q2, g2) = outs
