@@ -283,32 +283,48 @@ __device__ inline uint32_t block_scan_1024(uint32_t v, uint32_t* sh, uint32_t* t
 
 // One workgroup, after the column prefixes: the exclusive scan of the tile
 // totals in place (tile_start; 64-bit running total, so a pair count beyond
-// 32 bits is detected), the overflow flags, and the raster work items --
+// 32 bits is detected), the overflow flags, the raster work items --
 // max(1, ceil(list length / kItemSplats)) per tile -- with their exclusive
-// scan (items[total_tiles] = number of items).  Replaces three 3-kernel
-// scans for the tile-sized arrays.
+// scan (items[total_tiles] = number of items), and their dispatch order.
+// One pass over the tiles forms the starts, the item counts and the order
+// histogram; a second places the tiles in the order.
 constexpr int kTileScanThreads = 1024;
 constexpr int kTileScanPer = 8;
 constexpr int kOrderBuckets = kItemSplats / 32 + 1;
 
-// Bucket of tile t in the dispatch order: longest last work item first.
-// tile_start already holds the exclusive scan (tile_start[total_tiles] is
-// the total).
-__device__ __forceinline__ int order_bucket(const uint32_t* tile_start, int64_t t, uint64_t cap) {
-  uint64_t a = tile_start[t], e = tile_start[t + 1];
+// A tile's list length with both ends capped at the pair capacity.
+__device__ __forceinline__ uint64_t capped_len(uint64_t a, uint64_t e, uint64_t cap) {
   a = a < cap ? a : cap;
   e = e < cap ? e : cap;
-  const uint64_t l = e > a ? e - a : 0;
+  return e > a ? e - a : 0;
+}
+
+// Bucket of a tile in the dispatch order, from its (capped) list length:
+// longest last work item first.
+__device__ __forceinline__ int order_bucket(uint64_t l) {
   const uint64_t last = l == 0 ? 0 : l - ((l - 1) / kItemSplats) * kItemSplats;  // in [1, kItemSplats]
   return kOrderBuckets - 1 - static_cast<int>(last / 32);
 }
+
+// Dispatch order of the work items.  Items that hold a full kItemSplats
+// splats run first (in tile order: dispatch slot i < F, F the number of such
+// items, is tile t's full item i - (items[t] - t)); then every tile's last
+// item, longest first: tile_order lists the tiles by the length of that
+// item, counting-sorted in buckets of 32 splats.  Heavy items start early,
+// so the launch ends on short ones instead of waiting for a late heavy one.
+// Only the order of execution changes (within a bucket it varies from run
+// to run): every item writes the same outputs.
 __global__ __launch_bounds__(kTileScanThreads) void tile_scan_single(uint32_t* tile_start, int64_t total_tiles,
                                                                      uint32_t* items, uint32_t* tile_order,
                                                                      DevFlags* flags, int64_t capacity) {
   __shared__ uint32_t sh[16];
+  __shared__ uint32_t bucket[kOrderBuckets];
+  for (int k = threadIdx.x; k < kOrderBuckets; k += kTileScanThreads) bucket[k] = 0u;
   const int64_t len = total_tiles + 1;
+  const uint64_t cap = static_cast<uint64_t>(capacity);
   constexpr int64_t kChunk = static_cast<int64_t>(kTileScanThreads) * kTileScanPer;
   uint64_t carry = 0;
+  uint32_t icarry = 0;
   for (int64_t c0 = 0; c0 < len; c0 += kChunk) {
     const int64_t base = c0 + static_cast<int64_t>(threadIdx.x) * kTileScanPer;
     uint32_t vals[kTileScanPer];
@@ -319,75 +335,49 @@ __global__ __launch_bounds__(kTileScanThreads) void tile_scan_single(uint32_t* t
       s += vals[k];
     }
     uint32_t tot;
-    uint64_t run = carry + block_scan_1024(s, sh, &tot);
+    uint64_t run = carry + block_scan_1024(s, sh, &tot);  // (its first barrier also orders the bucket clear)
+    uint32_t icnt[kTileScanPer];
+    uint32_t is = 0;
 #pragma unroll
     for (int k = 0; k < kTileScanPer; ++k) {
-      if (base + k < len) tile_start[base + k] = static_cast<uint32_t>(run);
+      const int64_t t = base + k;
+      if (t < len) tile_start[t] = static_cast<uint32_t>(run);
+      icnt[k] = 0u;
+      if (t < total_tiles) {
+        // from the 32-bit starts as stored, which the placement pass reads
+        const uint64_t l = capped_len(static_cast<uint32_t>(run), static_cast<uint32_t>(run + vals[k]), cap);
+        icnt[k] = static_cast<uint32_t>(l == 0 ? 1 : (l + kItemSplats - 1) / kItemSplats);
+        atomicAdd(&bucket[order_bucket(l)], 1u);
+      }
+      is += icnt[k];
       run += vals[k];
     }
     carry += tot;
+    uint32_t itot;
+    uint32_t irun = icarry + block_scan_1024(is, sh, &itot);
+#pragma unroll
+    for (int k = 0; k < kTileScanPer; ++k) {
+      if (base + k < len) items[base + k] = irun;
+      irun += icnt[k];
+    }
+    icarry += itot;
   }
   if (threadIdx.x == 0) {
     flags->total_pairs = carry;
     flags->wrapped = carry > 0xffffffffull ? 1u : 0u;
     flags->overflow = (carry > static_cast<uint64_t>(capacity) || carry > 0xffffffffull) ? 1u : 0u;
     flags->sort_overflow = 0u;
-  }
-  __syncthreads();
-  const uint64_t cap = static_cast<uint64_t>(capacity);
-  uint32_t icarry = 0;
-  for (int64_t c0 = 0; c0 < len; c0 += kChunk) {
-    const int64_t base = c0 + static_cast<int64_t>(threadIdx.x) * kTileScanPer;
-    uint32_t vals[kTileScanPer];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kTileScanPer; ++k) {
-      const int64_t t = base + k;
-      uint32_t cnt = 0;
-      if (t < total_tiles) {
-        uint64_t a = tile_start[t], e = tile_start[t + 1];
-        a = a < cap ? a : cap;
-        e = e < cap ? e : cap;
-        const uint64_t l = e > a ? e - a : 0;
-        cnt = static_cast<uint32_t>(l == 0 ? 1 : (l + kItemSplats - 1) / kItemSplats);
-      }
-      vals[k] = cnt;
-      s += cnt;
+    uint32_t r = 0;
+    for (int k = 0; k < kOrderBuckets; ++k) {
+      const uint32_t c = bucket[k];
+      bucket[k] = r;
+      r += c;
     }
-    uint32_t tot;
-    uint32_t run = icarry + block_scan_1024(s, sh, &tot);
-#pragma unroll
-    for (int k = 0; k < kTileScanPer; ++k) {
-      if (base + k < len) items[base + k] = run;
-      run += vals[k];
-    }
-    icarry += tot;
   }
-  // Dispatch order of the work items.  Items that hold a full kItemSplats
-  // splats run first (in tile order: dispatch slot i < F, F the number of such
-  // items, is tile t's full item i - (items[t] - t)); then every tile's last
-  // item, longest first: tile_order lists the tiles by the length of that
-  // item, counting-sorted in buckets of 32 splats.  Heavy items start early,
-  // so the launch ends on short ones instead of waiting for a late heavy one.
-  // Only the order of execution changes (within a bucket it varies from run
-  // to run): every item writes the same outputs.
-  __shared__ uint32_t bucket[kOrderBuckets];
-  for (int b = threadIdx.x; b < kOrderBuckets; b += kTileScanThreads) bucket[b] = 0u;
-  __syncthreads();
+  __syncthreads();  // the starts of every tile and the bucket offsets are in place
   for (int64_t t = threadIdx.x; t < total_tiles; t += kTileScanThreads)
-    atomicAdd(&bucket[order_bucket(tile_start, t, cap)], 1u);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int b = 0; b < kOrderBuckets; ++b) {
-      const uint32_t c = bucket[b];
-      bucket[b] = run;
-      run += c;
-    }
-  }
-  __syncthreads();
-  for (int64_t t = threadIdx.x; t < total_tiles; t += kTileScanThreads)
-    tile_order[atomicAdd(&bucket[order_bucket(tile_start, t, cap)], 1u)] = static_cast<uint32_t>(t);
+    tile_order[atomicAdd(&bucket[order_bucket(capped_len(tile_start[t], tile_start[t + 1], cap))], 1u)] =
+        static_cast<uint32_t>(t);
 }
 
 // Exclusive scan (in place) of the per-(view, block) rectangle sums, in
