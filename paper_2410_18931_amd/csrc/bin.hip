@@ -10,8 +10,9 @@
 //   2. column_scan_wide: each tile's column of M becomes exclusive prefixes
 //      over the blocks, and the tile's total; tile_scan_single scans the
 //      totals into the start of every tile's list (tile_start).
-//   3. bin_pass<scatter>: the same blocks re-expand their pairs and place ids
-//      at tile_start[t] + M[v][b][t] + the pair's stable rank in the block.
+//   3. bin_pass<scatter>: the same blocks re-expand their pairs and place
+//      each pair's entry (Gaussian id, Gaussian-major slot, see below) at
+//      tile_start[t] + M[v][b][t] + the pair's stable rank in the block.
 // Pairs are expanded load-balanced: per round of 256 Gaussians a block-wide
 // scan of the pair counts lets every thread take every 256th pair, so one
 // huge splat does not serialise on one thread.  The scatter is stable: every
