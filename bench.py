@@ -54,16 +54,16 @@ def flops_per_pair(kernel: str, oit: bool) -> int:
 TRAFFIC = [
     {"kernel": "raster_bwd", "source": "raster.hip", "source_sha": "f9a99dedc04172bd",
      "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 0.0},
-     "fetch_kib": 553566.7, "write_kib": 540884.1,
-     "fetch_factor": 262157.7 / 524288.0, "write_factor": 524288.0 / 524288.0},
+     "fetch_kib": 553945.6, "write_kib": 540877.8,
+     "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
     {"kernel": "raster_bwd", "source": "raster.hip", "source_sha": "f9a99dedc04172bd",
      "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": True, "alpha_cut": 0.0},
-     "fetch_kib": 511918.4, "write_kib": 736587.7,
-     "fetch_factor": 262157.7 / 524288.0, "write_factor": 524288.0 / 524288.0},
+     "fetch_kib": 511970.4, "write_kib": 736618.0,
+     "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
     {"kernel": "raster_bwd", "source": "raster.hip", "source_sha": "f9a99dedc04172bd",
      "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 1.0 / 255.0},
-     "fetch_kib": 510771.8, "write_kib": 495749.3,
-     "fetch_factor": 262157.7 / 524288.0, "write_factor": 524288.0 / 524288.0},
+     "fetch_kib": 511453.2, "write_kib": 495680.3,
+     "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
 ]
 
 
