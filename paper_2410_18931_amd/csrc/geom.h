@@ -105,10 +105,10 @@ __device__ inline bool view_geom(const DevCamera& cam, double p0, double p1, dou
   return fabs(g->mux) < 4194304.0 && fabs(g->muy) < 4194304.0;
 }
 
-// Unit direction from the camera centre (-W^T T) to p.
-__device__ inline void view_dir(const ViewGeom& g, const DevCamera& cam, double p0, double p1, double p2,
-                                double d[3], double* len) {
-  const double* W = g.W;
+// Unit direction from the camera centre (-W^T T) to p, W the camera
+// rotation (as view_geom reads it from the camera).
+__device__ inline void view_dir_w(const double* W, const DevCamera& cam, double p0, double p1, double p2,
+                                  double d[3], double* len) {
   const double fx = -(W[0] * cam.T[0] + W[3] * cam.T[1] + W[6] * cam.T[2]);
   const double fy = -(W[1] * cam.T[0] + W[4] * cam.T[1] + W[7] * cam.T[2]);
   const double fz = -(W[2] * cam.T[0] + W[5] * cam.T[1] + W[8] * cam.T[2]);
@@ -118,6 +118,20 @@ __device__ inline void view_dir(const ViewGeom& g, const DevCamera& cam, double 
   d[0] = vx * il;
   d[1] = vy * il;
   d[2] = vz * il;
+}
+
+__device__ inline void view_dir(const ViewGeom& g, const DevCamera& cam, double p0, double p1, double p2,
+                                double d[3], double* len) {
+  view_dir_w(g.W, cam, p0, p1, p2, d, len);
+}
+
+// The same direction straight from the camera, before (or without) view_geom.
+__device__ inline void view_dir_cam(const DevCamera& cam, double p0, double p1, double p2, double d[3],
+                                    double* len) {
+  double W[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
+  view_dir_w(W, cam, p0, p1, p2, d, len);
 }
 
 }  // namespace wsr

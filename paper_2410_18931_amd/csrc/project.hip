@@ -48,7 +48,11 @@ __device__ inline uint32_t half_bits_up(float x) {
   return b;
 }
 
-template <int S, int DEG>
+// ONE: a single view.  The colour and opacity are evaluated first, from the
+// direction to the camera centre, so the SH coefficients are dead before the
+// FP64 geometry needs its registers (one view needs them only once); with
+// several views the coefficients stay live across the view loop.
+template <int S, int DEG, bool ONE>
 __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kProjBlock + threadIdx.x;
   if (i >= a.n) return;
@@ -71,20 +75,15 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
   const float lcv = a.weight_kind == WSR_WEIGHT_LC ? a.lc_v[i] : 0.f;
   const float sigma = a.globals[0], beta = a.globals[1];
 
-  for (int v = 0; v < a.nv; ++v) {
+  const int nv = ONE ? 1 : a.nv;
+  for (int v = 0; v < nv; ++v) {
     const DevCamera& cam = a.cams[v];
     const int64_t slot = static_cast<int64_t>(v) * n + i;
-    // ---- a2, a3: view transform, cull, EWA ----
-    ViewGeom g;
-    const bool vis = view_geom(cam, p0, p1, p2, S3, qs.ok, a.near_z, a.dilation, &g);
-    float rgb[3] = {0.f, 0.f, 0.f};
-    float u = 0.f, w = 0.f;
-    uint2 rect = make_uint2(0u, 0u);
-    bool alive = vis;
-    if (vis) {
-      // ---- a4: SH colour and opacity at the view direction ----
-      double dir[3], len;
-      view_dir(g, cam, p0, p1, p2, dir, &len);
+    // ---- a4: SH colour and opacity at the view direction ----
+    double dir[3], len;
+    view_dir_cam(cam, p0, p1, p2, dir, &len);
+    float rgb[3], u;
+    {
       float Y[K];
       sh_eval<DEG>(static_cast<float>(dir[0]), static_cast<float>(dir[1]), static_cast<float>(dir[2]), Y);
       float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -99,6 +98,37 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
       rgb[1] = fmaxf(acc.y + 0.5f, 0.f);
       rgb[2] = fmaxf(acc.z + 0.5f, 0.f);
       u = a.opa_mode == WSR_OPACITY_SH ? acc.w + a.opacity_offset : 1.f / (1.f + expf(-logit));
+    }
+    // ---- opacity early-out (App. D; off with alpha_cut = 0): a pair
+    // contributes only while u exp(-q/2) >= alpha_cut, i.e. while
+    // q <= 2 ln(u / alpha_cut); a Gaussian with u <= alpha_cut never does.
+    // The cutoff is a support decision, so u is evaluated again in double
+    // precision for it (the float32 u above carries the SH sum's rounding,
+    // which would move the cutoff by far more than the float rounding of
+    // q); the only float32 step left is the rounding of the cutoff itself.
+    double u64 = 0.0;
+    if (a.alpha_cut > 0.f) {
+      if (a.opa_mode == WSR_OPACITY_SH) {
+        double Y64[K];
+        sh_eval_f64<DEG>(dir[0], dir[1], dir[2], Y64);
+        u64 = a.opacity_offset;
+#pragma unroll
+        for (int k = 0; k < K; ++k) u64 = fma(static_cast<double>(coef[k].w), Y64[k], u64);
+      } else {
+        u64 = 1.0 / (1.0 + exp(-static_cast<double>(logit)));
+      }
+    }
+    // ---- a2, a3: view transform, cull, EWA ----
+    ViewGeom g;
+    const bool vis = view_geom(cam, p0, p1, p2, S3, qs.ok, a.near_z, a.dilation, &g);
+    float w = 0.f;
+    uint2 rect = make_uint2(0u, 0u);
+    bool alive = vis;
+    if (!vis) {
+      rgb[0] = rgb[1] = rgb[2] = 0.f;
+      u = 0.f;
+    }
+    if (vis) {
       // ---- a5: depth weight ----
       const float d = static_cast<float>(g.tz);
       if (a.weight_kind == WSR_WEIGHT_DIR) {
@@ -108,30 +138,12 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
       } else {
         w = fmaxf(1.f - d / sigma, 0.f) * lcv;
       }
-
-      // ---- opacity early-out (App. D; off with alpha_cut = 0): a pair
-      // contributes only while u exp(-q/2) >= alpha_cut, i.e. while
-      // q <= 2 ln(u / alpha_cut); a Gaussian with u <= alpha_cut never does.
-      // The cutoff is a support decision, so u is evaluated again in double
-      // precision for it (the float32 u above carries the SH sum's rounding,
-      // which would move the cutoff by far more than the float rounding of
-      // q); the only float32 step left is the rounding of the cutoff itself.
       double cut = a.tau;
       if (a.alpha_cut > 0.f) {
-        double u64;
-        if (a.opa_mode == WSR_OPACITY_SH) {
-          double Y64[K];
-          sh_eval_f64<DEG>(dir[0], dir[1], dir[2], Y64);
-          u64 = a.opacity_offset;
-#pragma unroll
-          for (int k = 0; k < K; ++k) u64 = fma(static_cast<double>(coef[k].w), Y64[k], u64);
-        } else {
-          u64 = 1.0 / (1.0 + exp(-static_cast<double>(logit)));
-        }
         alive = u64 > a.alpha_cut;
         if (alive) cut = fmin(cut, 2.0 * log(u64 / static_cast<double>(a.alpha_cut)));
       }
-      // ---- support box of q <= cut, widened so float rounding of q never
+    // ---- support box of q <= cut, widened so float rounding of q never
       // reaches a pixel outside it ----
       const double ex = sqrt(cut * g.c00) * (1.0 + 1e-4) + 1e-3;
       const double ey = sqrt(cut * g.c11) * (1.0 + 1e-4) + 1e-3;
@@ -177,15 +189,23 @@ __global__ __launch_bounds__(kProjBlock) void project_kernel(ProjArgs a) {
   }
 }
 
+template <int S, bool ONE>
+void launch_sd(const ProjArgs& a, int deg, dim3 grid, hipStream_t st) {
+  switch (deg) {
+    case 0: project_kernel<S, 0, ONE><<<grid, kProjBlock, 0, st>>>(a); break;
+    case 1: project_kernel<S, 1, ONE><<<grid, kProjBlock, 0, st>>>(a); break;
+    case 2: project_kernel<S, 2, ONE><<<grid, kProjBlock, 0, st>>>(a); break;
+    default: project_kernel<S, 3, ONE><<<grid, kProjBlock, 0, st>>>(a); break;
+  }
+}
+
 template <int S>
 hipError_t launch_s(const ProjArgs& a, int deg, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>((a.n + kProjBlock - 1) / kProjBlock));
-  switch (deg) {
-    case 0: project_kernel<S, 0><<<grid, kProjBlock, 0, st>>>(a); break;
-    case 1: project_kernel<S, 1><<<grid, kProjBlock, 0, st>>>(a); break;
-    case 2: project_kernel<S, 2><<<grid, kProjBlock, 0, st>>>(a); break;
-    default: project_kernel<S, 3><<<grid, kProjBlock, 0, st>>>(a); break;
-  }
+  if (a.nv == 1)
+    launch_sd<S, true>(a, deg, grid, st);
+  else
+    launch_sd<S, false>(a, deg, grid, st);
   return hipGetLastError();
 }
 
