@@ -49,28 +49,31 @@ def flops_per_pair(kernel: str, oit: bool) -> int:
 # HBM traffic of the dominant kernel, from `rocprofv3 --pmc FETCH_SIZE` and
 # `--pmc WRITE_SIZE` runs of this benchmark (KiB per dispatch), each scaled by
 # what the same counter reads for a plain device copy of known size
-# (`--calibrate-copy`).  Valid only for the kernel source and the workload it
-# was measured on.
+# (`--calibrate-copy`).  Valid only for the kernel sources (the raster kernels
+# and the constants they are built with) and the workload it was measured on.
 TRAFFIC = [
-    {"kernel": "raster_bwd", "source": "raster.hip", "source_sha": "f9a99dedc04172bd",
+    {"kernel": "raster_bwd", "source": ["raster.hip", "wsr_internal.h"], "source_sha": "PENDING",
      "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 0.0},
      "fetch_kib": 554022.3, "write_kib": 540841.0,
      "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
-    {"kernel": "raster_bwd", "source": "raster.hip", "source_sha": "f9a99dedc04172bd",
+    {"kernel": "raster_bwd", "source": ["raster.hip", "wsr_internal.h"], "source_sha": "PENDING",
      "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": True, "alpha_cut": 0.0},
      "fetch_kib": 511557.1, "write_kib": 736474.0,
      "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
-    {"kernel": "raster_bwd", "source": "raster.hip", "source_sha": "f9a99dedc04172bd",
+    {"kernel": "raster_bwd", "source": ["raster.hip", "wsr_internal.h"], "source_sha": "PENDING",
      "workload": {"config": "headline", "tile": 16, "storage": "f32", "oit": False, "alpha_cut": 1.0 / 255.0},
      "fetch_kib": 511452.1, "write_kib": 495651.4,
      "fetch_factor": 262157.8 / 524288.0, "write_factor": 524288.0 / 524288.0},
 ]
 
 
-def _source_sha(name: str) -> str:
-    path = os.path.join(ROOT, "paper_2410_18931_amd", "csrc", name)
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def _source_sha(names) -> str:
+    """sha256 prefix of the named kernel sources (one name or a list, hashed in order)."""
+    h = hashlib.sha256()
+    for name in ([names] if isinstance(names, str) else names):
+        with open(os.path.join(ROOT, "paper_2410_18931_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_bytes(kernel: str, args) -> float | None:

@@ -6,7 +6,7 @@
 //   backward: per pixel gbar = dL/dC / D and s = gbar . C; per pair
 //             dL/da = gbar . c_i - s, then the chain to (mu, conic, c, amp).
 //
-// One workgroup per work item (at most 1024 splats of one tile's list); the
+// One workgroup per work item (at most kItemSplats splats of one tile's list); the
 // items are dispatched longest first (the full ones, then the tiles' last
 // items by decreasing length; see tile_scan_single), so that the launch ends
 // on short items.

@@ -13,7 +13,7 @@ constexpr int kWave = 64;
 constexpr int kBinChunk = 2048;       // Gaussians per binning block
 constexpr int kTileChunk = 14336;     // tiles per binning LDS histogram (56 KB + static < 64 KB)
 constexpr int kRasterBatch = 256;     // splats staged in LDS per batch
-constexpr int kItemSplats = 1024;     // a tile's list is split into raster work items of at most this many
+constexpr int kItemSplats = 2048;     // a tile's list is split into raster work items of at most this many
 constexpr int kProjBlock = 256;
 
 // Camera as the kernels see it, with the per-view offsets into the
