@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define WSR_ABI_VERSION 5
+#define WSR_ABI_VERSION 6
 #define WSR_MAX_VIEWS 256
 
 typedef enum {
@@ -236,6 +236,39 @@ int32_t wsr_project_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t 
                         const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
                         const void* pairs, int64_t capacity, const wsr_grads* grads,
                         float* out_grad2d, void* stream);
+
+/* Adam settings of wsr_project_bwd_adam: one learning rate per attribute
+ * group, the decay rates, eps and the step number (from 1) of the bias
+ * correction, as in wsr_adam. */
+typedef struct {
+    float lr_means, lr_log_scales, lr_quats;
+    float lr_sh0;              /* SH coefficient 0 (RGBA) */
+    float lr_shN;              /* SH coefficients 1..K-1 */
+    float lr_opacity_logit, lr_lc_v;
+    float beta1, beta2, eps;
+    int32_t step;
+    int32_t reserved_;
+} wsr_adam_params;
+
+/* wsr_project_bwd and one Adam step (wsr_adam's update) of the per-Gaussian
+ * parameters in a single pass, for the training step of Sec. 5: every
+ * gradient is applied where it is formed instead of being written to memory
+ * and read back.  The result is bit for bit that of wsr_project_bwd followed
+ * by wsr_adam on each array with the same settings.  The scene must use
+ * FP32 storage and its arrays must be writable DEVICE memory: means,
+ * log_scales, quats and sh are updated in place, and opacity_logit and lc_v
+ * too where they, m's and v's fields are all non-NULL.  m and v (DEVICE,
+ * the layouts of wsr_grads, `globals` fields unused) are the first and
+ * second moments, read and written.  grad_globals (DEVICE [6]) receives the
+ * gradient of the global parameters (WSR_GLOBALS), which this call does not
+ * update (wsr_adam does, on the caller's side).  Returns WSR_ERR_INVALID for
+ * 16-bit storage, missing arrays, step < 1 or a beta outside [0, 1),
+ * before anything is enqueued. */
+int32_t wsr_project_bwd_adam(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views,
+                             const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
+                             const void* pairs, int64_t capacity, const wsr_grads* m, const wsr_grads* v,
+                             const wsr_adam_params* adam, float* grad_globals, float* out_grad2d,
+                             void* stream);
 
 /* Synchronises `stream` and returns, in *out_total, the number of
  * (tile, Gaussian) pairs the last wsr_bin on this workspace produced (the

@@ -17,12 +17,12 @@ WEIGHT_KINDS = {"dir": 0, "exp": 1, "lc": 2}
 OPACITY_MODES = {"logit": 0, "sh": 1}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 MAX_VIEWS = 256
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 EXPORTED = ("wsr_abi_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_pair_bytes", "wsr_project", "wsr_bin",
-            "wsr_render_fwd", "wsr_render_bwd", "wsr_raster_bwd", "wsr_project_bwd", "wsr_pair_count",
-            "wsr_check", "wsr_loss_workspace_bytes", "wsr_loss", "wsr_loss_noalloc", "wsr_adam", "wsr_sort_tiles",
-            "wsr_render_sorted")
+            "wsr_render_fwd", "wsr_render_bwd", "wsr_raster_bwd", "wsr_project_bwd", "wsr_project_bwd_adam",
+            "wsr_pair_count", "wsr_check", "wsr_loss_workspace_bytes", "wsr_loss", "wsr_loss_noalloc", "wsr_adam",
+            "wsr_sort_tiles", "wsr_render_sorted")
 
 
 class WsrScene(C.Structure):
@@ -63,6 +63,13 @@ class WsrGrads(C.Structure):
                 ("globals", C.c_void_p)]
 
 
+class WsrAdamParams(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_log_scales", C.c_float), ("lr_quats", C.c_float),
+                ("lr_sh0", C.c_float), ("lr_shN", C.c_float), ("lr_opacity_logit", C.c_float),
+                ("lr_lc_v", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32), ("reserved_", C.c_int32)]
+
+
 class WsrError(RuntimeError):
     def __init__(self, fn: str, status: int):
         super().__init__(f"{fn} failed: {status_string(status)} (status {status})")
@@ -99,6 +106,8 @@ def load():
     lib.wsr_raster_bwd.argtypes = [P, I32, P, I64, P, P, I64, P, I64, P, P, P, P]
     lib.wsr_project_bwd.restype = I32
     lib.wsr_project_bwd.argtypes = [P, P, I32, P, P, P, I64, P, I64, P, P, P]
+    lib.wsr_project_bwd_adam.restype = I32
+    lib.wsr_project_bwd_adam.argtypes = [P, P, I32, P, P, P, I64, P, I64, P, P, P, P, P, P]
     lib.wsr_pair_count.restype = I32
     lib.wsr_pair_count.argtypes = [P, I64, C.POINTER(C.c_int64), P]
     lib.wsr_check.restype = I32

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "adam.h"
 #include "wsr_internal.h"
 
 namespace wsr {
@@ -207,6 +208,34 @@ int32_t wsr_project_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t 
   if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
   return to_status(launch_project_bwd(scene, params, globals, L, ws, pairs, capacity, grads, out_grad2d,
                                       static_cast<hipStream_t>(stream)));
+}
+
+int32_t wsr_project_bwd_adam(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views,
+                             const wsr_params* params, const float* globals, void* ws, int64_t ws_bytes,
+                             const void* pairs, int64_t capacity, const wsr_grads* m, const wsr_grads* v,
+                             const wsr_adam_params* adam, float* grad_globals, float* out_grad2d,
+                             void* stream) {
+  if (!params_ok(params) || !scene_ok(scene, params->weight_kind) || !globals || !ws || !m || !v || !adam ||
+      !grad_globals || !pairs_ok(pairs, capacity))
+    return WSR_ERR_INVALID;
+  if (scene->storage != WSR_STORE_F32 || adam->step < 1 || !(adam->beta1 >= 0.f && adam->beta1 < 1.f) ||
+      !(adam->beta2 >= 0.f && adam->beta2 < 1.f))
+    return WSR_ERR_INVALID;
+  if (scene->n > 0 && (!m->means || !m->log_scales || !m->quats || !m->sh || !v->means || !v->log_scales ||
+                       !v->quats || !v->sh))
+    return WSR_ERR_INVALID;
+  Layout L;
+  if (!make_layout(scene->n, cams, n_views, params->tile, &L, nullptr)) return WSR_ERR_INVALID;
+  if (ws_bytes < static_cast<int64_t>(L.bytes)) return WSR_ERR_WORKSPACE;
+  FusedAdam f;
+  f.m = *m;
+  f.v = *v;
+  const float lr[7] = {adam->lr_means, adam->lr_log_scales, adam->lr_quats, adam->lr_sh0, adam->lr_shN,
+                       adam->lr_opacity_logit, adam->lr_lc_v};
+  for (int k = 0; k < 7; ++k) f.lr[k] = lr[k];
+  f.step = make_adam_step(adam->step, adam->beta1, adam->beta2, adam->eps);
+  return to_status(launch_project_bwd_adam(scene, params, globals, L, ws, pairs, capacity, f, grad_globals,
+                                           out_grad2d, static_cast<hipStream_t>(stream)));
 }
 
 int32_t wsr_render_bwd(const wsr_scene* scene, const wsr_camera* cams, int32_t n_views, const wsr_params* params,

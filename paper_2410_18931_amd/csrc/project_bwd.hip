@@ -9,6 +9,7 @@
 // gradient of Sigma3D is summed over views first and chained to (q, s) once.
 // The global parameters are reduced in double precision from per-block
 // partials (deterministic, no float atomics).
+#include "adam.h"
 #include "geom.h"
 #include "sh_basis.h"
 #include "wsr_internal.h"
@@ -36,9 +37,33 @@ struct BwdArgs {
   int32_t opa_mode;
   int32_t weight_kind;
   float near_z, dilation, opacity_offset;
+  // ADAM instances: the FP32 parameters (updated in place), the moments in
+  // the gradients' layout and one learning rate per group (means,
+  // log-scales, quaternions, SH degree 0, higher SH degrees, logit, v_i)
+  float* p_means;
+  float* p_log_scales;
+  float* p_quats;
+  float* p_sh;
+  float* p_logit;
+  float* p_lc_v;
+  wsr_grads m, v;
+  float lr[7];
+  AdamStep as;
 };
 
-template <int S, int DEG>
+// The parameter's new value, its moments updated in place (see adam.h).
+__device__ __forceinline__ void adam_store(float* p, float* m, float* v, int64_t o, float pv, float g, float mk,
+                                           float vk, float lr, const AdamStep& s) {
+  p[o] = adam_update(pv, g, mk, vk, lr, s);
+  m[o] = mk;
+  v[o] = vk;
+}
+
+// ADAM: instead of writing the per-Gaussian gradients, apply one Adam step to
+// the parameters with them (the values the plain instance writes, so both
+// paths give the same bits); the moments are read up front, before any
+// store, so that their loads are in flight together.
+template <int S, int DEG, bool ADAM>
 __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ double s_red[kBwdBlock / kWave][2];
@@ -246,17 +271,77 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
     const double proj = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
 
     const bool ok = qs.ok;
+    float gm[3], gl[3], gqt[4];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.g.means[c * n + i] = static_cast<float>(dp[c]);
+    for (int c = 0; c < 3; ++c) gm[c] = static_cast<float>(dp[c]);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.g.log_scales[c * n + i] = ok ? static_cast<float>(gs[c] * s[c]) : 0.f;
+    for (int c = 0; c < 3; ++c) gl[c] = ok ? static_cast<float>(gs[c] * s[c]) : 0.f;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a.g.quats[c * n + i] = ok ? static_cast<float>((gq[c] - qh[c] * proj) / qn) : 0.f;
-    float4* gsh = reinterpret_cast<float4*>(a.g.sh);
+    for (int c = 0; c < 4; ++c) gqt[c] = ok ? static_cast<float>((gq[c] - qh[c] * proj) / qn) : 0.f;
+    if (ADAM) {
+      const bool upd_logit = a.p_logit && a.m.opacity_logit && a.v.opacity_logit;
+      const bool upd_lcv = a.p_lc_v && a.m.lc_v && a.v.lc_v;
+      float mm[10], vm[10];
+      float4 msh[K], vsh[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) gsh[k * n + i] = dsh[k];
-    if (a.g.opacity_logit) a.g.opacity_logit[i] = dlogit;
-    if (a.g.lc_v) a.g.lc_v[i] = dv;
+      for (int c = 0; c < 3; ++c) {
+        mm[c] = a.m.means[c * n + i];
+        vm[c] = a.v.means[c * n + i];
+        mm[3 + c] = a.m.log_scales[c * n + i];
+        vm[3 + c] = a.v.log_scales[c * n + i];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        mm[6 + c] = a.m.quats[c * n + i];
+        vm[6 + c] = a.v.quats[c * n + i];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        msh[k] = reinterpret_cast<const float4*>(a.m.sh)[k * n + i];
+        vsh[k] = reinterpret_cast<const float4*>(a.v.sh)[k * n + i];
+      }
+      // the logit and v_i values were read above only where the modes use them
+      const float pl = upd_logit ? (a.opa_mode == WSR_OPACITY_LOGIT ? logit : a.p_logit[i]) : 0.f;
+      const float ml = upd_logit ? a.m.opacity_logit[i] : 0.f, vl = upd_logit ? a.v.opacity_logit[i] : 0.f;
+      const float pv = upd_lcv ? (a.weight_kind == WSR_WEIGHT_LC ? lcv : a.p_lc_v[i]) : 0.f;
+      const float mv = upd_lcv ? a.m.lc_v[i] : 0.f, vv = upd_lcv ? a.v.lc_v[i] : 0.f;
+      const float pmean[3] = {m0, m1, m2}, plog[3] = {l0, l1, l2};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        adam_store(a.p_means, a.m.means, a.v.means, c * n + i, pmean[c], gm[c], mm[c], vm[c], a.lr[0], a.as);
+        adam_store(a.p_log_scales, a.m.log_scales, a.v.log_scales, c * n + i, plog[c], gl[c], mm[3 + c],
+                   vm[3 + c], a.lr[1], a.as);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        adam_store(a.p_quats, a.m.quats, a.v.quats, c * n + i, rq[c], gqt[c], mm[6 + c], vm[6 + c], a.lr[2], a.as);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float lr = k == 0 ? a.lr[3] : a.lr[4];
+        float4 p4 = coef[k], m4 = msh[k], v4 = vsh[k];
+        p4.x = adam_update(p4.x, dsh[k].x, m4.x, v4.x, lr, a.as);
+        p4.y = adam_update(p4.y, dsh[k].y, m4.y, v4.y, lr, a.as);
+        p4.z = adam_update(p4.z, dsh[k].z, m4.z, v4.z, lr, a.as);
+        p4.w = adam_update(p4.w, dsh[k].w, m4.w, v4.w, lr, a.as);
+        reinterpret_cast<float4*>(a.p_sh)[k * n + i] = p4;
+        reinterpret_cast<float4*>(a.m.sh)[k * n + i] = m4;
+        reinterpret_cast<float4*>(a.v.sh)[k * n + i] = v4;
+      }
+      if (upd_logit) adam_store(a.p_logit, a.m.opacity_logit, a.v.opacity_logit, i, pl, dlogit, ml, vl, a.lr[5], a.as);
+      if (upd_lcv) adam_store(a.p_lc_v, a.m.lc_v, a.v.lc_v, i, pv, dv, mv, vv, a.lr[6], a.as);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.g.means[c * n + i] = gm[c];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.g.log_scales[c * n + i] = gl[c];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a.g.quats[c * n + i] = gqt[c];
+      float4* gsh = reinterpret_cast<float4*>(a.g.sh);
+#pragma unroll
+      for (int k = 0; k < K; ++k) gsh[k * n + i] = dsh[k];
+      if (a.g.opacity_logit) a.g.opacity_logit[i] = dlogit;
+      if (a.g.lc_v) a.g.lc_v[i] = dv;
+    }
   }
   // block partials of dL/dsigma, dL/dbeta
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
@@ -421,13 +506,13 @@ __global__ void fill_zero_kernel(uint32_t* p, int64_t words) {
   for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += stride) p[k] = 0u;
 }
 
-template <int S>
+template <int S, bool ADAM>
 hipError_t bwd_s(const BwdArgs& a, int deg, unsigned blocks, hipStream_t st) {
   switch (deg) {
-    case 0: project_bwd_kernel<S, 0><<<blocks, kBwdBlock, 0, st>>>(a); break;
-    case 1: project_bwd_kernel<S, 1><<<blocks, kBwdBlock, 0, st>>>(a); break;
-    case 2: project_bwd_kernel<S, 2><<<blocks, kBwdBlock, 0, st>>>(a); break;
-    default: project_bwd_kernel<S, 3><<<blocks, kBwdBlock, 0, st>>>(a); break;
+    case 0: project_bwd_kernel<S, 0, ADAM><<<blocks, kBwdBlock, 0, st>>>(a); break;
+    case 1: project_bwd_kernel<S, 1, ADAM><<<blocks, kBwdBlock, 0, st>>>(a); break;
+    case 2: project_bwd_kernel<S, 2, ADAM><<<blocks, kBwdBlock, 0, st>>>(a); break;
+    default: project_bwd_kernel<S, 3, ADAM><<<blocks, kBwdBlock, 0, st>>>(a); break;
   }
   return hipGetLastError();
 }
@@ -445,9 +530,11 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const float* globals,
-                              const Layout& L, void* ws, const void* pairs, int64_t capacity,
-                              const wsr_grads* g, float* out_grad2d, hipStream_t st) {
+// The projection backward; with `f` (FP32 storage only) the fused Adam
+// instances, which leave the per-Gaussian fields of g unused.
+static hipError_t project_bwd_impl(const wsr_scene* sc, const wsr_params* P, const float* globals,
+                                   const Layout& L, void* ws, const void* pairs, int64_t capacity,
+                                   const wsr_grads* g, const FusedAdam* f, float* out_grad2d, hipStream_t st) {
   double* gpart = at<double>(ws, L.off_gpart);
   const unsigned blocks = static_cast<unsigned>(project_bwd_blocks(L.n));
   hipError_t e = hipSuccess;
@@ -486,10 +573,25 @@ hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const fl
     a.near_z = P->near_z;
     a.dilation = P->dilation;
     a.opacity_offset = P->opacity_offset;
-    switch (sc->storage) {
-      case WSR_STORE_F16: e = bwd_s<WSR_STORE_F16>(a, sc->sh_degree, blocks, st); break;
-      case WSR_STORE_BF16: e = bwd_s<WSR_STORE_BF16>(a, sc->sh_degree, blocks, st); break;
-      default: e = bwd_s<WSR_STORE_F32>(a, sc->sh_degree, blocks, st); break;
+    if (f) {
+      if (sc->storage != WSR_STORE_F32) return hipErrorInvalidValue;
+      a.p_means = const_cast<float*>(static_cast<const float*>(sc->means));
+      a.p_log_scales = const_cast<float*>(static_cast<const float*>(sc->log_scales));
+      a.p_quats = const_cast<float*>(static_cast<const float*>(sc->quats));
+      a.p_sh = const_cast<float*>(static_cast<const float*>(sc->sh));
+      a.p_logit = const_cast<float*>(sc->opacity_logit);
+      a.p_lc_v = const_cast<float*>(sc->lc_v);
+      a.m = f->m;
+      a.v = f->v;
+      for (int k = 0; k < 7; ++k) a.lr[k] = f->lr[k];
+      a.as = f->step;
+      e = bwd_s<WSR_STORE_F32, true>(a, sc->sh_degree, blocks, st);
+    } else {
+      switch (sc->storage) {
+        case WSR_STORE_F16: e = bwd_s<WSR_STORE_F16, false>(a, sc->sh_degree, blocks, st); break;
+        case WSR_STORE_BF16: e = bwd_s<WSR_STORE_BF16, false>(a, sc->sh_degree, blocks, st); break;
+        default: e = bwd_s<WSR_STORE_F32, false>(a, sc->sh_degree, blocks, st); break;
+      }
     }
   } else {
     e = launch_fill_zero(gpart, 2 * sizeof(double), st);
@@ -498,6 +600,20 @@ hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const fl
   reduce_globals<<<1, 1024, 0, st>>>(gpart, static_cast<int64_t>(blocks), at<float>(ws, L.off_tilepart),
                                     L.total_tiles, g->globals);
   return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const wsr_scene* sc, const wsr_params* P, const float* globals,
+                              const Layout& L, void* ws, const void* pairs, int64_t capacity,
+                              const wsr_grads* g, float* out_grad2d, hipStream_t st) {
+  return project_bwd_impl(sc, P, globals, L, ws, pairs, capacity, g, nullptr, out_grad2d, st);
+}
+
+hipError_t launch_project_bwd_adam(const wsr_scene* sc, const wsr_params* P, const float* globals,
+                                   const Layout& L, void* ws, const void* pairs, int64_t capacity,
+                                   const FusedAdam& f, float* grad_globals, float* out_grad2d, hipStream_t st) {
+  wsr_grads g = {};
+  g.globals = grad_globals;
+  return project_bwd_impl(sc, P, globals, L, ws, pairs, capacity, &g, &f, out_grad2d, st);
 }
 
 }  // namespace wsr

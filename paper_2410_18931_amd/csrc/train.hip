@@ -21,6 +21,7 @@
 #include <cmath>
 #include <mutex>
 
+#include "adam.h"
 #include "wsr_internal.h"
 
 // Workspace of the allocation-free loss entry point: the derivative maps and
@@ -219,16 +220,13 @@ __global__ __launch_bounds__(256) void loss_finalize(const double* part, int64_t
 
 // Adam with bias correction; bc1 = 1 - beta1^t, bc2 = 1 - beta2^t.
 __global__ __launch_bounds__(256) void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n,
-                                                   float lr, float b1, float b2, float eps, float bc1,
-                                                   float bc2) {
+                                                   float lr, AdamStep as) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
   for (int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; k < n; k += stride) {
-    const float gk = g[k];
-    const float mk = fmaf(b1, m[k], (1.f - b1) * gk);
-    const float vk = fmaf(b2, v[k], (1.f - b2) * gk * gk);
+    float mk = m[k], vk = v[k];
+    p[k] = adam_update(p[k], g[k], mk, vk, lr, as);
     m[k] = mk;
     v[k] = vk;
-    p[k] -= lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
   }
 }
 
@@ -357,11 +355,9 @@ hipError_t loss_static_workspace(void** out) {
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int32_t step, float lr, float b1,
                        float b2, float eps, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  const float bc1 = static_cast<float>(1.0 - std::pow(static_cast<double>(b1), step));
-  const float bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(b2), step));
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  adam_kernel<<<static_cast<unsigned>(blocks), 256, 0, st>>>(p, g, m, v, n, lr, b1, b2, eps, bc1, bc2);
+  adam_kernel<<<static_cast<unsigned>(blocks), 256, 0, st>>>(p, g, m, v, n, lr, make_adam_step(step, b1, b2, eps));
   return hipGetLastError();
 }
 

@@ -195,19 +195,59 @@ class WSRContext:
             "globals": torch.empty((6,), dtype=torch.float32, device=dev),
         }
 
+    @staticmethod
+    def grads_struct(g: dict) -> _lib.WsrGrads:
+        """A wsr_grads struct over the tensors of a gradient-shaped dict (see
+        alloc_grads); also the layout of Adam's moments."""
+        return _lib.WsrGrads(g["means"].data_ptr(), g["log_scales"].data_ptr(), g["quats"].data_ptr(),
+                             g["sh"].data_ptr(), g["opacity_logit"].data_ptr(), g["lc_v"].data_ptr(),
+                             g["globals"].data_ptr())
+
     def render_bwd(self, scene: dict, globals_: torch.Tensor, dL_drgb: torch.Tensor, rgb: torch.Tensor,
                    den: torch.Tensor, grads: dict | None = None, grad2d: torch.Tensor | None = None) -> dict:
         sc = self.scene_struct(scene)
         g = self.alloc_grads(scene) if grads is None else grads
-        gs = _lib.WsrGrads(g["means"].data_ptr(), g["log_scales"].data_ptr(), g["quats"].data_ptr(),
-                           g["sh"].data_ptr(), g["opacity_logit"].data_ptr(), g["lc_v"].data_ptr(),
-                           g["globals"].data_ptr())
+        gs = self.grads_struct(g)
         dL = dL_drgb.contiguous()
         st = self.lib.wsr_render_bwd(C.byref(sc), self.cams_c, self.nv, C.byref(self.params), _ptr(globals_),
                                      _ptr(self.ws), self.ws_bytes, _ptr(self.pairs), self.capacity, _ptr(dL),
                                      _ptr(rgb), _ptr(den), C.byref(gs), _ptr(grad2d), _stream())
         _lib.check("wsr_render_bwd", st)
         return g
+
+    def raster_bwd(self, globals_: torch.Tensor, dL_drgb: torch.Tensor, rgb: torch.Tensor, den: torch.Tensor):
+        """wsr_raster_bwd: the per-pair partial 2D gradients (first half of
+        render_bwd)."""
+        dL = dL_drgb.contiguous()
+        st = self.lib.wsr_raster_bwd(self.cams_c, self.nv, C.byref(self.params), self.n, _ptr(globals_),
+                                     _ptr(self.ws), self.ws_bytes, _ptr(self.pairs), self.capacity, _ptr(dL),
+                                     _ptr(rgb), _ptr(den), _stream())
+        _lib.check("wsr_raster_bwd", st)
+
+    def project_bwd(self, scene: dict, globals_: torch.Tensor, grads: dict) -> dict:
+        """wsr_project_bwd after raster_bwd: the scene gradients into
+        ``grads`` (second half of render_bwd)."""
+        sc = self.scene_struct(scene)
+        gs = self.grads_struct(grads)
+        st = self.lib.wsr_project_bwd(C.byref(sc), self.cams_c, self.nv, C.byref(self.params), _ptr(globals_),
+                                      _ptr(self.ws), self.ws_bytes, _ptr(self.pairs), self.capacity, C.byref(gs),
+                                      None, _stream())
+        _lib.check("wsr_project_bwd", st)
+        return grads
+
+    def project_bwd_adam(self, scene: dict, globals_: torch.Tensor, m: dict, v: dict, adam: _lib.WsrAdamParams,
+                         grad_globals: torch.Tensor) -> None:
+        """wsr_project_bwd_adam after raster_bwd: one Adam step of the
+        scene's per-Gaussian float32 tensors in place, moments ``m`` and
+        ``v`` shaped like alloc_grads; the global parameters' gradient goes
+        to ``grad_globals`` [6]."""
+        sc = self.scene_struct(scene)
+        ms, vs = self.grads_struct(m), self.grads_struct(v)
+        st = self.lib.wsr_project_bwd_adam(C.byref(sc), self.cams_c, self.nv, C.byref(self.params), _ptr(globals_),
+                                           _ptr(self.ws), self.ws_bytes, _ptr(self.pairs), self.capacity,
+                                           C.byref(ms), C.byref(vs), C.byref(adam), _ptr(grad_globals), None,
+                                           _stream())
+        _lib.check("wsr_project_bwd_adam", st)
 
     def forward(self, scene: dict, globals_: torch.Tensor, grow: bool = True, count: bool = False):
         self.project(scene, globals_)

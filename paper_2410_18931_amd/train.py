@@ -86,10 +86,18 @@ def default_lrs(extent: float = 1.0) -> dict:
 class TrainStep:
     """One optimisation step over all views of ``ctx``: forward, loss,
     backward, Adam.  ``scene`` holds float32 device tensors that are updated
-    in place; ``targets`` is the concatenated [P][3] target image."""
+    in place; ``targets`` is the concatenated [P][3] target image.
+
+    With ``fused`` (the default) the per-Gaussian parameters take their Adam
+    step inside the projection backward (wsr_project_bwd_adam), and only the
+    six global parameters go through wsr_adam; otherwise the backward writes
+    every gradient and wsr_adam updates each parameter group.  Both give the
+    same bits."""
+
+    BETA1, BETA2, EPS = 0.9, 0.999, 1e-15
 
     def __init__(self, ctx: WSRContext, scene: dict, globals_: torch.Tensor, targets: torch.Tensor,
-                 lrs: dict | None = None, lam: float = 0.2, grow: bool = True):
+                 lrs: dict | None = None, lam: float = 0.2, grow: bool = True, fused: bool = True):
         for k in ("means", "log_scales", "quats", "sh"):
             if scene[k].dtype != torch.float32:
                 raise ValueError("training needs float32 attribute storage")
@@ -97,22 +105,31 @@ class TrainStep:
         self.lrs = dict(default_lrs(), **(lrs or {}))
         self.loss = Loss(ctx.cams, lam, device=ctx.device)
         self.grads = ctx.alloc_grads(scene)
+        # Adam's moments, laid out like the gradients
+        self.m = {k: torch.zeros_like(t) for k, t in self.grads.items()}
+        self.v = {k: torch.zeros_like(t) for k, t in self.grads.items()}
         self.grow = grow
+        self.fused = fused
         self.it = 0
-        self._groups = []   # (param view, grad view, lr key)
-        sh, gsh = scene["sh"], self.grads["sh"]
-        for key, p, g in (("means", scene["means"], self.grads["means"]),
-                          ("log_scales", scene["log_scales"], self.grads["log_scales"]),
-                          ("quats", scene["quats"], self.grads["quats"]),
-                          ("opacity_logit", scene["opacity_logit"], self.grads["opacity_logit"]),
-                          ("lc_v", scene["lc_v"], self.grads["lc_v"]),
-                          ("sh0", sh[0], gsh[0]),
-                          ("shN", sh[1:], gsh[1:]),
-                          ("globals", globals_, self.grads["globals"])):
+        self._groups = []   # (param view, grad view, lr key, m view, v view)
+        for key, p, field, sl in (("means", scene["means"], "means", None),
+                                  ("log_scales", scene["log_scales"], "log_scales", None),
+                                  ("quats", scene["quats"], "quats", None),
+                                  ("opacity_logit", scene["opacity_logit"], "opacity_logit", None),
+                                  ("lc_v", scene["lc_v"], "lc_v", None),
+                                  ("sh0", scene["sh"][0], "sh", 0),
+                                  ("shN", scene["sh"][1:], "sh", slice(1, None)),
+                                  ("globals", globals_, "globals", None)):
             if p.numel() == 0:
                 continue
-            self._groups.append((p, g, key, torch.zeros_like(p), torch.zeros_like(p)))
+            pick = (lambda t: t) if sl is None else (lambda t, sl=sl: t[sl])
+            self._groups.append((p, pick(self.grads[field]), key, pick(self.m[field]), pick(self.v[field])))
         self.dL = torch.empty((ctx.total_pixels, 3), dtype=torch.float32, device=ctx.device)
+
+    def adam_params(self, step: int) -> _lib.WsrAdamParams:
+        lr = self.lrs
+        return _lib.WsrAdamParams(lr["means"], lr["log_scales"], lr["quats"], lr["sh0"], lr["shN"],
+                                  lr["opacity_logit"], lr["lc_v"], self.BETA1, self.BETA2, self.EPS, int(step), 0)
 
     def step(self) -> torch.Tensor:
         ctx = self.ctx
@@ -120,8 +137,15 @@ class TrainStep:
         ctx.bin(grow=self.grow)
         rgb, den = ctx.render_fwd(self.globals_)
         value, _ = self.loss(rgb, self.targets, self.dL)
-        ctx.render_bwd(self.scene, self.globals_, self.dL, rgb, den, grads=self.grads)
         self.it += 1
-        for p, g, key, m, v in self._groups:
-            adam_(p, g, m, v, self.it, self.lrs[key])
+        if self.fused:
+            ctx.raster_bwd(self.globals_, self.dL, rgb, den)
+            ctx.project_bwd_adam(self.scene, self.globals_, self.m, self.v, self.adam_params(self.it),
+                                 self.grads["globals"])
+            adam_(self.globals_, self.grads["globals"], self.m["globals"], self.v["globals"], self.it,
+                  self.lrs["globals"], self.BETA1, self.BETA2, self.EPS)
+        else:
+            ctx.render_bwd(self.scene, self.globals_, self.dL, rgb, den, grads=self.grads)
+            for p, g, key, m, v in self._groups:
+                adam_(p, g, m, v, self.it, self.lrs[key], self.BETA1, self.BETA2, self.EPS)
         return value

@@ -157,3 +157,34 @@ def test_sorted_entry_points_reject_bad_arguments_before_launch():
     assert lib.wsr_sort_tiles(cc, 1, C.byref(p_dir), 8, dummy, 1 << 30, C.c_void_p(0x1004), 10, None) == INV
     assert lib.wsr_sort_tiles(cc, 1, C.byref(p_dir), 8, dummy, 16, dummy, 10, None) == _lib.WSR_ERR_WORKSPACE
     assert "sort" in _lib.status_string(_lib.WSR_ERR_TILE_LIST)
+
+
+def test_fused_adam_backward_rejects_bad_arguments_before_launch():
+    lib = _lib.load()
+    _, cams, st = ws.make_scene("c1", n=8)
+    cc = _lib.make_cameras(cams)
+    p = _lib.make_params(st)
+    dummy = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    INV, WSP = _lib.WSR_ERR_INVALID, _lib.WSR_ERR_WORKSPACE
+    f32 = _lib.WsrScene(8, 0, 0, 0, 0, dummy, dummy, dummy, dummy, dummy, dummy)
+    bf16 = _lib.WsrScene(8, 0, 2, 0, 0, dummy, dummy, dummy, dummy, dummy, dummy)
+    mom = _lib.WsrGrads(dummy, dummy, dummy, dummy, None, None, None)
+    no_sh = _lib.WsrGrads(dummy, dummy, dummy, None, None, None, None)
+
+    def adam(**kw):
+        a = dict(lr_means=1e-4, lr_log_scales=5e-3, lr_quats=1e-3, lr_sh0=2.5e-3, lr_shN=1.25e-4,
+                 lr_opacity_logit=5e-2, lr_lc_v=1e-3, beta1=0.9, beta2=0.999, eps=1e-15, step=1, reserved_=0)
+        a.update(kw)
+        return _lib.WsrAdamParams(**a)
+
+    def call(scene, m, v, hp, ws_bytes=1 << 30, grad_globals=dummy):
+        return lib.wsr_project_bwd_adam(C.byref(scene), cc, 1, C.byref(p), dummy, dummy, ws_bytes, dummy, 10,
+                                        C.byref(m), C.byref(v), C.byref(hp), grad_globals, None, None)
+
+    assert call(f32, mom, mom, adam(), ws_bytes=16) == WSP      # valid settings reach the workspace check
+    assert call(bf16, mom, mom, adam(), ws_bytes=16) == INV     # the update needs FP32 storage
+    assert call(f32, mom, no_sh, adam(), ws_bytes=16) == INV    # every per-Gaussian moment array
+    assert call(f32, mom, mom, adam(step=0), ws_bytes=16) == INV
+    assert call(f32, mom, mom, adam(beta1=1.0), ws_bytes=16) == INV
+    assert call(f32, mom, mom, adam(beta2=-0.1), ws_bytes=16) == INV
+    assert call(f32, mom, mom, adam(), ws_bytes=16, grad_globals=None) == INV

@@ -100,3 +100,41 @@ def test_training_fits_a_hidden_scene():
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.5 * losses[0]
     assert np.mean(losses[-10:]) < np.mean(losses[:10])
+
+
+@pytest.mark.parametrize("config,n", [("c1", 4096), ("c2", 20000)])
+def test_fused_adam_step_matches_backward_then_adam(config, n):
+    """wsr_project_bwd_adam against wsr_render_bwd followed by wsr_adam on
+    every group: the parameters, both moments and the global parameters
+    agree bit for bit after three steps.  c1 (SH degree 0, logit opacity,
+    EXP weight) carries an unused v_i array and c2 (degree 3, SH opacity, LC
+    weight) an unused logit array, which the update must leave as they are."""
+    sc, _, st = ws.make_scene(config, n=n)
+    cams = [ws.look_at_camera(p, w, h) for p, w, h in (((0, 0, -4), 96, 64), ((4, 1, 0), 80, 80))]
+    log(f"case: fused adam {config} n={n}")
+    g = globals_tensor(st)
+    ctx0 = WSRContext(n, cams, st)
+    targets = ctx0.forward(scene_to_device(sc), g)[0].clone()
+    rng = np.random.default_rng(5)
+    init = {k: v.copy() for k, v in sc.items()}
+    init["means"] = init["means"] + rng.normal(0, 0.02, init["means"].shape).astype(np.float32)
+    init["sh"] = init["sh"] + rng.normal(0, 0.1, init["sh"].shape).astype(np.float32)
+    runs = []
+    for fused in (True, False):
+        dev = scene_to_device(init)
+        step = TrainStep(WSRContext(n, cams, st), dev, g.clone(), targets, fused=fused)
+        for _ in range(3):
+            step.step()
+        torch.cuda.synchronize()
+        step.ctx.check()
+        runs.append((dev, step))
+    (d_f, s_f), (d_u, s_u) = runs
+    moved = (d_f["means"].cpu().numpy() != init["means"]).mean()
+    log(f"fraction of centre coordinates moved: {moved:.3f}")
+    assert moved > 0.5
+    for k in ("means", "log_scales", "quats", "sh", "opacity_logit", "lc_v"):
+        assert torch.equal(d_f[k], d_u[k]), k
+    assert torch.equal(s_f.globals_, s_u.globals_)
+    for k in s_f.m:
+        assert torch.equal(s_f.m[k], s_u.m[k]), ("m", k)
+        assert torch.equal(s_f.v[k], s_u.v[k]), ("v", k)
