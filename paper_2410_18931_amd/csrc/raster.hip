@@ -319,7 +319,12 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
     const bool hit = k < cnt && block_hits<CUT>(s_rec[k], bx, by, static_cast<float>(G::kSub - 1), a.tau);
     const uint64_t mask = __ballot(hit);
     const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
-    if (hit) list[pos] = static_cast<LT>(sizeof(LT) == 1 ? k : k * static_cast<int>(sizeof(StagedRec)));
+    if (hit) {
+      if constexpr (sizeof(LT) == 8)
+        list[pos] = LT{static_cast<uint32_t>(k * static_cast<int>(sizeof(StagedRec))), __float_as_uint(s_rec[k].r2.x)};
+      else
+        list[pos] = static_cast<LT>(sizeof(LT) == 1 ? k : k * static_cast<int>(sizeof(StagedRec)));
+    }
     if (SLOTS && k < BATCH) s_pos[c.wave * BATCH + k] = hit ? static_cast<uint16_t>(pos) : 0xffffu;
     m += __popcll(mask);
   }
@@ -373,11 +378,29 @@ __device__ __forceinline__ const StagedRec& rec_at(const StagedRec* base, uint32
   return *reinterpret_cast<const StagedRec*>(reinterpret_cast<const char*>(base) + off);
 }
 
+// The first two vectors of a staged record (centre, conic, amplitude and two
+// premultiplied colours): with 8-byte list entries, whose second word holds
+// the third colour, a forward step reads two 16-byte vectors per record.
+struct StagedHead {
+  float4 r0, r1;
+};
+__device__ __forceinline__ StagedHead head_at(const StagedRec* base, uint32_t off) {
+  const StagedRec& r = rec_at(base, off);
+  return StagedHead{r.r0, r.r1};
+}
+
+// List entry type of the forward: with the weighted sum of Eq. 7 (no
+// per-splat cutoff, no opacity), (record byte offset, third premultiplied
+// colour), so that one 16-byte read fetches two entries and a step reads
+// 2.5 LDS vectors instead of 3.25; otherwise the byte offset alone.
+template <bool CUT, bool OIT>
+using FwdList = typename std::conditional<!CUT && !OIT, uint2, uint32_t>::type;
+
 // The forward of one work item (tile_setup's c), S records staged per batch.
 template <int T, int S, bool COUNT, bool CUT, bool OIT>
 __device__ __forceinline__ void raster_fwd_item(const RasterArgs& a, const TileCtx<T>& c, const DevCamera* cam,
-                                                StagedRec* s_rec, uint32_t* s_list) {
-  using LT = uint32_t;
+                                                StagedRec* s_rec, FwdList<CUT, OIT>* s_list) {
+  using LT = FwdList<CUT, OIT>;
   float nr = 0.f, ng = 0.f, nb = 0.f, dd = 0.f;
   float cov = 1.f;  // OIT: prod (1 - alpha)
   int cntp = 0;
@@ -403,18 +426,49 @@ __device__ __forceinline__ void raster_fwd_item(const RasterArgs& a, const TileC
       if (COUNT) cntp += q <= cut ? 1 : 0;
     };
     int i = 0;
-    for (; i + 4 <= m; i += 4) {
-      const uint4 o4 = *reinterpret_cast<const uint4*>(list + i);
-      const StagedRec r0 = rec_at(s_rec, o4.x);
-      const StagedRec r1 = rec_at(s_rec, o4.y);
-      const StagedRec r2 = rec_at(s_rec, o4.z);
-      const StagedRec r3 = rec_at(s_rec, o4.w);
-      accumulate(r0);
-      accumulate(r1);
-      accumulate(r2);
-      accumulate(r3);
+    if constexpr (sizeof(LT) == 8) {
+      // the same arithmetic as accumulate, with the third colour from the entry
+      auto accumulate_head = [&](const StagedHead& r, float cb) {
+        const float dx = pcx - r.r0.x;
+        const float dy = pcy - r.r0.y;
+        const float q = quad_form(r.r0.z, r.r0.w * dy, (r.r1.x * dy) * dy, dx);
+        const float G = q <= tau ? falloff(q) : 0.f;
+        nr = fmaf(G, r.r1.z, nr);
+        ng = fmaf(G, r.r1.w, ng);
+        nb = fmaf(G, cb, nb);
+        dd = fmaf(G, r.r1.y, dd);
+        if (COUNT) cntp += q <= tau ? 1 : 0;
+      };
+      for (; i + 4 <= m; i += 4) {
+        const uint4 e01 = *reinterpret_cast<const uint4*>(list + i);
+        const uint4 e23 = *reinterpret_cast<const uint4*>(list + i + 2);
+        const StagedHead r0 = head_at(s_rec, e01.x);
+        const StagedHead r1 = head_at(s_rec, e01.z);
+        const StagedHead r2 = head_at(s_rec, e23.x);
+        const StagedHead r3 = head_at(s_rec, e23.z);
+        accumulate_head(r0, __uint_as_float(e01.y));
+        accumulate_head(r1, __uint_as_float(e01.w));
+        accumulate_head(r2, __uint_as_float(e23.y));
+        accumulate_head(r3, __uint_as_float(e23.w));
+      }
+      for (; i < m; ++i) {
+        const uint2 e = list[i];
+        accumulate_head(head_at(s_rec, e.x), __uint_as_float(e.y));
+      }
+    } else {
+      for (; i + 4 <= m; i += 4) {
+        const uint4 o4 = *reinterpret_cast<const uint4*>(list + i);
+        const StagedRec r0 = rec_at(s_rec, o4.x);
+        const StagedRec r1 = rec_at(s_rec, o4.y);
+        const StagedRec r2 = rec_at(s_rec, o4.z);
+        const StagedRec r3 = rec_at(s_rec, o4.w);
+        accumulate(r0);
+        accumulate(r1);
+        accumulate(r2);
+        accumulate(r3);
+      }
+      for (; i < m; ++i) accumulate(rec_at(s_rec, list[i]));
     }
-    for (; i < m; ++i) accumulate(rec_at(s_rec, list[i]));
   }
   if (c.px >= cam->width || c.py >= cam->height) return;
   const int64_t pix = cam->pix_base + static_cast<int64_t>(c.py) * cam->width + c.px;
@@ -451,7 +505,7 @@ __device__ __forceinline__ void raster_fwd_item(const RasterArgs& a, const TileC
 template <int T, int S, bool COUNT, bool CUT, bool OIT, bool PERSIST>
 __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(RasterArgs a) {
   using G = TileGeom<T>;
-  using LT = uint32_t;
+  using LT = FwdList<CUT, OIT>;
   __shared__ StagedRec s_rec[S];
   __shared__ __align__(16) LT s_list[G::kWaves * S];
   __shared__ uint32_t s_item;
