@@ -19,6 +19,7 @@
 //   loss_pass2: the three derivative maps filtered again -> dL/dx.
 // The tile shares are summed in FP64 in a fixed order (loss_finalize).
 #include <cmath>
+#include <type_traits>
 #include <mutex>
 
 #include "adam.h"
@@ -78,36 +79,48 @@ __device__ __forceinline__ TileWhere loss_tile(const LossViews& lv, int t) {
   return {v, (local % lv.tiles_x[v]) * kLT, (local / lv.tiles_x[v]) * kLT};
 }
 
-// Stage a (26 x 26) region of channel `ch` of the interleaved [pix][3] image
-// (or of a planar map when stride == 1) with zeros outside the view.
-__device__ __forceinline__ void stage(float (*dst)[kLE + 1], const float* src, int stride, int ch,
+// Stage the (26 x 26) region of the tile in M sources -- channel `ch` of the
+// interleaved [pix][3] images (stride 3) or planar maps (stride 1) -- with
+// zeros outside the view, interleaved in LDS (source q in component q of a
+// float2 or float4), so that a filter tap reads all of them at once.  Every
+// load of the thread is issued before the first LDS store, so a workgroup
+// pays one memory round trip for all M.
+constexpr int kStageIters = (kLE * kLE + 255) / 256;
+
+template <int M>
+using StageVec = typename std::conditional<M == 2, float2, float4>::type;
+
+template <int M>
+__device__ __forceinline__ void stage(StageVec<M> (*dst)[kLE + 1], const float* const src[M], int stride, int ch,
                                       const LossViews& lv, const TileWhere& w) {
-  for (int k = threadIdx.x; k < kLE * kLE; k += 256) {
+  static_assert(M == 2 || M == 3, "two or three interleaved sources");
+  const int width = lv.width[w.v], height = lv.height[w.v];
+  const int64_t base = lv.pix_base[w.v];
+  float val[M][kStageIters];
+#pragma unroll
+  for (int it = 0; it < kStageIters; ++it) {
+    const int k = threadIdx.x + 256 * it;
     const int r = k / kLE, cc = k % kLE;
     const int py = w.ty0 - kHalo + r, px = w.tx0 - kHalo + cc;
-    float val = 0.f;
-    if (px >= 0 && py >= 0 && px < lv.width[w.v] && py < lv.height[w.v]) {
-      const int64_t pix = lv.pix_base[w.v] + static_cast<int64_t>(py) * lv.width[w.v] + px;
-      val = src[pix * stride + ch];
+    const bool in = k < kLE * kLE && px >= 0 && py >= 0 && px < width && py < height;
+    // outside the view the load reads the view's first pixel and is discarded
+    const int64_t pix = base + (in ? static_cast<int64_t>(py) * width + px : 0);
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const float x = src[q][pix * stride + ch];
+      val[q][it] = in ? x : 0.f;
     }
-    dst[r][cc] = val;
   }
-}
-
-// Row pass of the separable filter over the staged region: out[r][c] for the
-// 26 rows and the 16 output columns.
-__device__ __forceinline__ float row_filter(const float* g, const float (*src)[kLE + 1], int r, int c) {
-  float s = 0.f;
 #pragma unroll
-  for (int b = 0; b < 11; ++b) s = fmaf(g[b], src[r][c + b], s);
-  return s;
-}
-
-__device__ __forceinline__ float col_filter(const float* g, const float (*src)[kLT + 1], int i, int j) {
-  float s = 0.f;
-#pragma unroll
-  for (int a = 0; a < 11; ++a) s = fmaf(g[a], src[i + a][j], s);
-  return s;
+  for (int it = 0; it < kStageIters; ++it) {
+    const int k = threadIdx.x + 256 * it;
+    if (k < kLE * kLE) {
+      if constexpr (M == 2)
+        dst[k / kLE][k % kLE] = make_float2(val[0][it], val[1][it]);
+      else
+        dst[k / kLE][k % kLE] = make_float4(val[0][it], val[1][it], val[2][it], 0.f);
+    }
+  }
 }
 
 __device__ __forceinline__ double block_sum_256(double x, double* sh) {
@@ -121,41 +134,53 @@ __device__ __forceinline__ double block_sum_256(double x, double* sh) {
 }
 
 __global__ __launch_bounds__(256) void loss_pass1(LossArgs a, LossViews lv) {
-  __shared__ float s_x[kLE][kLE + 1], s_y[kLE][kLE + 1];
-  __shared__ float s_h[5][kLE][kLT + 1];
+  __shared__ float2 s_xy[kLE][kLE + 1];   // (x, y)
+  __shared__ float4 s_h4[kLE][kLT + 1];   // row-filtered x, y, x^2, y^2
+  __shared__ float s_h1[kLE][kLT + 1];    // row-filtered x y
   __shared__ double s_red[4];
   const int t = blockIdx.x, ch = blockIdx.y;
   const TileWhere w = loss_tile(lv, t);
-  stage(s_x, a.img, 3, ch, lv, w);
-  stage(s_y, a.target, 3, ch, lv, w);
+  {
+    const float* const src[2] = {a.img, a.target};
+    stage<2>(s_xy, src, 3, ch, lv, w);
+  }
   __syncthreads();
+  // row pass of the separable filter: the 26 rows, the 16 output columns
   for (int k = threadIdx.x; k < kLE * kLT; k += 256) {
     const int r = k / kLT, c = k % kLT;
     float hx = 0.f, hy = 0.f, hxx = 0.f, hyy = 0.f, hxy = 0.f;
 #pragma unroll
     for (int b = 0; b < 11; ++b) {
-      const float gb = lv.gauss[b], x = s_x[r][c + b], y = s_y[r][c + b];
+      const float gb = lv.gauss[b];
+      const float2 xy = s_xy[r][c + b];
+      const float x = xy.x, y = xy.y;
       hx = fmaf(gb, x, hx);
       hy = fmaf(gb, y, hy);
       hxx = fmaf(gb, x * x, hxx);
       hyy = fmaf(gb, y * y, hyy);
       hxy = fmaf(gb, x * y, hxy);
     }
-    s_h[0][r][c] = hx;
-    s_h[1][r][c] = hy;
-    s_h[2][r][c] = hxx;
-    s_h[3][r][c] = hyy;
-    s_h[4][r][c] = hxy;
+    s_h4[r][c] = make_float4(hx, hy, hxx, hyy);
+    s_h1[r][c] = hxy;
   }
   __syncthreads();
   const int i = threadIdx.x / kLT, j = threadIdx.x % kLT;
   const int px = w.tx0 + j, py = w.ty0 + i;
   double share = 0.0;
   if (px < lv.width[w.v] && py < lv.height[w.v]) {
-    const float* g = lv.gauss;
-    const float u = col_filter(g, s_h[0], i, j), v = col_filter(g, s_h[1], i, j);
-    const float sxx = col_filter(g, s_h[2], i, j), syy = col_filter(g, s_h[3], i, j);
-    const float sxy = col_filter(g, s_h[4], i, j);
+    // column pass
+    float u = 0.f, v = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f;
+#pragma unroll
+    for (int q = 0; q < 11; ++q) {
+      const float gq = lv.gauss[q];
+      const float4 h = s_h4[i + q][j];
+      const float h1 = s_h1[i + q][j];
+      u = fmaf(gq, h.x, u);
+      v = fmaf(gq, h.y, v);
+      sxx = fmaf(gq, h.z, sxx);
+      syy = fmaf(gq, h.w, syy);
+      sxy = fmaf(gq, h1, sxy);
+    }
     const float a1 = 2.f * u * v + kC1;
     const float a2 = 2.f * (sxy - u * v) + kC2;
     const float b1 = u * u + v * v + kC1;
@@ -170,7 +195,7 @@ __global__ __launch_bounds__(256) void loss_pass1(LossArgs a, LossViews lv) {
     a.dmaps[(0 * 3 + ch) * P + pix] = d_u;
     a.dmaps[(1 * 3 + ch) * P + pix] = d_sxx;
     a.dmaps[(2 * 3 + ch) * P + pix] = d_sxy;
-    const float x = s_x[i + kHalo][j + kHalo], y = s_y[i + kHalo][j + kHalo];
+    const float x = s_xy[i + kHalo][j + kHalo].x, y = s_xy[i + kHalo][j + kHalo].y;
     // this entry's part of L_v * V * P_v: (1 - lambda)|x - y| + lambda (1 - S)
     share = (1.0 - a.lambda) * fabs(static_cast<double>(x) - y) + a.lambda * (1.0 - static_cast<double>(s));
   }
@@ -179,22 +204,39 @@ __global__ __launch_bounds__(256) void loss_pass1(LossArgs a, LossViews lv) {
 }
 
 __global__ __launch_bounds__(256) void loss_pass2(LossArgs a, LossViews lv) {
-  __shared__ float s_m[kLE][kLE + 1];
-  __shared__ float s_h[kLE][kLT + 1];
+  __shared__ float4 s_m[kLE][kLE + 1];   // the three derivative maps (fourth component unused)
+  __shared__ float4 s_h[kLE][kLT + 1];   // the same, row-filtered
   const int t = blockIdx.x, ch = blockIdx.y;
   const TileWhere w = loss_tile(lv, t);
   const int i = threadIdx.x / kLT, j = threadIdx.x % kLT;
   const int64_t P = a.total_pixels;
-  float f[3];
+  {
+    const float* const src[3] = {a.dmaps + (0 * 3 + ch) * P, a.dmaps + (1 * 3 + ch) * P, a.dmaps + (2 * 3 + ch) * P};
+    stage<3>(s_m, src, 1, 0, lv, w);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kLE * kLT; k += 256) {
+    const int r = k / kLT, c = k % kLT;
+    float h0 = 0.f, h1 = 0.f, h2 = 0.f;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    __syncthreads();
-    stage(s_m, a.dmaps + (q * 3 + ch) * P, 1, 0, lv, w);
-    __syncthreads();
-    for (int k = threadIdx.x; k < kLE * kLT; k += 256)
-      s_h[k / kLT][k % kLT] = row_filter(lv.gauss, s_m, k / kLT, k % kLT);
-    __syncthreads();
-    f[q] = col_filter(lv.gauss, s_h, i, j);
+    for (int b = 0; b < 11; ++b) {
+      const float gb = lv.gauss[b];
+      const float4 m = s_m[r][c + b];
+      h0 = fmaf(gb, m.x, h0);
+      h1 = fmaf(gb, m.y, h1);
+      h2 = fmaf(gb, m.z, h2);
+    }
+    s_h[r][c] = make_float4(h0, h1, h2, 0.f);
+  }
+  __syncthreads();
+  float f[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < 11; ++q) {
+    const float gq = lv.gauss[q];
+    const float4 h = s_h[i + q][j];
+    f[0] = fmaf(gq, h.x, f[0]);
+    f[1] = fmaf(gq, h.y, f[1]);
+    f[2] = fmaf(gq, h.z, f[2]);
   }
   const int px = w.tx0 + j, py = w.ty0 + i;
   if (px >= lv.width[w.v] || py >= lv.height[w.v]) return;
