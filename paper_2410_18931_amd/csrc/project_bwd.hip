@@ -101,12 +101,24 @@ __global__ __launch_bounds__(kBwdBlock) void project_bwd_kernel(BwdArgs a) {
     for (int k = 0; k < K; ++k) dsh[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     float dlogit = 0.f, dv = 0.f;
 
+    // View v's 2D gradient (and OIT dL/du) comes from gn, which the previous
+    // iteration requested: with one wave per SIMD, loading it at the top of
+    // its own iteration would expose a memory round trip per view.
+    float gn[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) gn[j] = gv0[j];
+    float dn = a.du2d ? a.du2d[i] : 0.f;
     for (int v = 0; v < a.nv; ++v) {
-      const float* g2 = a.grad2d + (static_cast<int64_t>(v) * n + i) * 9;
       float gv[9];
 #pragma unroll
-      for (int j = 0; j < 9; ++j) gv[j] = v == 0 ? gv0[j] : g2[j];
-      const float du_cov = a.du2d ? a.du2d[static_cast<int64_t>(v) * n + i] : 0.f;
+      for (int j = 0; j < 9; ++j) gv[j] = gn[j];
+      const float du_cov = dn;
+      if (v + 1 < a.nv) {
+        const float* g2 = a.grad2d + (static_cast<int64_t>(v + 1) * n + i) * 9;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) gn[j] = g2[j];
+        if (a.du2d) dn = a.du2d[static_cast<int64_t>(v + 1) * n + i];
+      }
       bool nz = du_cov != 0.f;
 #pragma unroll
       for (int j = 0; j < 9; ++j) nz |= gv[j] != 0.f;
