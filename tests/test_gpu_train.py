@@ -102,16 +102,18 @@ def test_training_fits_a_hidden_scene():
     assert np.mean(losses[-10:]) < np.mean(losses[:10])
 
 
-@pytest.mark.parametrize("config,n", [("c1", 4096), ("c2", 20000)])
-def test_fused_adam_step_matches_backward_then_adam(config, n):
+@pytest.mark.parametrize("config,n,oit", [("c1", 4096, False), ("c2", 20000, False), ("c2", 20000, True)])
+def test_fused_adam_step_matches_backward_then_adam(config, n, oit):
     """wsr_project_bwd_adam against wsr_render_bwd followed by wsr_adam on
     every group: the parameters, both moments and the global parameters
     agree bit for bit after three steps.  c1 (SH degree 0, logit opacity,
     EXP weight) carries an unused v_i array and c2 (degree 3, SH opacity, LC
-    weight) an unused logit array, which the update must leave as they are."""
+    weight) an unused logit array, which the update must leave as they are;
+    with OIT (Eq. 2) the pair sums also carry dL/du of the coverage term."""
     sc, _, st = ws.make_scene(config, n=n)
+    st = st.copy(oit=oit)
     cams = [ws.look_at_camera(p, w, h) for p, w, h in (((0, 0, -4), 96, 64), ((4, 1, 0), 80, 80))]
-    log(f"case: fused adam {config} n={n}")
+    log(f"case: fused adam {config} n={n} oit={oit}")
     g = globals_tensor(st)
     ctx0 = WSRContext(n, cams, st)
     targets = ctx0.forward(scene_to_device(sc), g)[0].clone()
