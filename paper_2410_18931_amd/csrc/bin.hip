@@ -368,6 +368,7 @@ __global__ __launch_bounds__(kTileScanThreads) void tile_scan_single(uint32_t* t
     flags->wrapped = carry > 0xffffffffull ? 1u : 0u;
     flags->overflow = (carry > static_cast<uint64_t>(capacity) || carry > 0xffffffffull) ? 1u : 0u;
     flags->sort_overflow = 0u;
+    flags->cull_masks = 0u;  // new lists: no culling masks yet
     uint32_t r = 0;
     for (int k = 0; k < kOrderBuckets; ++k) {
       const uint32_t c = bucket[k];

@@ -188,6 +188,11 @@ struct RasterArgs {
   // persistent launches: the counter the workgroups take work items from
   // (zeroed before the launch); null for one workgroup per work item
   uint32_t* queue;
+  // culling masks (see cull_mask_word), or null where the pair buffer has no
+  // room for them or the region is in use (Eq. 2); flags->cull_masks says
+  // whether they hold the current lists' masks
+  uint64_t* masks;
+  DevFlags* flags;
 };
 
 // A persistent workgroup's next work item: the next unclaimed one, taken
@@ -214,12 +219,26 @@ struct TileCtx {
   int64_t tile;
   int64_t n;
   uint32_t start, end;
+  uint32_t list0;                 // first list position of the tile (capped at the capacity)
   uint32_t k, nk;                 // item index within the tile, items of the tile
   int wave, lane;
   int bx0, by0;                   // first pixel of this wave's block
   int px, py;                     // this lane's pixel
   int fx0, fy0;                   // frame origin of the staged centres: the tile's centre
 };
+
+// The culling masks: wave w's 64-bit ballot for the 64-entry group g of tile
+// t's list (entries list0 + 64 g ...) is word (list0 / 64 + t + g) W + w, W the
+// waves of a tile.  A tile of l entries has ceil(l / 64) groups and the next
+// tile's first group is at least floor((list0 + l) / 64) + t + 1, so the
+// tiles' words never overlap; all of them lie below
+// (ceil(capacity / 64) + tiles + 2) W.
+template <int T>
+__device__ __forceinline__ int64_t cull_mask_word(const TileCtx<T>& c, uint32_t pos) {
+  constexpr int W = TileGeom<T>::kWaves;
+  const int64_t g = static_cast<int64_t>(c.list0 >> 6) + c.tile + ((pos - c.list0) >> 6);
+  return g * W + c.wave;
+}
 
 template <int T>
 __device__ __forceinline__ void tile_setup(const RasterArgs& a, uint32_t item, TileCtx<T>& c, const DevCamera*& cam) {
@@ -255,6 +274,7 @@ __device__ __forceinline__ void tile_setup(const RasterArgs& a, uint32_t item, T
   s = s < cap ? s : cap;
   e = e < cap ? e : cap;
   if (e < s) e = s;
+  c.list0 = static_cast<uint32_t>(s);
   const uint64_t ss = s + static_cast<uint64_t>(c.k) * kItemSplats;
   const uint64_t ee = ss + kItemSplats;
   c.start = static_cast<uint32_t>(ss < e ? ss : e);
@@ -282,7 +302,8 @@ __device__ __forceinline__ void tile_setup(const RasterArgs& a, uint32_t item, T
 template <int T, int BATCH, bool SLOTS, bool CUT, bool OIT, bool PREMUL, typename LT>
 __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx<T>& c, uint32_t b,
                                               StagedRec* s_rec, uint32_t* s_slot, LT* s_list,
-                                              uint16_t* s_pos) {
+                                              uint16_t* s_pos, uint64_t* mask_out = nullptr,
+                                              const uint64_t* mask_in = nullptr) {
   using G = TileGeom<T>;
   const float tox = static_cast<float>(c.fx0), toy = static_cast<float>(c.fy0);
   __syncthreads();  // previous batch fully consumed
@@ -316,8 +337,18 @@ __device__ __forceinline__ int stage_and_cull(const RasterArgs& a, const TileCtx
   const float bx = static_cast<float>(c.bx0 - c.fx0) + 0.5f, by = static_cast<float>(c.by0 - c.fy0) + 0.5f;
   for (int k0 = 0; k0 < cnt; k0 += kWave) {
     const int k = k0 + c.lane;
-    const bool hit = k < cnt && block_hits<CUT>(s_rec[k], bx, by, static_cast<float>(G::kSub - 1), a.tau);
-    const uint64_t mask = __ballot(hit);
+    bool hit;
+    uint64_t mask;
+    if (mask_in) {
+      // the forward's ballot for these entries: the same test of the same
+      // staged values (the staged colour aside), so the same lists
+      mask = mask_in[cull_mask_word(c, b + k0)];
+      hit = ((mask >> c.lane) & 1ull) != 0;
+    } else {
+      hit = k < cnt && block_hits<CUT>(s_rec[k], bx, by, static_cast<float>(G::kSub - 1), a.tau);
+      mask = __ballot(hit);
+      if (mask_out && c.lane == 0) mask_out[cull_mask_word(c, b + k0)] = mask;
+    }
     const int pos = m + __popcll(mask & ((1ull << c.lane) - 1ull));
     if (hit) {
       if constexpr (sizeof(LT) == 8)
@@ -409,7 +440,8 @@ __device__ __forceinline__ void raster_fwd_item(const RasterArgs& a, const TileC
   const float pcy = static_cast<float>(c.py - c.fy0) + 0.5f;
   const float tau = a.tau;
   for (uint32_t b = c.start; b < c.end; b += S) {
-    const int m = stage_and_cull<T, S, false, CUT, OIT, true, LT>(a, c, b, s_rec, nullptr, s_list, nullptr);
+    const int m = stage_and_cull<T, S, false, CUT, OIT, true, LT>(a, c, b, s_rec, nullptr, s_list, nullptr,
+                                                                  a.masks);
     const LT* list = s_list + c.wave * S;
     // four splats per step: one read fetches their list entries and all four
     // records are requested before any arithmetic, so LDS latency is paid
@@ -509,6 +541,9 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads) void raster_fwd_kernel(Raste
   __shared__ StagedRec s_rec[S];
   __shared__ __align__(16) LT s_list[G::kWaves * S];
   __shared__ uint32_t s_item;
+  // every work item stores its waves' culling masks (when there is room):
+  // valid for the backward once this launch has finished
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.flags->cull_masks = a.masks ? (kCullMasks | (CUT ? 2u : 0u)) : 0u;
   const uint32_t n_items = a.items[a.total_tiles];
   uint32_t item = PERSIST ? claim_item(a, &s_item) : blockIdx.x;
   while (item < n_items) {
@@ -986,6 +1021,11 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
   __shared__ float s_pk[OIT ? G::kThreads : 1];   // OIT: per-pixel coverage factors
   __shared__ float s_bg[G::kWaves][4];
   __shared__ uint32_t s_item;
+  // the forward's culling masks, if it stored them for these lists with the
+  // same early-out setting; Eq. 2's backward writes their region instead
+  const uint64_t* masks_in =
+      (!OIT && a.masks && a.flags->cull_masks == (kCullMasks | (CUT ? 2u : 0u))) ? a.masks : nullptr;
+  if (OIT && blockIdx.x == 0 && threadIdx.x == 0) a.flags->cull_masks = 0u;
   const uint32_t n_items = a.items[a.total_tiles];
   uint32_t item = PERSIST ? claim_item(a, &s_item) : blockIdx.x;
   while (item < n_items) {
@@ -1022,7 +1062,8 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
     const float tau = a.tau;
     const int own = threadIdx.x;  // staged record owned by this thread (if < kB)
     for (uint32_t b = c.start; b < c.end; b += kB) {
-      const int m = stage_and_cull<T, kB, true, CUT, OIT, false, uint8_t>(a, c, b, s_rec, s_slot, s_list, s_pos);
+      const int m = stage_and_cull<T, kB, true, CUT, OIT, false, uint8_t>(a, c, b, s_rec, s_slot, s_list, s_pos,
+                                                                          nullptr, masks_in);
       const int cnt = static_cast<int>(min(static_cast<uint32_t>(kB), c.end - b));
       if (c.lane == 0) s_m[c.wave] = m;
       __syncthreads();
@@ -1112,6 +1153,8 @@ __global__ __launch_bounds__(1024) void sort_tiles_kernel(const DevCamera* cams,
   constexpr int R = CAP / 1024;  // list positions per thread
   __shared__ uint64_t keys[CAP];
   const int tile = static_cast<int>(blockIdx.x);
+  // entries move: culling masks stored for the old positions no longer apply
+  if (CAP == kSortSmall && tile == 0 && threadIdx.x == 0) flags->cull_masks = 0u;
   const uint64_t cap = static_cast<uint64_t>(capacity);
   uint64_t s = tile_start[tile], e = tile_start[tile + 1];
   s = s < cap ? s : cap;
@@ -1265,6 +1308,18 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   a.oit = at<float4>(ws, L.off_oit);
   a.acclog = at<float>(ws, L.off_acclog);
   a.du = pv.du;
+  a.flags = at<DevFlags>(ws, L.off_flags);
+  // The culling masks live in the pair buffer's dL/du region (4 bytes per
+  // pair), which only Eq. 2's backward writes; a capacity too small for the
+  // per-tile rounding of the groups leaves them off.
+  {
+    const uintptr_t du = reinterpret_cast<uintptr_t>(pv.du);
+    const uintptr_t m0 = (du + 7) & ~static_cast<uintptr_t>(7);
+    const int64_t waves = static_cast<int64_t>(L.tile / 8) * (L.tile / 8);
+    const int64_t words = (((capacity + 63) >> 6) + L.total_tiles + 2) * waves;
+    const int64_t room = (4 * capacity - static_cast<int64_t>(m0 - du)) / 8;
+    a.masks = capacity > 0 && words <= room ? reinterpret_cast<uint64_t*>(m0) : nullptr;
+  }
   return a;
 }
 
@@ -1395,6 +1450,7 @@ hipError_t launch_raster_fwd(const Layout& L, void* ws, const void* pairs, int64
   }
   const int64_t grid = max_raster_items(L, capacity);
   const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
+  if (oit) a.masks = nullptr;  // Eq. 2's backward needs the region
   uint32_t* queue = (P->flags & WSR_FLAG_PERSISTENT) ? at<uint32_t>(ws, L.off_queue) : nullptr;
   const bool cut = P->alpha_cut > 0.f;
   switch (L.tile) {
@@ -1415,6 +1471,7 @@ hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t cap
   a.tilepart = at<float>(ws, L.off_tilepart);
   const int64_t grid = max_raster_items(L, capacity);
   const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
+  if (oit) a.masks = nullptr;
   uint32_t* queue = (P->flags & WSR_FLAG_PERSISTENT) ? at<uint32_t>(ws, L.off_queue) + 1 : nullptr;
   const bool cut = P->alpha_cut > 0.f;
   switch (L.tile) {
@@ -1448,6 +1505,7 @@ hipError_t launch_raster_sorted(const Layout& L, void* ws, const void* pairs, in
                                 float t_min, float* out_rgb, float* out_T, hipStream_t st) {
   if (L.total_tiles == 0) return hipSuccess;
   RasterArgs a = make_args(L, ws, pairs, capacity, P, globals);
+  a.masks = nullptr;  // the sorted lists are culled on their own
   a.out_rgb = out_rgb;
   const dim3 grid(static_cast<unsigned>(L.total_tiles));
   switch (L.tile) {

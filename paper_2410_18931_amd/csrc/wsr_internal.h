@@ -80,8 +80,14 @@ struct DevFlags {
   uint32_t wrapped;         // 32-bit pair count wrapped
   uint64_t total_pairs;     // pairs produced by the last binning
   uint32_t sort_overflow;   // a tile list longer than the per-tile sort takes
-  uint32_t pad_;
+  uint32_t cull_masks;      // culling masks in the pair buffer: 0 none, else kCullMasks | CUT bit
 };
+
+// Value of DevFlags::cull_masks once a forward raster (without OIT) has
+// stored every wave's culling masks for the current tile lists; bit 1 holds
+// whether that forward used the opacity early-out.  Binning, the per-tile sort
+// and Eq. 2's backward (which writes the region the masks occupy) set it to 0.
+constexpr uint32_t kCullMasks = 1u;
 
 // Longest tile list the per-tile depth sort of the sorted-blending baseline
 // holds in LDS (64-bit keys, 128 KB of the 160 KB a gfx950 workgroup may use).
