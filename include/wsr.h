@@ -189,8 +189,10 @@ int64_t wsr_pair_bytes(void);
  * every float sum of the later steps, are the same from run to run.
  * `pairs` is a DEVICE buffer of capacity * wsr_pair_bytes() bytes, aligned
  * to 256 bytes, that holds one entry per (tile, Gaussian) pair: the id lists
- * and the per-pair scratch of the backward.  It is owned by the caller and
- * must be passed unchanged to the later steps of the same frame.  If the
+ * and per-pair scratch (the forward's split-tile partial sums and culling
+ * masks, which the backward reuses, and the backward's partial gradients).
+ * It is owned by the caller and must be passed unchanged to the later steps
+ * of the same frame.  If the
  * number of pairs exceeds capacity the overflow flag is set (wsr_check,
  * wsr_pair_count give the needed capacity). */
 int32_t wsr_bin(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
@@ -201,7 +203,7 @@ int32_t wsr_bin(const wsr_camera* cams, int32_t n_views, const wsr_params* param
  * [H][W] (w_B + sum a_i); out_count (nullable, int32 [H][W]): the number of
  * in-support pairs per pixel. */
 int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
-                       const float* globals, void* ws, int64_t ws_bytes, const void* pairs,
+                       const float* globals, void* ws, int64_t ws_bytes, void* pairs,
                        int64_t capacity, float* out_rgb, float* out_den, int32_t* out_count,
                        void* stream);
 

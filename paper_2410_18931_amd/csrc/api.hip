@@ -173,7 +173,7 @@ int32_t wsr_bin(const wsr_camera* cams, int32_t n_views, const wsr_params* param
 }
 
 int32_t wsr_render_fwd(const wsr_camera* cams, int32_t n_views, const wsr_params* params, int64_t n,
-                       const float* globals, void* ws, int64_t ws_bytes, const void* pairs,
+                       const float* globals, void* ws, int64_t ws_bytes, void* pairs,
                        int64_t capacity, float* out_rgb, float* out_den, int32_t* out_count, void* stream) {
   if (!params_ok(params) || !globals || !ws || !out_rgb || !out_den || !pairs_ok(pairs, capacity))
     return WSR_ERR_INVALID;
