@@ -716,3 +716,35 @@ def test_reduced_precision_batched_errors(dt):
     for k in _grad_keys(st, 16):
         rel = np.abs(gg[k] - gs[k]).max() / max(np.abs(gs[k]).max(), 1e-30)
         log(f"[{dt}] grad {k} rel-to-max vs float32 source inputs: {rel:.3g}")
+
+
+def test_culling_masks_follow_the_pair_buffer_room():
+    """The raster backward takes the forward's per-wave culling masks from the
+    pair buffer where it has room for them (a 64-bit word per wave and 64 list
+    entries, plus one group per tile) and culls on its own otherwise.  A few
+    Gaussians on a 1080p frame (8,160 tiles) need a large buffer for the
+    masks: with the pair buffer sized to the pairs exactly there is no room,
+    and the lists, image and gradients must equal those of a buffer with room
+    bit for bit."""
+    sc, _, st = ws.make_scene("c1", n=64)
+    cams = [ws.look_at_camera((0.0, 0.0, -4.0), 1920, 1080)]
+    log("case: culling masks with and without room, c1 n=64 at 1920x1080")
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    big = WSRContext(64, cams, st)
+    rgb_b, den_b = big.forward(dev, g)
+    pairs = big.last_pairs
+    tiles = ((1920 + st.tile - 1) // st.tile) * ((1080 + st.tile - 1) // st.tile)
+    log(f"pairs {pairs}, tiles {tiles}, capacities {big.capacity} and {pairs}")
+    assert 0 < pairs < 9 * tiles  # then a buffer of `pairs` entries has no room for the masks
+    small = WSRContext(64, cams, st, capacity=pairs)
+    rgb_s, den_s = small.forward(dev, g)
+    dL = seeded_normal_like(rgb_b, 17)
+    gb = big.render_bwd(dev, g, dL, rgb_b, den_b)
+    gs = small.render_bwd(dev, g, dL, rgb_s, den_s)
+    torch.cuda.synchronize()
+    big.check()
+    small.check()
+    assert torch.equal(rgb_b, rgb_s) and torch.equal(den_b, den_s)
+    for k in ("means", "log_scales", "quats", "sh", "opacity_logit", "globals"):
+        assert torch.equal(gb[k], gs[k]), k

@@ -147,6 +147,34 @@ def test_tile_list_longer_than_the_sort_limit_is_reported():
     ctx.check()
 
 
+def test_backward_after_the_sort_culls_on_its_own():
+    """The forward stores each wave's culling masks by list position, and the
+    backward reuses them; the per-tile sort moves the entries, so a backward
+    that follows it (with the image of a forward on the binned lists) must
+    cull again -- the sort clears the masks' flag.  Against the backward on
+    the binned lists: only the float summation order may differ."""
+    sc, cams, st = ws.make_scene("c1", seed=7)
+    st = st.copy(weight_kind="dir")
+    log("case: c1, DIR weight, Eq. 7 backward after the sort with the binned lists' forward")
+    ctx = WSRContext(sc["means"].shape[1], cams, st)
+    dev = scene_to_device(sc)
+    g = globals_tensor(st)
+    ctx.project(dev, g)
+    ctx.bin(grow=True)
+    rgb0, den0 = ctx.render_fwd(g)
+    dL = torch.from_numpy(ws.upstream_grad(cams, seed=5)[0].reshape(-1, 3)).cuda()
+    g0 = {k: v.clone() for k, v in ctx.render_bwd(dev, g, dL, rgb0, den0).items()}
+    ctx.render_sorted(g)  # sorts the lists in place; no Eq. 7 forward after it
+    g1 = ctx.render_bwd(dev, g, dL, rgb0, den0)
+    torch.cuda.synchronize()
+    ctx.check()
+    for k in g0:
+        ref = g0[k].abs().max().item()
+        err = (g1[k] - g0[k]).abs().max().item()
+        log(f"  {k}: max |after sort - binned| = {err:.3g} of max {ref:.3g}")
+        assert err <= 1e-4 * max(ref, 1e-30), k
+
+
 def test_sorted_lists_still_serve_the_weighted_sum_backward():
     """The per-tile sort reorders the list entries in place; every entry must
     keep its pair's Gaussian-major slot, so that Eq. 7's forward and backward
