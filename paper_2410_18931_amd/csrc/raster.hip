@@ -189,8 +189,8 @@ struct RasterArgs {
   // (zeroed before the launch); null for one workgroup per work item
   uint32_t* queue;
   // culling masks (see cull_mask_word), or null where the pair buffer has no
-  // room for them or the region is in use (Eq. 2); flags->cull_masks says
-  // whether they hold the current lists' masks
+  // room for them; flags->cull_masks says whether they hold the current
+  // lists' masks
   uint64_t* masks;
   DevFlags* flags;
 };
@@ -1022,10 +1022,9 @@ __global__ __launch_bounds__(TileGeom<T>::kThreads, (bwd_min_blocks<T, OIT>())) 
   __shared__ float s_bg[G::kWaves][4];
   __shared__ uint32_t s_item;
   // the forward's culling masks, if it stored them for these lists with the
-  // same early-out setting; Eq. 2's backward writes their region instead
+  // same early-out setting
   const uint64_t* masks_in =
-      (!OIT && a.masks && a.flags->cull_masks == (kCullMasks | (CUT ? 2u : 0u))) ? a.masks : nullptr;
-  if (OIT && blockIdx.x == 0 && threadIdx.x == 0) a.flags->cull_masks = 0u;
+      (a.masks && a.flags->cull_masks == (kCullMasks | (CUT ? 2u : 0u))) ? a.masks : nullptr;
   const uint32_t n_items = a.items[a.total_tiles];
   uint32_t item = PERSIST ? claim_item(a, &s_item) : blockIdx.x;
   while (item < n_items) {
@@ -1309,16 +1308,12 @@ RasterArgs make_args(const Layout& L, void* ws, const void* pairs, int64_t capac
   a.acclog = at<float>(ws, L.off_acclog);
   a.du = pv.du;
   a.flags = at<DevFlags>(ws, L.off_flags);
-  // The culling masks live in the pair buffer's dL/du region (4 bytes per
-  // pair), which only Eq. 2's backward writes; a capacity too small for the
-  // per-tile rounding of the groups leaves them off.
+  // The culling masks have 4 bytes per pair of the pair buffer; a capacity
+  // too small for the per-tile rounding of the groups leaves them off.
   {
-    const uintptr_t du = reinterpret_cast<uintptr_t>(pv.du);
-    const uintptr_t m0 = (du + 7) & ~static_cast<uintptr_t>(7);
     const int64_t waves = static_cast<int64_t>(L.tile / 8) * (L.tile / 8);
     const int64_t words = (((capacity + 63) >> 6) + L.total_tiles + 2) * waves;
-    const int64_t room = (4 * capacity - static_cast<int64_t>(m0 - du)) / 8;
-    a.masks = capacity > 0 && words <= room ? reinterpret_cast<uint64_t*>(m0) : nullptr;
+    a.masks = capacity > 0 && 8 * words <= 4 * capacity ? pv.masks : nullptr;
   }
   return a;
 }
@@ -1450,7 +1445,6 @@ hipError_t launch_raster_fwd(const Layout& L, void* ws, const void* pairs, int64
   }
   const int64_t grid = max_raster_items(L, capacity);
   const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
-  if (oit) a.masks = nullptr;  // Eq. 2's backward needs the region
   uint32_t* queue = (P->flags & WSR_FLAG_PERSISTENT) ? at<uint32_t>(ws, L.off_queue) : nullptr;
   const bool cut = P->alpha_cut > 0.f;
   switch (L.tile) {
@@ -1471,7 +1465,6 @@ hipError_t launch_raster_bwd(const Layout& L, void* ws, void* pairs, int64_t cap
   a.tilepart = at<float>(ws, L.off_tilepart);
   const int64_t grid = max_raster_items(L, capacity);
   const bool oit = (P->flags & WSR_FLAG_OIT) != 0;
-  if (oit) a.masks = nullptr;
   uint32_t* queue = (P->flags & WSR_FLAG_PERSISTENT) ? at<uint32_t>(ws, L.off_queue) + 1 : nullptr;
   const bool cut = P->alpha_cut > 0.f;
   switch (L.tile) {

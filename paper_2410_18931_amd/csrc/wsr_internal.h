@@ -58,12 +58,15 @@ struct __align__(64) DevSplat {
 // mode the pair's partial dL/du through the coverage term (Gaussian-major,
 // like the 2D gradient), and the per-tile lists: at each list position the
 // Gaussian id and that pair's Gaussian-major slot, which the binning knows
-// when it places the id, so the backward reads it with the id.
-constexpr int64_t kPairBytes = 48;
+// when it places the id, so the backward reads it with the id; then 4 bytes
+// per pair for the forward's culling masks, which the backward reuses (see
+// cull_mask_word in raster.hip).
+constexpr int64_t kPairBytes = 52;
 struct PairView {
   float3* part;        // [capacity][3] float3: (mu_x, mu_y, A) (B, C, r) (g, b, a)
   float* du;           // [capacity]
   uint2* ent;          // [capacity] list entries: (Gaussian id, Gaussian-major slot)
+  uint64_t* masks;     // [capacity / 2] culling-mask words
 };
 __host__ __device__ inline PairView pair_view(const void* pairs, int64_t capacity) {
   char* b = static_cast<char*>(const_cast<void*>(pairs));
@@ -71,6 +74,7 @@ __host__ __device__ inline PairView pair_view(const void* pairs, int64_t capacit
   v.part = reinterpret_cast<float3*>(b);
   v.du = reinterpret_cast<float*>(b + 36 * capacity);
   v.ent = reinterpret_cast<uint2*>(b + 40 * capacity);  // 8-byte aligned for any capacity
+  v.masks = reinterpret_cast<uint64_t*>(b + 48 * capacity);
   return v;
 }
 
@@ -85,8 +89,8 @@ struct DevFlags {
 
 // Value of DevFlags::cull_masks once a forward raster (without OIT) has
 // stored every wave's culling masks for the current tile lists; bit 1 holds
-// whether that forward used the opacity early-out.  Binning, the per-tile sort
-// and Eq. 2's backward (which writes the region the masks occupy) set it to 0.
+// whether that forward used the opacity early-out.  Binning and the per-tile
+// sort set it to 0.
 constexpr uint32_t kCullMasks = 1u;
 
 // Longest tile list the per-tile depth sort of the sorted-blending baseline

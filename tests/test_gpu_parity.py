@@ -178,8 +178,9 @@ def test_every_pair_slot_is_written_by_the_backward(c1, oit):
     g = globals_tensor(st)
     ctx.project(dev, g)
     ctx.bin(grow=True)
-    # pair buffer layout: [capacity][36 B] partials, [capacity] dL/du, [capacity] (id, slot) list entries
-    assert ctx.pair_bytes == 48
+    # pair buffer layout: [capacity][36 B] partials, [capacity] dL/du, [capacity] (id, slot) list entries,
+    # [capacity][4 B] culling masks
+    assert ctx.pair_bytes == 52
     ctx.pairs[: 36 * ctx.capacity].fill_(0xFF)                     # every partial slot NaN
     ctx.pairs[36 * ctx.capacity: 40 * ctx.capacity].fill_(0xFF)    # and every dL/du slot
     ctx.bin(grow=False)
